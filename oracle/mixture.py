@@ -1,0 +1,138 @@
+"""Ensemble mixture of member statistics (oracle side, FP64, plain Python).
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
+
+Follows arXiv 2506.23712:
+  * ensemble hypothesis, eq. (ensemble_hypothesis): a statistic at scale gap Z
+    is the average over lambda, weighted by P(lambda; Z), of the statistic of a
+    member with injection e^lambda * eps_bar;
+  * PDFs superpose the same way, eq. (pdf_superposition);
+  * quadratic (log-normal) exponents zeta_p = p/3 - c (p^2 - 3p)/2,
+    eq. (quadratic_scaling_exponents), give a Gaussian P(lambda; Z) with mean
+    -9cZ/2 and variance 9cZ, eq. (gaussian_lambda_pdf);
+  * each member is given the probability mass of its lambda bin (the sentence
+    after eq. gaussian_lambda_pdf); any average is then a weighted sum;
+  * skewness / flatness predictions are ratios of mixed moments
+    (section "Modeling choices", eq. def_skewness_flatness and the skewness
+    prediction that follows it);
+  * Z follows R_lambda,ref ~ exp(2Z/3), eq. (Rlambda_Z_relation).
+
+Readings (the paper is silent): members are sorted by lambda and the bin of a
+member is bounded by the midpoints to its neighbours; the two end bins are open
+to -inf / +inf (mode 0), or closed at half a spacing and renormalised (mode 1);
+mode 2 is self-normalised importance weighting P(lambda_i; Z) / q(lambda_i) for
+members whose lambda were drawn from a normal density q.
+"""
+from __future__ import annotations
+
+import math
+from typing import Sequence
+
+
+def gaussian_params(c: float, Z: float) -> tuple[float, float]:
+    """(mean, standard deviation) of P(lambda; Z) for quadratic exponents."""
+    return -4.5 * c * Z, math.sqrt(9.0 * c * Z)
+
+
+def lambda_pdf(lam: float, c: float, Z: float) -> float:
+    """P(lambda; Z), eq. (gaussian_lambda_pdf)."""
+    mu, sig = gaussian_params(c, Z)
+    return math.exp(-(lam - mu) ** 2 / (2.0 * sig * sig)) / (sig * math.sqrt(2.0 * math.pi))
+
+
+def _mass(a: float, b: float, mu: float, sig: float) -> float:
+    """Normal probability of [a, b); tails use erfc so small masses keep their digits."""
+    r = 1.0 / (sig * math.sqrt(2.0))
+
+    def upper(x):   # P(X >= x)
+        return 0.5 * math.erfc((x - mu) * r) if x != math.inf else 0.0
+
+    def lower(x):   # P(X < x)
+        return 0.5 * math.erfc((mu - x) * r) if x != -math.inf else 0.0
+
+    if a >= mu:
+        return upper(a) - upper(b)
+    if b <= mu:
+        return lower(b) - lower(a)
+    return 1.0 - lower(a) - upper(b)
+
+
+def cell_edges(lams: Sequence[float], mode: int = 0) -> list[tuple[float, float]]:
+    """Bin [a_i, b_i) of each member (input order kept)."""
+    order = sorted(range(len(lams)), key=lambda i: lams[i])
+    s = [lams[i] for i in order]
+    n = len(s)
+    edges = [None] * n
+    for r in range(n):
+        a = 0.5 * (s[r - 1] + s[r]) if r > 0 else None
+        b = 0.5 * (s[r] + s[r + 1]) if r < n - 1 else None
+        if a is None:
+            a = -math.inf if (mode == 0 or n == 1) else s[r] - (b - s[r])
+        if b is None:
+            b = math.inf if (mode == 0 or n == 1) else s[r] + (s[r] - a)
+        edges[order[r]] = (a, b)
+    return edges
+
+
+def weights(lams: Sequence[float], c: float, Z: float, mode: int = 0,
+            q_sigma: float | None = None) -> list[float]:
+    """Mixture weight of each member (same order as ``lams``)."""
+    n = len(lams)
+    if n == 0:
+        return []
+    if mode == 2:
+        if Z <= 0:
+            raise ValueError("importance weights need Z > 0")
+        mu, sig = gaussian_params(c, Z)
+        raw = []
+        for l in lams:
+            p = math.exp(-(l - mu) ** 2 / (2 * sig * sig)) / sig
+            q = math.exp(-l * l / (2 * q_sigma * q_sigma)) / q_sigma
+            raw.append(p / q)
+        s = sum(raw)
+        return [r / s for r in raw]
+    edges = cell_edges(lams, mode)
+    if Z <= 0.0:                       # P(lambda; 0) = delta(lambda)
+        return [1.0 if (a <= 0.0 < b) else 0.0 for a, b in edges]
+    mu, sig = gaussian_params(c, Z)
+    w = [_mass(a, b, mu, sig) for a, b in edges]
+    if mode == 1:
+        s = sum(w)
+        w = [x / s for x in w]
+    return w
+
+
+def z_from_rlambda(r_target: float, r_anchor: float, z_anchor: float) -> float:
+    """Scale gap for a target R_lambda, from R_lambda ~ exp(2Z/3) through an anchor."""
+    return z_anchor + 1.5 * math.log(r_target / r_anchor)
+
+
+def mix(ws: Sequence[float], values: Sequence[Sequence[float]]) -> list[float]:
+    """sum_i w_i values_i, elementwise, members summed in the given order."""
+    out = [0.0] * len(values[0])
+    for w, v in zip(ws, values):
+        for j, x in enumerate(v):
+            out[j] += w * x
+    return out
+
+
+def normalised_pdf(counts: Sequence[int], total: int, bin_width: float) -> list[float]:
+    """count / (total samples x bin width); total includes under/overflow."""
+    return [c / (total * bin_width) for c in counts] if total > 0 else [0.0] * len(counts)
+
+
+def skewness(m2: float, m3: float) -> float:
+    return m3 / m2 ** 1.5
+
+
+def flatness(m2: float, m4: float) -> float:
+    return m4 / (m2 * m2)
+
+
+def hyperflatness(m2: float, m6: float) -> float:
+    return m6 / (m2 * m2 * m2)
+
+
+def cost_ratio(r_ref: float, r_ens: float, n: int) -> float:
+    """Cost of one full DNS over the cost of the ensemble, (R_ref/R_ens)^5 / n."""
+    return (r_ref / r_ens) ** 5 / n
