@@ -1,0 +1,615 @@
+// ens_api.cpp -- host side of libensdns: the C ABI declared in include/ens.h,
+// member registry, per-member-set step plans, HIP graph capture and replay.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "ens_internal.h"
+
+#define ENS_API extern "C" __attribute__((visibility("default")))
+
+namespace {
+
+using namespace ens;
+
+thread_local std::string g_err;
+
+ens_status fail(ens_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+bool pow2_supported(int n) { return n == 16 || n == 32 || n == 64 || n == 128 || n == 256; }
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// ------------------------------------------------------------------ twiddles
+// tw[j] = exp(-2 pi i j / n), j < n, evaluated in FP64 on the first octant and
+// mapped by symmetry so that quarter/eighth turns are exact.
+void twiddles_fp64(int n, std::vector<double> &out) {
+    out.resize(2 * (size_t)n);
+    const int q4 = n / 4, q8 = n / 8;
+    for (int j = 0; j < n; j++) {
+        int quad = j / q4, r = j % q4;
+        double c, s;
+        if (q8 > 0 && r > q8) {
+            const double a = 2.0 * M_PI * (double)(q4 - r) / (double)n;
+            c = std::sin(a); s = std::cos(a);
+        } else {
+            const double a = 2.0 * M_PI * (double)r / (double)n;
+            c = std::cos(a); s = std::sin(a);
+        }
+        double cc, ss;   // rotate by quad quarter turns
+        switch (quad) {
+        case 0: cc = c; ss = s; break;
+        case 1: cc = -s; ss = c; break;
+        case 2: cc = -c; ss = -s; break;
+        default: cc = s; ss = -c; break;
+        }
+        out[2 * j] = cc;
+        out[2 * j + 1] = -ss;
+    }
+}
+
+std::mutex g_tw_mu;
+std::map<std::tuple<int, int, int>, void *> g_tw;   // (device, n, prec) -> device table
+
+hipError_t get_twiddles(int device, int n, int prec, const void **out) {
+    std::lock_guard<std::mutex> lk(g_tw_mu);
+    auto key = std::make_tuple(device, n, prec);
+    auto it = g_tw.find(key);
+    if (it != g_tw.end()) { *out = it->second; return hipSuccess; }
+    std::vector<double> d;
+    twiddles_fp64(n, d);
+    void *p = nullptr;
+    hipError_t e;
+    if (prec == ENS_FP32) {
+        std::vector<float> f(d.size());
+        for (size_t i = 0; i < d.size(); i++) f[i] = (float)d[i];
+        e = hipMalloc(&p, f.size() * sizeof(float));
+        if (e != hipSuccess) return e;
+        e = hipMemcpy(p, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice);
+    } else {
+        e = hipMalloc(&p, d.size() * sizeof(double));
+        if (e != hipSuccess) return e;
+        e = hipMemcpy(p, d.data(), d.size() * sizeof(double), hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) return e;
+    g_tw[key] = p;
+    *out = p;
+    return hipSuccess;
+}
+
+// ------------------------------------------------------------ member layout
+struct Layout {
+    size_t off_st, off_uh, off_q, off_a, off_b, off_part, off_counts, off_mom, total;
+};
+
+Layout member_layout(const ens_member_desc &d, const HistGeom *hg) {
+    const Geom g = make_geom(d.n);
+    const size_t cs = d.precision == ENS_FP32 ? 8 : 16;
+    const long long n = d.n;
+    Layout L;
+    size_t o = 0;
+    L.off_st = o; o += align256(sizeof(DevState));
+    L.off_uh = o; o += align256(3 * (size_t)g.S * cs);
+    L.off_q = o; o += align256(3 * (size_t)g.S * cs);
+    const size_t a_elems = std::max((size_t)6 * n * g.nzl, (size_t)3 * n * n * (g.K + 1));
+    L.off_a = o; o += align256(a_elems * cs);
+    L.off_b = o; o += align256((size_t)9 * n * n * (g.K + 1) * cs);
+    const size_t nparts = std::max({(size_t)(2 * zfwd_blocks(d.n)), (size_t)init_blocks(d.n),
+                                    (size_t)(ENS_NMOM * xstats_blocks(d.n))});
+    L.off_part = o; o += align256(nparts * sizeof(double));
+    const size_t ncounts = hg ? (size_t)hg->n_counts : 0;
+    L.off_counts = o; o += align256(ncounts * sizeof(unsigned long long));
+    L.off_mom = o; o += align256(ENS_NMOM * sizeof(double));
+    L.total = o;
+    return L;
+}
+
+struct Member {
+    ens_member_desc d;
+    Geom g;
+    Layout lay;
+    void *ws = nullptr;
+    MemberDev md;            // host copy
+    MemberDev *dev = nullptr;   // device copy (library-owned, one element)
+    hipStream_t last = nullptr;
+};
+
+struct Group {
+    int n = 0, prec = 0;
+    std::vector<int> ids;
+    MemberDev *dev = nullptr;   // device array of the group's MemberDev
+    const void *tw = nullptr;
+};
+
+struct Plan {
+    std::vector<Group> groups;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+};
+
+}  // namespace
+
+struct ens_ctx {
+    int device = 0;
+    bool poisoned = false;
+    bool graphs = true;
+    bool has_hist = false;
+    ens_hist_desc hist{};
+    HistGeom hg{};
+    hipStream_t cap = nullptr;   // private stream used for graph capture
+    std::vector<std::unique_ptr<Member>> members;
+    std::map<std::vector<int>, std::unique_ptr<Plan>> plans;
+    std::vector<void *> dev_allocs;   // library-owned small device tables
+    void *mix_scratch = nullptr;      // member table of ens_mix (library-owned)
+    size_t mix_scratch_bytes = 0;
+};
+
+namespace {
+
+#define HIPCK(ctx, expr)                                                                   \
+    do {                                                                                   \
+        hipError_t _e = (expr);                                                            \
+        if (_e != hipSuccess) {                                                            \
+            if (ctx) (ctx)->poisoned = true;                                               \
+            return fail(ENS_E_HIP, std::string(#expr) + ": " + hipGetErrorString(_e));      \
+        }                                                                                  \
+    } while (0)
+
+ens_status check_ctx(const ens_ctx *ctx) {
+    if (!ctx) return fail(ENS_E_INVALID, "null context");
+    if (ctx->poisoned) return fail(ENS_E_STATE, "context poisoned by an earlier HIP failure");
+    return ENS_OK;
+}
+
+ens_status validate_desc(const ens_member_desc *d) {
+    if (!d) return fail(ENS_E_INVALID, "null member descriptor");
+    if (!pow2_supported(d->n)) return fail(ENS_E_UNSUPPORTED, "n must be one of 16, 32, 64, 128, 256");
+    if (d->precision != ENS_FP64 && d->precision != ENS_FP32) return fail(ENS_E_INVALID, "precision must be 0 or 1");
+    if (!(d->box > 0) || !std::isfinite(d->box)) return fail(ENS_E_INVALID, "box must be positive");
+    if (!(d->nu >= 0) || !std::isfinite(d->nu)) return fail(ENS_E_INVALID, "nu must be >= 0");
+    if (!(d->eps_ref >= 0) || !std::isfinite(d->eps_ref)) return fail(ENS_E_INVALID, "eps_ref must be >= 0");
+    if (!std::isfinite(d->lambda)) return fail(ENS_E_INVALID, "lambda must be finite");
+    if (!(d->kf_lo >= 0) || !(d->kf_hi >= d->kf_lo) || !std::isfinite(d->kf_hi))
+        return fail(ENS_E_INVALID, "need 0 <= kf_lo <= kf_hi");
+    if (!(d->dt > 0) && !(d->cfl > 0)) return fail(ENS_E_INVALID, "need dt > 0 or cfl > 0");
+    if (!std::isfinite(d->dt) || !std::isfinite(d->cfl)) return fail(ENS_E_INVALID, "dt/cfl must be finite");
+    if (!(d->k_peak > 0) || !(d->e0 >= 0) || !std::isfinite(d->e0)) return fail(ENS_E_INVALID, "need k_peak > 0, e0 >= 0");
+    if (d->visc_mode != 0 && d->visc_mode != 1) return fail(ENS_E_INVALID, "visc_mode must be 0 or 1");
+    if (d->reserved != 0) return fail(ENS_E_INVALID, "reserved must be 0");
+    return ENS_OK;
+}
+
+ens_status validate_hist(const ens_hist_desc *h) {
+    if (h->qr_bins <= 0 || h->log_bins <= 0 || h->a_bins <= 0) return fail(ENS_E_INVALID, "histogram bin counts must be positive");
+    if (h->qr_bins > 4096 || h->log_bins > (1 << 20) || h->a_bins > (1 << 20)) return fail(ENS_E_INVALID, "too many bins");
+    if (!(h->q_hi > h->q_lo) || !(h->r_hi > h->r_lo) || !(h->log10_hi > h->log10_lo) || !(h->a_hi > h->a_lo))
+        return fail(ENS_E_INVALID, "histogram ranges need hi > lo");
+    if (!(h->eps_ref > 0) || !(h->nu_ref > 0)) return fail(ENS_E_INVALID, "eps_ref and nu_ref must be positive");
+    return ENS_OK;
+}
+
+ens_status member_of(ens_ctx *ctx, int32_t m, Member **out) {
+    if (m < 0 || m >= (int32_t)ctx->members.size() || !ctx->members[m]) return fail(ENS_E_INVALID, "bad member id");
+    *out = ctx->members[m].get();
+    return ENS_OK;
+}
+
+ens_status make_plan(ens_ctx *ctx, const std::vector<int> &ids, Plan **out) {
+    auto it = ctx->plans.find(ids);
+    if (it != ctx->plans.end()) { *out = it->second.get(); return ENS_OK; }
+    auto plan = std::make_unique<Plan>();
+    std::map<std::pair<int, int>, std::vector<int>> by;
+    for (int id : ids) {
+        Member *m = ctx->members[id].get();
+        by[{m->d.n, m->d.precision}].push_back(id);
+    }
+    for (auto &kv : by) {
+        Group g;
+        g.n = kv.first.first; g.prec = kv.first.second; g.ids = kv.second;
+        std::vector<MemberDev> host;
+        for (int id : g.ids) host.push_back(ctx->members[id]->md);
+        void *p = nullptr;
+        HIPCK(ctx, hipMalloc(&p, host.size() * sizeof(MemberDev)));
+        ctx->dev_allocs.push_back(p);
+        HIPCK(ctx, hipMemcpy(p, host.data(), host.size() * sizeof(MemberDev), hipMemcpyHostToDevice));
+        g.dev = (MemberDev *)p;
+        HIPCK(ctx, get_twiddles(ctx->device, g.n, g.prec, &g.tw));
+        plan->groups.push_back(g);
+    }
+    *out = plan.get();
+    ctx->plans[ids] = std::move(plan);
+    return ENS_OK;
+}
+
+// Enqueue one RK step of every group of the plan.  With `ev` (profiling),
+// events are recorded around each launch and times are added to ms[pass].
+struct Prof {
+    std::vector<hipEvent_t> ev;
+    std::vector<int> pass;
+};
+
+hipError_t enqueue_step(const Plan &pl, hipStream_t s, Prof *prof) {
+    hipError_t e = hipSuccess;
+    auto rec = [&](int pass, auto &&fn) -> hipError_t {
+        if (prof) {
+            hipEvent_t a, b;
+            hipError_t r = hipEventCreate(&a);
+            if (r != hipSuccess) return r;
+            r = hipEventCreate(&b);
+            if (r != hipSuccess) return r;
+            r = hipEventRecord(a, s);
+            if (r != hipSuccess) return r;
+            r = fn();
+            if (r != hipSuccess) return r;
+            r = hipEventRecord(b, s);
+            prof->ev.push_back(a); prof->ev.push_back(b); prof->pass.push_back(pass);
+            return r;
+        }
+        return fn();
+    };
+    for (int stage = 0; stage < 3; stage++) {
+        for (const Group &g : pl.groups) {
+            const int cnt = (int)g.ids.size();
+            if ((e = rec(P_BAND, [&] { return launch_band_energy(g.n, g.prec, g.dev, cnt, stage, s); }))) return e;
+            if ((e = rec(P_ZINV, [&] { return launch_zinv(g.n, g.prec, g.dev, cnt, g.tw, s); }))) return e;
+            if ((e = rec(P_YINV, [&] { return launch_yinv(g.n, g.prec, g.dev, cnt, 6, g.tw, s); }))) return e;
+            if ((e = rec(P_XPASS, [&] { return launch_xpass(g.n, g.prec, g.dev, cnt, stage, g.tw, s); }))) return e;
+            if ((e = rec(P_YFWD, [&] { return launch_yfwd(g.n, g.prec, g.dev, cnt, g.tw, s); }))) return e;
+            if ((e = rec(P_ZFWD, [&] { return launch_zfwd_update(g.n, g.prec, g.dev, cnt, stage, g.tw, s); }))) return e;
+        }
+    }
+    for (const Group &g : pl.groups) {
+        const int cnt = (int)g.ids.size();
+        if ((e = rec(P_END, [&] { return launch_end_step(g.n, g.prec, g.dev, cnt, s); }))) return e;
+    }
+    return hipSuccess;
+}
+
+ens_status collect_ids(ens_ctx *ctx, const int32_t *members, int32_t count, std::vector<int> &ids) {
+    if (count <= 0 || !members) return fail(ENS_E_INVALID, "empty member list");
+    ids.assign(members, members + count);
+    std::vector<int> sorted = ids;
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end()) return fail(ENS_E_INVALID, "duplicate member id");
+    for (int id : ids) {
+        Member *m;
+        ens_status st = member_of(ctx, id, &m);
+        if (st) return st;
+    }
+    return ENS_OK;
+}
+
+}  // namespace
+
+// ======================================================================= ABI
+ENS_API const char *ens_last_error(void) { return g_err.c_str(); }
+
+ENS_API ens_status ens_create(ens_ctx **out, int device, const ens_hist_desc *h) {
+    if (!out) return fail(ENS_E_INVALID, "null output pointer");
+    *out = nullptr;
+    if (h) {
+        ens_status st = validate_hist(h);
+        if (st) return st;
+    }
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev <= 0) return fail(ENS_E_HIP, "no HIP device available");
+    if (device < 0 || device >= ndev) return fail(ENS_E_INVALID, "device index out of range");
+    e = hipSetDevice(device);
+    if (e != hipSuccess) return fail(ENS_E_HIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    auto ctx = std::make_unique<ens_ctx>();
+    ctx->device = device;
+    if (h) {
+        ctx->has_hist = true;
+        ctx->hist = *h;
+        ctx->hg = make_hist_geom(*h);
+    }
+    e = hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return fail(ENS_E_HIP, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+    *out = ctx.release();
+    return ENS_OK;
+}
+
+ENS_API ens_status ens_destroy(ens_ctx *ctx) {
+    if (!ctx) return fail(ENS_E_INVALID, "null context");
+    hipSetDevice(ctx->device);
+    hipDeviceSynchronize();
+    for (auto &kv : ctx->plans) {
+        if (kv.second->exec) hipGraphExecDestroy(kv.second->exec);
+        if (kv.second->graph) hipGraphDestroy(kv.second->graph);
+    }
+    for (auto &m : ctx->members)
+        if (m && m->dev) hipFree(m->dev);
+    for (void *p : ctx->dev_allocs) hipFree(p);
+    if (ctx->mix_scratch) hipFree(ctx->mix_scratch);
+    if (ctx->cap) hipStreamDestroy(ctx->cap);
+    delete ctx;
+    return ENS_OK;
+}
+
+ENS_API ens_status ens_set_graphs(ens_ctx *ctx, int32_t enable) {
+    if (ens_status st = check_ctx(ctx)) return st;
+    ctx->graphs = enable != 0;
+    return ENS_OK;
+}
+
+ENS_API ens_status ens_member_workspace_bytes(const ens_ctx *ctx, const ens_member_desc *d, size_t *bytes) {
+    if (ens_status st = check_ctx(ctx)) return st;
+    if (!bytes) return fail(ENS_E_INVALID, "null output pointer");
+    if (ens_status st = validate_desc(d)) return st;
+    *bytes = member_layout(*d, ctx->has_hist ? &ctx->hg : nullptr).total;
+    return ENS_OK;
+}
+
+ENS_API ens_status ens_member_init(ens_ctx *ctx, const ens_member_desc *d, void *dev_workspace, size_t bytes,
+                                   void *stream, int32_t *member_id) {
+    if (ens_status st = check_ctx(ctx)) return st;
+    if (ens_status st = validate_desc(d)) return st;
+    if (!member_id) return fail(ENS_E_INVALID, "null member_id");
+    if (!dev_workspace || ((uintptr_t)dev_workspace & 255)) return fail(ENS_E_INVALID, "workspace must be 256-byte aligned device memory");
+    const Layout lay = member_layout(*d, ctx->has_hist ? &ctx->hg : nullptr);
+    if (bytes < lay.total) return fail(ENS_E_OOM, "workspace too small: need " + std::to_string(lay.total) + " bytes");
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, dev_workspace) != hipSuccess || attr.type != hipMemoryTypeDevice)
+        return fail(ENS_E_INVALID, "workspace is not device memory");
+    HIPCK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    auto m = std::make_unique<Member>();
+    m->d = *d;
+    m->g = make_geom(d->n);
+    m->lay = lay;
+    m->ws = dev_workspace;
+    char *base = (char *)dev_workspace;
+    MemberDev &md = m->md;
+    md.st = (DevState *)(base + lay.off_st);
+    md.uh = base + lay.off_uh;
+    md.q = base + lay.off_q;
+    md.bufA = base + lay.off_a;
+    md.bufB = base + lay.off_b;
+    md.partials = (double *)(base + lay.off_part);
+    md.counts = (unsigned long long *)(base + lay.off_counts);
+    md.moments = (double *)(base + lay.off_mom);
+    md.nu = d->nu;
+    md.eps_m = std::exp(d->lambda) * d->eps_ref;
+    md.kf_lo2 = d->kf_lo * d->kf_lo;
+    md.kf_hi2 = d->kf_hi * d->kf_hi;
+    md.dt_fixed = d->dt > 0 ? d->dt : 0.0;
+    md.cfl = d->cfl;
+    md.box = d->box;
+    md.dk = 2.0 * M_PI / d->box;
+    md.n = d->n; md.K = d->n / 3; md.prec = d->precision; md.visc_mode = d->visc_mode;
+    void *p = nullptr;
+    HIPCK(ctx, hipMalloc(&p, sizeof(MemberDev)));
+    m->dev = (MemberDev *)p;
+    HIPCK(ctx, hipMemcpy(m->dev, &md, sizeof(MemberDev), hipMemcpyHostToDevice));
+    HIPCK(ctx, launch_init_field(d->n, d->precision, m->dev, d->seed, d->k_peak, d->e0, s));
+    if (ctx->has_hist) {
+        HIPCK(ctx, launch_fill_u64(md.counts, ctx->hg.n_counts, 0ull, s));
+        HIPCK(ctx, launch_fill_f64(md.moments, ENS_NMOM, 0.0, s));
+    }
+    m->last = s;
+    *member_id = (int32_t)ctx->members.size();
+    ctx->members.push_back(std::move(m));
+    return ENS_OK;
+}
+
+ENS_API ens_status ens_member_set_state(ens_ctx *ctx, int32_t mid, const double *dev_uhat, void *stream) {
+    if (ens_status st = check_ctx(ctx)) return st;
+    Member *m;
+    if (ens_status st = member_of(ctx, mid, &m)) return st;
+    if (!dev_uhat) return fail(ENS_E_INVALID, "null state pointer");
+    HIPCK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    HIPCK(ctx, launch_set_state(m->d.n, m->d.precision, m->dev, dev_uhat, s));
+    m->last = s;
+    return ENS_OK;
+}
+
+ENS_API ens_status ens_member_get_state(ens_ctx *ctx, int32_t mid, double *dev_uhat, void *stream) {
+    if (ens_status st = check_ctx(ctx)) return st;
+    Member *m;
+    if (ens_status st = member_of(ctx, mid, &m)) return st;
+    if (!dev_uhat) return fail(ENS_E_INVALID, "null state pointer");
+    HIPCK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    HIPCK(ctx, launch_get_state(m->d.n, m->d.precision, m->dev, dev_uhat, s));
+    m->last = s;
+    return ENS_OK;
+}
+
+ENS_API ens_status ens_step(ens_ctx *ctx, const int32_t *members, int32_t count, int32_t nsteps, void *stream) {
+    if (ens_status st = check_ctx(ctx)) return st;
+    if (nsteps < 0) return fail(ENS_E_INVALID, "nsteps must be >= 0");
+    std::vector<int> ids;
+    if (ens_status st = collect_ids(ctx, members, count, ids)) return st;
+    HIPCK(ctx, hipSetDevice(ctx->device));
+    Plan *pl;
+    if (ens_status st = make_plan(ctx, ids, &pl)) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (nsteps == 0) return ENS_OK;
+    if (ctx->graphs) {
+        if (!pl->exec) {
+            HIPCK(ctx, hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
+            hipError_t e = enqueue_step(*pl, ctx->cap, nullptr);
+            hipGraph_t g = nullptr;
+            hipError_t e2 = hipStreamEndCapture(ctx->cap, &g);
+            HIPCK(ctx, e);
+            HIPCK(ctx, e2);
+            pl->graph = g;
+            HIPCK(ctx, hipGraphInstantiate(&pl->exec, g, nullptr, nullptr, 0));
+        }
+        for (int i = 0; i < nsteps; i++) HIPCK(ctx, hipGraphLaunch(pl->exec, s));
+    } else {
+        for (int i = 0; i < nsteps; i++) HIPCK(ctx, enqueue_step(*pl, s, nullptr));
+    }
+    for (int id : ids) ctx->members[id]->last = s;
+    return ENS_OK;
+}
+
+ENS_API ens_status ens_profile_step(ens_ctx *ctx, const int32_t *members, int32_t count, void *stream, double *ms_out) {
+    if (ens_status st = check_ctx(ctx)) return st;
+    if (!ms_out) return fail(ENS_E_INVALID, "null output pointer");
+    std::vector<int> ids;
+    if (ens_status st = collect_ids(ctx, members, count, ids)) return st;
+    HIPCK(ctx, hipSetDevice(ctx->device));
+    Plan *pl;
+    if (ens_status st = make_plan(ctx, ids, &pl)) return st;
+    hipStream_t s = (hipStream_t)stream;
+    Prof prof;
+    hipError_t e = enqueue_step(*pl, s, &prof);
+    hipError_t e2 = hipStreamSynchronize(s);
+    for (int p = 0; p < ENS_NPASS; p++) ms_out[p] = 0.0;
+    for (size_t i = 0; i < prof.pass.size(); i++) {
+        float ms = 0.f;
+        if (e == hipSuccess && e2 == hipSuccess && hipEventElapsedTime(&ms, prof.ev[2 * i], prof.ev[2 * i + 1]) == hipSuccess)
+            ms_out[prof.pass[i]] += ms;
+    }
+    for (hipEvent_t ev : prof.ev) hipEventDestroy(ev);
+    HIPCK(ctx, e);
+    HIPCK(ctx, e2);
+    for (int id : ids) ctx->members[id]->last = s;
+    return ENS_OK;
+}
+
+ENS_API ens_status ens_get_diag(ens_ctx *ctx, int32_t mid, ens_diag *out) {
+    if (ens_status st = check_ctx(ctx)) return st;
+    Member *m;
+    if (ens_status st = member_of(ctx, mid, &m)) return st;
+    if (!out) return fail(ENS_E_INVALID, "null output pointer");
+    HIPCK(ctx, hipSetDevice(ctx->device));
+    HIPCK(ctx, hipStreamSynchronize(m->last));
+    HIPCK(ctx, hipMemcpy(out, &m->md.st->diag, sizeof(ens_diag), hipMemcpyDeviceToHost));
+    return out->flags & 5 ? fail(ENS_E_DIVERGED, "member diverged (non-finite energy or no CFL velocity)") : ENS_OK;
+}
+
+ENS_API ens_status ens_stats_len(const ens_ctx *ctx, size_t *n_counts) {
+    if (ens_status st = check_ctx(ctx)) return st;
+    if (!n_counts) return fail(ENS_E_INVALID, "null output pointer");
+    if (!ctx->has_hist) return fail(ENS_E_STATE, "context has no histogram descriptor");
+    *n_counts = (size_t)ctx->hg.n_counts;
+    return ENS_OK;
+}
+
+ENS_API ens_status ens_accumulate_stats(ens_ctx *ctx, const int32_t *members, int32_t count, void *stream) {
+    if (ens_status st = check_ctx(ctx)) return st;
+    if (!ctx->has_hist) return fail(ENS_E_STATE, "context has no histogram descriptor");
+    std::vector<int> ids;
+    if (ens_status st = collect_ids(ctx, members, count, ids)) return st;
+    HIPCK(ctx, hipSetDevice(ctx->device));
+    Plan *pl;
+    if (ens_status st = make_plan(ctx, ids, &pl)) return st;
+    hipStream_t s = (hipStream_t)stream;
+    for (const Group &g : pl->groups) {
+        const int cnt = (int)g.ids.size();
+        HIPCK(ctx, launch_grad_zinv(g.n, g.prec, g.dev, cnt, g.tw, s));
+        HIPCK(ctx, launch_grad_yinv(g.n, g.prec, g.dev, cnt, g.tw, s));
+        HIPCK(ctx, launch_grad_xstats(g.n, g.prec, g.dev, cnt, ctx->hist, g.tw, s));
+        HIPCK(ctx, launch_stats_reduce(g.n, g.prec, g.dev, cnt, s));
+    }
+    for (int id : ids) ctx->members[id]->last = s;
+    return ENS_OK;
+}
+
+ENS_API ens_status ens_get_stats(ens_ctx *ctx, int32_t mid, uint64_t *counts, double *moments, uint64_t *n_points) {
+    if (ens_status st = check_ctx(ctx)) return st;
+    if (!ctx->has_hist) return fail(ENS_E_STATE, "context has no histogram descriptor");
+    Member *m;
+    if (ens_status st = member_of(ctx, mid, &m)) return st;
+    HIPCK(ctx, hipSetDevice(ctx->device));
+    HIPCK(ctx, hipStreamSynchronize(m->last));
+    if (counts) HIPCK(ctx, hipMemcpy(counts, m->md.counts, ctx->hg.n_counts * sizeof(uint64_t), hipMemcpyDeviceToHost));
+    if (moments) HIPCK(ctx, hipMemcpy(moments, m->md.moments, ENS_NMOM * sizeof(double), hipMemcpyDeviceToHost));
+    if (n_points) {
+        // every snapshot adds n^3 samples to the QR histogram (bins + specials)
+        std::vector<uint64_t> c(ctx->hg.n_counts);
+        HIPCK(ctx, hipMemcpy(c.data(), m->md.counts, c.size() * sizeof(uint64_t), hipMemcpyDeviceToHost));
+        uint64_t s = 0;
+        for (long long i = 0; i < ctx->hg.off_le; i++) s += c[i];
+        *n_points = s;
+    }
+    return ENS_OK;
+}
+
+ENS_API ens_status ens_reset_stats(ens_ctx *ctx, int32_t mid, void *stream) {
+    if (ens_status st = check_ctx(ctx)) return st;
+    if (!ctx->has_hist) return fail(ENS_E_STATE, "context has no histogram descriptor");
+    Member *m;
+    if (ens_status st = member_of(ctx, mid, &m)) return st;
+    HIPCK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    HIPCK(ctx, launch_fill_u64(m->md.counts, ctx->hg.n_counts, 0ull, s));
+    HIPCK(ctx, launch_fill_f64(m->md.moments, ENS_NMOM, 0.0, s));
+    m->last = s;
+    return ENS_OK;
+}
+
+ENS_API ens_status ens_mix_len(const ens_ctx *ctx, int32_t count, size_t *n_out) {
+    if (ens_status st = check_ctx(ctx)) return st;
+    if (!ctx->has_hist) return fail(ENS_E_STATE, "context has no histogram descriptor");
+    if (count <= 0 || !n_out) return fail(ENS_E_INVALID, "bad arguments");
+    const HistGeom &g = ctx->hg;
+    *n_out = (size_t)count + (size_t)g.qb * g.qb + 2 * (size_t)g.lb + 2 * (size_t)g.ab + ENS_NMOM + 8;
+    return ENS_OK;
+}
+
+ENS_API ens_status ens_mix(ens_ctx *ctx, const int32_t *members, int32_t count, double c, double Z,
+                           int32_t weight_mode, double q_sigma, double *dev_out, void *stream) {
+    if (ens_status st = check_ctx(ctx)) return st;
+    if (!ctx->has_hist) return fail(ENS_E_STATE, "context has no histogram descriptor");
+    std::vector<int> ids;
+    if (ens_status st = collect_ids(ctx, members, count, ids)) return st;
+    if (!dev_out) return fail(ENS_E_INVALID, "null output pointer");
+    if (count > mix_max_members()) return fail(ENS_E_INVALID, "too many members for one mixture call");
+    if (!(c > 0) || !(Z >= 0) || !std::isfinite(Z)) return fail(ENS_E_INVALID, "need c > 0 and Z >= 0");
+    if (weight_mode < 0 || weight_mode > 2) return fail(ENS_E_INVALID, "weight_mode must be 0, 1 or 2");
+    if (weight_mode == 2 && (!(q_sigma > 0) || !(Z > 0))) return fail(ENS_E_INVALID, "mode 2 needs q_sigma > 0 and Z > 0");
+    HIPCK(ctx, hipSetDevice(ctx->device));
+    std::vector<const MemberDev *> mds;
+    std::vector<double> lam;
+    for (int id : ids) {
+        mds.push_back(&ctx->members[id]->md);
+        lam.push_back(ctx->members[id]->d.lambda);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    for (int id : ids) HIPCK(ctx, hipStreamSynchronize(ctx->members[id]->last));
+    const size_t need = mix_scratch_bytes(count);
+    if (need > ctx->mix_scratch_bytes) {
+        if (ctx->mix_scratch) HIPCK(ctx, hipFree(ctx->mix_scratch));
+        ctx->mix_scratch = nullptr;
+        HIPCK(ctx, hipMalloc(&ctx->mix_scratch, need));
+        ctx->mix_scratch_bytes = need;
+    }
+    HIPCK(ctx, launch_mix(mds.data(), lam.data(), count, ctx->hist, c, Z, weight_mode, q_sigma, dev_out,
+                          ctx->mix_scratch, s));
+    return ENS_OK;
+}
+
+ENS_API ens_status ens_fft_pencils(int32_t n, int32_t precision, int32_t sign, int64_t lines, const void *dev_in,
+                                   void *dev_out, void *stream) {
+    if (!pow2_supported(n)) return fail(ENS_E_UNSUPPORTED, "n must be one of 16, 32, 64, 128, 256");
+    if (precision != ENS_FP64 && precision != ENS_FP32) return fail(ENS_E_INVALID, "bad precision");
+    if (sign != 1 && sign != -1) return fail(ENS_E_INVALID, "sign must be +1 or -1");
+    if (lines < 0) return fail(ENS_E_INVALID, "lines must be >= 0");
+    if (lines == 0) return ENS_OK;
+    if (!dev_in || !dev_out) return fail(ENS_E_INVALID, "null data pointer");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(ENS_E_HIP, hipGetErrorString(e));
+    const void *tw;
+    e = get_twiddles(dev, n, precision, &tw);
+    if (e != hipSuccess) return fail(ENS_E_HIP, hipGetErrorString(e));
+    e = launch_fft_pencils(n, precision, sign, lines, dev_in, dev_out, tw, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(ENS_E_HIP, hipGetErrorString(e));
+    return ENS_OK;
+}

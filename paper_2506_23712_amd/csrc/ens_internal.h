@@ -1,0 +1,121 @@
+// ens_internal.h -- types shared by the host side and the kernels of libensdns.
+// Not part of the public ABI (include/ens.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/ens.h"
+
+namespace ens {
+
+// Lines (pencils) per workgroup and threads per workgroup of the FFT passes.
+// Each thread owns 16 complex values of one line; a line of length n uses
+// n/16 threads, so a 256-thread workgroup holds 16*256/n lines.
+constexpr int kThreads = 256;
+constexpr int kPerThread = 16;
+
+// Per-member scalars kept in device memory.  `diag` is what ens_get_diag
+// returns; the rest carries values between kernels of one step.
+struct DevState {
+    ens_diag diag;
+    double Ef;                       // band energy of the current stage (FP64)
+    double dt;                       // time step of the current step
+    unsigned long long umax_bits;    // max(|u|+|v|+|w|) as bits of a non-negative double
+    double e_init;                   // energy of the raw initial field (init only)
+    double pad[4];
+};
+
+// Everything a kernel needs to know about one member (lives in a device
+// table owned by the library; pointers refer to the caller's workspace).
+struct MemberDev {
+    void *uh;          // velocity  [3][2K+1 (kz)][2K+1 (ky)][K+1 (kx)] complex
+    void *q;           // RK register, same layout
+    void *bufA;        // [F][n (z)][2K+1][K+1] (z-inverse out) / [3][n][n][K+1] (x-pass out)
+    void *bufB;        // [F][n (z)][n (y)][K+1] (y-inverse out) / [3][n][2K+1][K+1] (y-forward out)
+    DevState *st;
+    double *partials;  // per-workgroup FP64 partial sums
+    unsigned long long *counts;   // statistics counters
+    double *moments;              // ENS_NMOM sums
+    double nu, eps_m, kf_lo2, kf_hi2, dt_fixed, cfl, box, dk;
+    int n, K, prec, visc_mode;
+};
+
+// Host-visible geometry of one member.
+struct Geom {
+    int n, K;
+    long long nzl;     // z-lines = (2K+1)(K+1)
+    long long S;       // retained modes per component = (2K+1) nzl
+    long long nyl;     // y-lines = n (K+1)
+};
+
+inline Geom make_geom(int n) {
+    Geom g;
+    g.n = n; g.K = n / 3;
+    g.nzl = (long long)(2 * g.K + 1) * (g.K + 1);
+    g.S = (long long)(2 * g.K + 1) * g.nzl;
+    g.nyl = (long long)n * (g.K + 1);
+    return g;
+}
+
+// Histogram geometry (from ens_hist_desc).
+struct HistGeom {
+    int qb, lb, ab;
+    long long n_counts;
+    long long off_qr, off_le, off_lw, off_al, off_at;
+};
+
+inline HistGeom make_hist_geom(const ens_hist_desc &h) {
+    HistGeom g;
+    g.qb = h.qr_bins; g.lb = h.log_bins; g.ab = h.a_bins;
+    g.off_qr = 0;
+    g.off_le = (long long)g.qb * g.qb + 3;
+    g.off_lw = g.off_le + g.lb + 3;
+    g.off_al = g.off_lw + g.lb + 3;
+    g.off_at = g.off_al + g.ab + 3;
+    g.n_counts = g.off_at + g.ab + 3;
+    return g;
+}
+
+// Passes timed by ens_profile_step.
+enum Pass { P_BAND = 0, P_ZINV = 1, P_YINV = 2, P_XPASS = 3, P_YFWD = 4, P_ZFWD = 5, P_END = 6 };
+
+// Launchers (defined in the .hip files).  `mem` points to a device array of
+// `count` MemberDev of one size n and precision; grids cover all of them.
+hipError_t launch_band_energy(int n, int prec, const MemberDev *mem, int count, int stage, hipStream_t s);
+hipError_t launch_zinv(int n, int prec, const MemberDev *mem, int count, const void *tw, hipStream_t s);
+hipError_t launch_yinv(int n, int prec, const MemberDev *mem, int count, int nfields, const void *tw, hipStream_t s);
+hipError_t launch_xpass(int n, int prec, const MemberDev *mem, int count, int stage, const void *tw, hipStream_t s);
+hipError_t launch_yfwd(int n, int prec, const MemberDev *mem, int count, const void *tw, hipStream_t s);
+hipError_t launch_zfwd_update(int n, int prec, const MemberDev *mem, int count, int stage, const void *tw, hipStream_t s);
+hipError_t launch_end_step(int n, int prec, const MemberDev *mem, int count, hipStream_t s);
+
+hipError_t launch_init_field(int n, int prec, const MemberDev *mem, uint64_t seed, double k_peak, double e0, hipStream_t s);
+hipError_t launch_set_state(int n, int prec, const MemberDev *mem, const double *src, hipStream_t s);
+hipError_t launch_get_state(int n, int prec, const MemberDev *mem, double *dst, hipStream_t s);
+
+hipError_t launch_grad_zinv(int n, int prec, const MemberDev *mem, int count, const void *tw, hipStream_t s);
+hipError_t launch_grad_yinv(int n, int prec, const MemberDev *mem, int count, const void *tw, hipStream_t s);
+hipError_t launch_grad_xstats(int n, int prec, const MemberDev *mem, int count, const ens_hist_desc &h,
+                              const void *tw, hipStream_t s);
+hipError_t launch_stats_reduce(int n, int prec, const MemberDev *mem, int count, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long *p, long long n, unsigned long long v, hipStream_t s);
+hipError_t launch_fill_f64(double *p, long long n, double v, hipStream_t s);
+
+hipError_t launch_fft_pencils(int n, int prec, int sign, long long lines, const void *in, void *out,
+                              const void *tw, hipStream_t s);
+
+hipError_t launch_mix(const MemberDev *const *members_host, const double *lambdas, int count,
+                      const ens_hist_desc &h, double c, double Z, int mode, double q_sigma,
+                      double *out, void *scratch, hipStream_t s);
+
+size_t mix_scratch_bytes(int count);
+int mix_max_members();
+
+// Number of workgroups that write FP64 partials, per member.
+long long zfwd_blocks(int n);
+long long xstats_blocks(int n);
+long long init_blocks(int n);
+
+}  // namespace ens

@@ -1,0 +1,267 @@
+// fft.hpp -- workgroup-level pencil FFT engine for gfx950.
+//
+// A line of length N is transformed by M = N/E threads, each holding E complex
+// values in registers.  The transform is a Stockham (self-sorting) radix
+// sequence: the first stage has radix E, the next ones radix min(E, remaining).
+// Stage s with radix r and span Ns (product of earlier radices) computes, for
+// every butterfly j in [0, N/r):
+//     k = j mod Ns,
+//     y_m = DFT_r( x[j + m N/r] * w^(m k N/(Ns r)) ),  w = exp(DIR 2 pi i / N),
+//     out[(j/Ns) Ns r + k + m Ns] = y_m.
+// Thread t owns butterflies j = t + M b, b < E/r.  Between stages values
+// are exchanged through LDS laid out [position][line] (lines fastest), so that
+// lanes of consecutive lines touch consecutive LDS words.
+//
+// line_fft   : input  v[m] = x[t + M m]; output v[b r_L + m] = X[out_pos(t, b r_L + m)]
+// line_fft_T : the transposed flow graph (stages reversed, twiddles after the
+//              butterflies): input in out_pos layout, output v[m] = X[t + M m].
+// Both compute the same DFT; using one after the other avoids a permutation.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace ens {
+
+template <typename P> struct V2;
+template <> struct V2<double> { using T = double2; };
+template <> struct V2<float> { using T = float2; };
+
+template <typename P> struct Cx { P re, im; };
+
+template <typename P> __device__ __forceinline__ Cx<P> operator+(Cx<P> a, Cx<P> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename P> __device__ __forceinline__ Cx<P> operator-(Cx<P> a, Cx<P> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename P> __device__ __forceinline__ Cx<P> cmul(Cx<P> a, Cx<P> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename P> __device__ __forceinline__ Cx<P> cmulc(Cx<P> a, Cx<P> b) {   // a * conj(b)
+    return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
+}
+template <typename P> __device__ __forceinline__ Cx<P> cscale(Cx<P> a, P s) { return {a.re * s, a.im * s}; }
+template <typename P> __device__ __forceinline__ Cx<P> cconj(Cx<P> a) { return {a.re, -a.im}; }
+template <typename P> __device__ __forceinline__ Cx<P> mul_i(Cx<P> a) { return {-a.im, a.re}; }       // i a
+template <typename P> __device__ __forceinline__ Cx<P> czero() { return {P(0), P(0)}; }
+
+// multiply by exp(DIR i pi / 2) = DIR i
+template <int DIR, typename P> __device__ __forceinline__ Cx<P> rot90(Cx<P> a) {
+    if constexpr (DIR < 0) return {a.im, -a.re};
+    else return {-a.im, a.re};
+}
+// multiply by (cr + DIR i si)
+template <int DIR, typename P> __device__ __forceinline__ Cx<P> rotc(Cx<P> a, P cr, P si) {
+    if constexpr (DIR < 0) return {a.re * cr + a.im * si, a.im * cr - a.re * si};
+    else return {a.re * cr - a.im * si, a.im * cr + a.re * si};
+}
+
+// cos(pi/8), sin(pi/8), sqrt(1/2)
+#define ENS_C8 0.92387953251128675612818318939678828682
+#define ENS_S8 0.38268343236508977172845998403039886676
+#define ENS_R2 0.70710678118654752440084436210484903928
+
+template <int DIR, typename P> __device__ __forceinline__ void dft2(Cx<P> &a, Cx<P> &b) {
+    Cx<P> t = a; a = t + b; b = t - b;
+}
+
+template <int DIR, typename P> __device__ __forceinline__ void dft4(Cx<P> &a0, Cx<P> &a1, Cx<P> &a2, Cx<P> &a3) {
+    Cx<P> t0 = a0 + a2, t1 = a0 - a2, t2 = a1 + a3, t3 = rot90<DIR>(a1 - a3);
+    a0 = t0 + t2; a2 = t0 - t2; a1 = t1 + t3; a3 = t1 - t3;
+}
+
+template <int DIR, typename P> __device__ __forceinline__ void dft8(Cx<P> *v) {
+    Cx<P> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    Cx<P> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4<DIR>(e0, e1, e2, e3);
+    dft4<DIR>(o0, o1, o2, o3);
+    const P r = P(ENS_R2);
+    o1 = rotc<DIR>(o1, r, r);
+    o2 = rot90<DIR>(o2);
+    o3 = rotc<DIR>(o3, -r, r);
+    v[0] = e0 + o0; v[4] = e0 - o0;
+    v[1] = e1 + o1; v[5] = e1 - o1;
+    v[2] = e2 + o2; v[6] = e2 - o2;
+    v[3] = e3 + o3; v[7] = e3 - o3;
+}
+
+template <int DIR, typename P> __device__ __forceinline__ void dft16(Cx<P> *v) {
+    // 16 = 4 x 4: n = 4 n1 + n2, k = k1 + 4 k2
+    Cx<P> y[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; n2++) {
+        y[n2][0] = v[n2]; y[n2][1] = v[n2 + 4]; y[n2][2] = v[n2 + 8]; y[n2][3] = v[n2 + 12];
+        dft4<DIR>(y[n2][0], y[n2][1], y[n2][2], y[n2][3]);
+    }
+    const P c = P(ENS_C8), s = P(ENS_S8), r = P(ENS_R2);
+    // twiddles w16^(n2 k1)
+    y[1][1] = rotc<DIR>(y[1][1], c, s);
+    y[1][2] = rotc<DIR>(y[1][2], r, r);
+    y[1][3] = rotc<DIR>(y[1][3], s, c);
+    y[2][1] = rotc<DIR>(y[2][1], r, r);
+    y[2][2] = rot90<DIR>(y[2][2]);
+    y[2][3] = rotc<DIR>(y[2][3], -r, r);
+    y[3][1] = rotc<DIR>(y[3][1], s, c);
+    y[3][2] = rotc<DIR>(y[3][2], -r, r);
+    y[3][3] = rotc<DIR>(y[3][3], -c, -s);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; k1++) {
+        Cx<P> a0 = y[0][k1], a1 = y[1][k1], a2 = y[2][k1], a3 = y[3][k1];
+        dft4<DIR>(a0, a1, a2, a3);
+        v[k1] = a0; v[k1 + 4] = a1; v[k1 + 8] = a2; v[k1 + 12] = a3;
+    }
+}
+
+template <int R, int DIR, typename P> __device__ __forceinline__ void dft(Cx<P> *v) {
+    if constexpr (R == 2) dft2<DIR>(v[0], v[1]);
+    else if constexpr (R == 4) dft4<DIR>(v[0], v[1], v[2], v[3]);
+    else if constexpr (R == 8) dft8<DIR>(v);
+    else if constexpr (R == 16) dft16<DIR>(v);
+    else static_assert(R == 2, "unsupported radix");
+}
+
+// ---------------------------------------------------------------- stage plan
+__host__ __device__ constexpr int stage_radix(int N, int E, int s) {
+    int rem = N, r = 1;
+    for (int i = 0; i <= s; i++) { r = rem < E ? rem : E; rem /= r; }
+    return r;
+}
+__host__ __device__ constexpr int num_stages(int N, int E) {
+    int rem = N, s = 0;
+    while (rem > 1) { int r = rem < E ? rem : E; rem /= r; s++; }
+    return s;
+}
+__host__ __device__ constexpr int stage_span(int N, int E, int s) {
+    int p = 1;
+    for (int i = 0; i < s; i++) p *= stage_radix(N, E, i);
+    return p;
+}
+
+template <int N, int E> struct Plan {
+    static constexpr int M = N / E;                              // threads per line
+    static constexpr int S = num_stages(N, E);
+    static constexpr int RL = stage_radix(N, E, S - 1);          // last radix
+    // output position of register slot `slot` of thread t after line_fft
+    __device__ static __forceinline__ int out_pos(int t, int slot) {
+        return t + M * (slot / RL) + (slot % RL) * (N / RL);
+    }
+    // input position of register slot m (before line_fft / after line_fft_T)
+    __device__ static __forceinline__ int in_pos(int t, int m) { return t + M * m; }
+};
+
+// Twiddle w_N^idx for direction DIR from a table of exp(-2 pi i j / N).
+template <int DIR, typename P> __device__ __forceinline__ Cx<P> twiddle(const Cx<P> *tw, int idx) {
+    Cx<P> w = tw[idx];
+    if constexpr (DIR > 0) w.im = -w.im;
+    return w;
+}
+
+template <typename P> using LdsT = typename V2<P>::T;
+
+template <typename P> __device__ __forceinline__ void lds_put(LdsT<P> *lds, int i, Cx<P> v) {
+    LdsT<P> x; x.x = v.re; x.y = v.im; lds[i] = x;
+}
+template <typename P> __device__ __forceinline__ Cx<P> lds_get(const LdsT<P> *lds, int i) {
+    LdsT<P> x = lds[i]; return {x.x, x.y};
+}
+
+// One forward-flow stage s >= 1: gather from LDS, twiddle, butterfly.
+template <typename P, int N, int E, int T, int DIR, int s>
+__device__ __forceinline__ void stage_gather(Cx<P> *v, const LdsT<P> *lds, int l, int t, const Cx<P> *tw) {
+    constexpr int R = stage_radix(N, E, s), NS = stage_span(N, E, s), M = N / E;
+#pragma unroll
+    for (int b = 0; b < E / R; b++) {
+        const int j = t + M * b, k = j % NS;
+#pragma unroll
+        for (int m = 0; m < R; m++) {
+            Cx<P> x = lds_get<P>(lds, (j + m * (N / R)) * T + l);
+            if (m > 0) x = cmul(x, twiddle<DIR>(tw, m * k * (N / (NS * R))));
+            v[b * R + m] = x;
+        }
+        dft<R, DIR>(v + b * R);
+    }
+}
+
+// Scatter the outputs of stage s to LDS.
+template <typename P, int N, int E, int T, int s>
+__device__ __forceinline__ void stage_scatter(const Cx<P> *v, LdsT<P> *lds, int l, int t) {
+    constexpr int R = stage_radix(N, E, s), NS = stage_span(N, E, s), M = N / E;
+#pragma unroll
+    for (int b = 0; b < E / R; b++) {
+        const int j = t + M * b, k = j % NS;
+#pragma unroll
+        for (int m = 0; m < R; m++) lds_put<P>(lds, ((j / NS) * NS * R + k + m * NS) * T + l, v[b * R + m]);
+    }
+}
+
+template <typename P, int N, int E, int T, int DIR, int s>
+__device__ __forceinline__ void run_stages(Cx<P> *v, LdsT<P> *lds, int l, int t, const Cx<P> *tw) {
+    if constexpr (s < num_stages(N, E)) {
+        __syncthreads();
+        stage_scatter<P, N, E, T, s - 1>(v, lds, l, t);
+        __syncthreads();
+        stage_gather<P, N, E, T, DIR, s>(v, lds, l, t, tw);
+        run_stages<P, N, E, T, DIR, s + 1>(v, lds, l, t, tw);
+    }
+}
+
+// Forward-flow transform.  All threads of the workgroup must call it (it
+// contains barriers).  LDS: N*T elements of V2<P>.
+template <typename P, int N, int E, int T, int DIR>
+__device__ __forceinline__ void line_fft(Cx<P> *v, LdsT<P> *lds, int l, int t, const Cx<P> *tw) {
+    static_assert(N % E == 0 && N >= E, "line length must be a multiple of E");
+    dft<E, DIR>(v);                       // stage 0: span 1, no twiddles
+    run_stages<P, N, E, T, DIR, 1>(v, lds, l, t, tw);
+}
+
+// ---- transposed flow (stages in reverse order, twiddles after the butterflies)
+template <typename P, int N, int E, int T, int DIR, int s>
+__device__ __forceinline__ void stageT_compute(Cx<P> *v, int t, const Cx<P> *tw) {
+    constexpr int R = stage_radix(N, E, s), NS = stage_span(N, E, s), M = N / E;
+#pragma unroll
+    for (int b = 0; b < E / R; b++) {
+        const int j = t + M * b, k = j % NS;
+        dft<R, DIR>(v + b * R);
+        if constexpr (NS > 1) {
+#pragma unroll
+            for (int m = 1; m < R; m++) v[b * R + m] = cmul(v[b * R + m], twiddle<DIR>(tw, m * k * (N / (NS * R))));
+        }
+    }
+}
+// after stage s (transposed) values belong at its input positions j + m N/R
+template <typename P, int N, int E, int T, int s>
+__device__ __forceinline__ void stageT_scatter(const Cx<P> *v, LdsT<P> *lds, int l, int t) {
+    constexpr int R = stage_radix(N, E, s), M = N / E;
+#pragma unroll
+    for (int b = 0; b < E / R; b++) {
+        const int j = t + M * b;
+#pragma unroll
+        for (int m = 0; m < R; m++) lds_put<P>(lds, (j + m * (N / R)) * T + l, v[b * R + m]);
+    }
+}
+// stage s (transposed) reads from its output positions
+template <typename P, int N, int E, int T, int s>
+__device__ __forceinline__ void stageT_gather(Cx<P> *v, const LdsT<P> *lds, int l, int t) {
+    constexpr int R = stage_radix(N, E, s), NS = stage_span(N, E, s), M = N / E;
+#pragma unroll
+    for (int b = 0; b < E / R; b++) {
+        const int j = t + M * b, k = j % NS;
+#pragma unroll
+        for (int m = 0; m < R; m++) v[b * R + m] = lds_get<P>(lds, ((j / NS) * NS * R + k + m * NS) * T + l);
+    }
+}
+
+template <typename P, int N, int E, int T, int DIR, int s>
+__device__ __forceinline__ void run_stagesT(Cx<P> *v, LdsT<P> *lds, int l, int t, const Cx<P> *tw) {
+    stageT_compute<P, N, E, T, DIR, s>(v, t, tw);
+    if constexpr (s > 0) {
+        __syncthreads();
+        stageT_scatter<P, N, E, T, s>(v, lds, l, t);
+        __syncthreads();
+        stageT_gather<P, N, E, T, s - 1>(v, lds, l, t);
+        run_stagesT<P, N, E, T, DIR, s - 1>(v, lds, l, t, tw);
+    }
+}
+
+template <typename P, int N, int E, int T, int DIR>
+__device__ __forceinline__ void line_fft_T(Cx<P> *v, LdsT<P> *lds, int l, int t, const Cx<P> *tw) {
+    run_stagesT<P, N, E, T, DIR, num_stages(N, E) - 1>(v, lds, l, t, tw);
+}
+
+}  // namespace ens

@@ -1,0 +1,550 @@
+// kernels_stats.hip -- velocity-gradient statistics of a snapshot and the
+// Gaussian-in-lambda ensemble mixture.
+//
+// Gradient transforms (K = N/3):
+//   gzinv  : U_c = Z^-1[u_c], W_c = Z^-1[i k_z u_c]              -> bufA [6][N][NZL]
+//   gyinv  : U_c, V_c = d_y u_c, W_c = d_z u_c (y physical)      -> bufB [9][N][N][K+1]
+//   gxstats: A_c1 = X^-1[i k_x U_c], A_c2 = X^-1[V_c], A_c3 = X^-1[W_c] (c2r),
+//            then per point in FP64: Q, R, eps, omega^2, histograms, moments.
+#include <vector>
+
+#include "ens_internal.h"
+#include "fft.hpp"
+
+namespace ens {
+
+template <typename P> using L2 = LdsT<P>;
+
+template <typename P> __device__ __forceinline__ Cx<P> ldc(const void *base, long long i) {
+    L2<P> v = reinterpret_cast<const L2<P> *>(base)[i];
+    return {v.x, v.y};
+}
+template <typename P> __device__ __forceinline__ void stc(void *base, long long i, Cx<P> c) {
+    L2<P> v; v.x = c.re; v.y = c.im;
+    reinterpret_cast<L2<P> *>(base)[i] = v;
+}
+__device__ __forceinline__ int mode_of(int n, int N) { return n <= N / 2 ? n : n - N; }
+
+template <int N> struct SCfg {
+    static constexpr int K = N / 3;
+    static constexpr long long NZL = (long long)(2 * K + 1) * (K + 1);
+    static constexpr long long S = (long long)(2 * K + 1) * NZL;
+    static constexpr long long NYL = (long long)N * (K + 1);
+    static constexpr int E16 = 16, M16 = N / 16, T16 = 256 / M16;
+    static constexpr int E8 = 8, M8 = N / 8, TX = 256 / M8;
+};
+
+// ------------------------------------------------------------------ gzinv
+template <typename P, int N>
+__global__ void __launch_bounds__(256) k_gzinv(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw) {
+    using C = SCfg<N>;
+    constexpr int E = C::E16, M = C::M16, T = C::T16, K = C::K;
+    __shared__ L2<P> lds[N * T];
+    const MemberDev &md = mems[blockIdx.y];
+    const int l = threadIdx.x % T, t = threadIdx.x / T;
+    const long long L = (long long)blockIdx.x * T + l;
+    const bool valid = L < C::NZL;
+    const P dk = (P)md.dk;
+    Cx<P> a[E], b[E];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+#pragma unroll
+        for (int m = 0; m < E; m++) {
+            const int mz = mode_of(t + M * m, N);
+            const bool keep = valid && mz >= -K && mz <= K;
+            a[m] = keep ? ldc<P>(md.uh, c * C::S + (mz >= 0 ? mz : mz + 2 * K + 1) * C::NZL + L) : czero<P>();
+            b[m] = mul_i(cscale(a[m], dk * (P)mz));
+        }
+        line_fft<P, N, E, T, +1>(b, lds, l, t, tw);
+        line_fft<P, N, E, T, +1>(a, lds, l, t, tw);
+        if (valid) {
+#pragma unroll
+            for (int s = 0; s < E; s++) {
+                const int z = Plan<N, E>::out_pos(t, s);
+                stc<P>(md.bufA, ((3 + c) * N + z) * C::NZL + L, b[s]);
+                stc<P>(md.bufA, (c * N + z) * C::NZL + L, a[s]);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ gyinv
+template <typename P, int N>
+__global__ void __launch_bounds__(256) k_gyinv(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw) {
+    using C = SCfg<N>;
+    constexpr int E = C::E16, M = C::M16, T = C::T16, K = C::K;
+    __shared__ L2<P> lds[N * T];
+    const MemberDev &md = mems[blockIdx.y];
+    const int l = threadIdx.x % T, t = threadIdx.x / T;
+    const long long L = (long long)blockIdx.x * T + l;
+    const bool valid = L < C::NYL;
+    const long long z = valid ? L / (K + 1) : 0;
+    const int kx = valid ? (int)(L % (K + 1)) : 0;
+    const P dk = (P)md.dk;
+    auto load = [&](Cx<P> *v, int f) {
+#pragma unroll
+        for (int m = 0; m < E; m++) {
+            const int my = mode_of(t + M * m, N);
+            const bool keep = valid && my >= -K && my <= K;
+            v[m] = keep ? ldc<P>(md.bufA, (f * N + z) * C::NZL + (long long)(my >= 0 ? my : my + 2 * K + 1) * (K + 1) + kx)
+                        : czero<P>();
+        }
+    };
+    auto store = [&](const Cx<P> *v, int f) {
+        if (valid) {
+#pragma unroll
+            for (int s = 0; s < E; s++)
+                stc<P>(md.bufB, ((f * N + z) * N + Plan<N, E>::out_pos(t, s)) * (long long)(K + 1) + kx, v[s]);
+        }
+    };
+    Cx<P> a[E], b[E];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        load(a, c);
+#pragma unroll
+        for (int m = 0; m < E; m++) b[m] = mul_i(cscale(a[m], dk * (P)mode_of(t + M * m, N)));
+        line_fft<P, N, E, T, +1>(b, lds, l, t, tw);
+        store(b, 3 + c);
+        line_fft<P, N, E, T, +1>(a, lds, l, t, tw);
+        store(a, c);
+        load(a, 3 + c);
+        line_fft<P, N, E, T, +1>(a, lds, l, t, tw);
+        store(a, 6 + c);
+    }
+}
+
+// ----------------------------------------------------------------- gxstats
+struct HistArgs {
+    int qb, lb, ab;
+    long long off_le, off_lw, off_al, off_at;
+    double q_lo, q_scale, r_lo, r_scale, l_lo, l_scale, a_lo, a_scale;
+    double tau, inv_trs, inv_trs15, inv_eps_ref, om_scale;
+    int qr_in_lds, d1_in_lds;
+};
+
+// -1 under, -2 over, -3 nan, else bin
+__device__ __forceinline__ int bin_of(double x, double lo, double scale, int nb) {
+    if (x != x) return -3;
+    if (x < lo) return -1;
+    const double b = floor((x - lo) * scale);
+    if (b >= (double)nb) return -2;
+    return (int)b;
+}
+__device__ __forceinline__ int slot_1d(int b, int nb) { return b >= 0 ? b : (b == -1 ? nb : (b == -2 ? nb + 1 : nb + 2)); }
+
+template <typename P, int N>
+__global__ void __launch_bounds__(256) k_gxstats(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw, HistArgs h) {
+    using C = SCfg<N>;
+    constexpr int E = C::E8, M = C::M8, T = C::TX, K = C::K;
+    extern __shared__ unsigned int hs[];                    // dynamic: 1-D histograms (+ QR)
+    __shared__ L2<P> lds[N * T];
+    __shared__ double red[4][32];
+    const MemberDev &md = mems[blockIdx.y];
+    const int l = threadIdx.x % T, t = threadIdx.x / T;
+    const long long R = (long long)blockIdx.x * T + l;
+    const long long plane = (long long)N * N;
+    const P dk = (P)md.dk;
+    const int n1d = 2 * (h.lb + 3) + 2 * (h.ab + 3);
+    const int nqr = h.qr_in_lds ? h.qb * h.qb + 3 : 0;
+    const int nh_lds = (h.d1_in_lds ? n1d : 0) + nqr;
+    for (int i = threadIdx.x; i < nh_lds; i += 256) hs[i] = 0u;
+    // spectral value of gradient field f = 3 c + j at kx
+    auto spec = [&](int f, int kx) -> Cx<P> {
+        const int c = f / 3, j = f % 3;
+        if (j == 0) return mul_i(cscale(ldc<P>(md.bufB, (c * plane + R) * (K + 1) + kx), dk * (P)kx));
+        return ldc<P>(md.bufB, (((j == 1 ? 3 : 6) + c) * plane + R) * (K + 1) + kx);
+    };
+    P g[9][E];
+    Cx<P> v[E];
+#pragma unroll
+    for (int pr = 0; pr < 5; pr++) {
+        const int fa = 2 * pr, fb = 2 * pr + 1;
+#pragma unroll
+        for (int m = 0; m < E; m++) {
+            const int n = t + M * m;
+            Cx<P> A = czero<P>(), B = czero<P>();
+            if (n <= K) { A = spec(fa, n); if (fb < 9) B = spec(fb, n); }
+            else if (n >= N - K) { A = cconj(spec(fa, N - n)); if (fb < 9) B = cconj(spec(fb, N - n)); }
+            if (n == 0) { A.im = P(0); B.im = P(0); }
+            v[m] = {A.re - B.im, A.im + B.re};
+        }
+        line_fft<P, N, E, T, +1>(v, lds, l, t, tw);
+#pragma unroll
+        for (int s = 0; s < E; s++) { g[fa][s] = v[s].re; if (fb < 9) g[fb][s] = v[s].im; }
+    }
+    __syncthreads();   // LDS histograms zeroed before use
+    unsigned int *h_le = hs, *h_lw = hs + (h.lb + 3), *h_al = hs + 2 * (h.lb + 3), *h_at = h_al + (h.ab + 3);
+    unsigned int *h_qr = hs + (h.d1_in_lds ? n1d : 0);
+    unsigned long long *G = md.counts;
+    double mom[26];
+#pragma unroll
+    for (int i = 0; i < 26; i++) mom[i] = 0.0;
+    const double nu = md.nu;
+#pragma unroll
+    for (int s = 0; s < E; s++) {
+        double a[3][3];
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int j = 0; j < 3; j++) a[i][j] = (double)g[3 * i + j][s];
+        const double tr = a[0][0] + a[1][1] + a[2][2];
+        double q = 0.0, r = 0.0, ss = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int j = 0; j < 3; j++) {
+                q += a[i][j] * a[j][i];
+                const double sij = 0.5 * (a[i][j] + a[j][i]);
+                ss += sij * sij;
+#pragma unroll
+                for (int k = 0; k < 3; k++) r += a[i][j] * a[j][k] * a[k][i];
+            }
+        q *= -0.5; r *= -1.0 / 3.0;
+        const double w0 = a[2][1] - a[1][2], w1 = a[0][2] - a[2][0], w2 = a[1][0] - a[0][1];
+        const double ens = w0 * w0 + w1 * w1 + w2 * w2;
+        const double qs = q * h.inv_trs, rs = r * h.inv_trs15;
+        const double es = 2.0 * nu * ss * h.inv_eps_ref, ws = ens * h.om_scale;
+        // QR
+        {
+            int idx;
+            if (qs != qs || rs != rs) idx = h.qb * h.qb + 2;
+            else {
+                const int bq = bin_of(qs, h.q_lo, h.q_scale, h.qb), br = bin_of(rs, h.r_lo, h.r_scale, h.qb);
+                idx = (bq < 0 || br < 0) ? h.qb * h.qb : bq * h.qb + br;
+            }
+            if (h.qr_in_lds) atomicAdd(&h_qr[idx], 1u);
+            else atomicAdd(&G[idx], 1ull);
+        }
+        const int ble = slot_1d(es > 0.0 ? bin_of(log10(es), h.l_lo, h.l_scale, h.lb) : (es != es ? -3 : -1), h.lb);
+        const int blw = slot_1d(ws > 0.0 ? bin_of(log10(ws), h.l_lo, h.l_scale, h.lb) : (ws != ws ? -3 : -1), h.lb);
+        if (h.d1_in_lds) { atomicAdd(&h_le[ble], 1u); atomicAdd(&h_lw[blw], 1u); }
+        else { atomicAdd(&G[h.off_le + ble], 1ull); atomicAdd(&G[h.off_lw + blw], 1ull); }
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int j = 0; j < 3; j++) {
+                const double x = a[i][j] * h.tau;
+                const int b = slot_1d(bin_of(x, h.a_lo, h.a_scale, h.ab), h.ab);
+                if (i == j) {
+                    if (h.d1_in_lds) atomicAdd(&h_al[b], 1u); else atomicAdd(&G[h.off_al + b], 1ull);
+                } else {
+                    if (h.d1_in_lds) atomicAdd(&h_at[b], 1u); else atomicAdd(&G[h.off_at + b], 1ull);
+                }
+                double xp = 1.0;
+#pragma unroll
+                for (int p = 0; p < 6; p++) { xp *= x; mom[(i == j ? 0 : 6) + p] += xp; }
+            }
+        double ep = 1.0, wp = 1.0;
+#pragma unroll
+        for (int p = 0; p < 4; p++) { ep *= es; wp *= ws; mom[12 + p] += ep; mom[16 + p] += wp; }
+        mom[20] += qs; mom[21] += rs;
+        mom[22] += ss * h.tau * h.tau;
+        mom[23] += tr * tr * h.tau * h.tau;
+        mom[24] += qs * qs; mom[25] += rs * rs;
+    }
+    // deterministic reduction of the moments: wave butterfly, then waves in order
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int i = 0; i < 26; i++) {
+        double x = mom[i];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        if (lane == 0) red[wave][i] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 32) {
+        double x = 0.0;
+        if (threadIdx.x < 26) x = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
+        md.partials[(long long)blockIdx.x * 32 + threadIdx.x] = x;
+    }
+    // flush LDS histograms
+    if (h.d1_in_lds) {
+        for (int i = threadIdx.x; i < n1d; i += 256) {
+            const unsigned int c = hs[i];
+            if (!c) continue;
+            long long gi;
+            if (i < h.lb + 3) gi = h.off_le + i;
+            else if (i < 2 * (h.lb + 3)) gi = h.off_lw + (i - (h.lb + 3));
+            else if (i < 2 * (h.lb + 3) + h.ab + 3) gi = h.off_al + (i - 2 * (h.lb + 3));
+            else gi = h.off_at + (i - 2 * (h.lb + 3) - (h.ab + 3));
+            atomicAdd(&G[gi], (unsigned long long)c);
+        }
+    }
+    if (h.qr_in_lds) {
+        for (int i = threadIdx.x; i < nqr; i += 256) {
+            const unsigned int c = h_qr[i];
+            if (c) atomicAdd(&G[i], (unsigned long long)c);
+        }
+    }
+}
+
+// one workgroup per member: moments += sum over blocks (fixed order)
+__global__ void __launch_bounds__(256) k_stats_reduce(const MemberDev *__restrict__ mems, long long nblocks) {
+    __shared__ double red[256];
+    const MemberDev &md = mems[blockIdx.x];
+    for (int i = 0; i < 26; i++) {
+        double x = 0.0;
+        for (long long b = threadIdx.x; b < nblocks; b += 256) x += md.partials[b * 32 + i];
+        red[threadIdx.x] = x;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) md.moments[i] += red[0];
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+template <typename P, int N>
+static hipError_t stats_pass(int pass, const MemberDev *mem, int count, const ens_hist_desc *hd, const void *tw, hipStream_t s) {
+    using C = SCfg<N>;
+    const Cx<P> *twp = reinterpret_cast<const Cx<P> *>(tw);
+    if (pass == 0) {
+        k_gzinv<P, N><<<dim3((unsigned)((C::NZL + C::T16 - 1) / C::T16), count), 256, 0, s>>>(mem, twp);
+    } else if (pass == 1) {
+        k_gyinv<P, N><<<dim3((unsigned)((C::NYL + C::T16 - 1) / C::T16), count), 256, 0, s>>>(mem, twp);
+    } else if (pass == 2) {
+        const ens_hist_desc &d = *hd;
+        HistArgs h;
+        const HistGeom g = make_hist_geom(d);
+        h.qb = d.qr_bins; h.lb = d.log_bins; h.ab = d.a_bins;
+        h.off_le = g.off_le; h.off_lw = g.off_lw; h.off_al = g.off_al; h.off_at = g.off_at;
+        h.q_lo = d.q_lo; h.q_scale = (double)d.qr_bins / (d.q_hi - d.q_lo);
+        h.r_lo = d.r_lo; h.r_scale = (double)d.qr_bins / (d.r_hi - d.r_lo);
+        h.l_lo = d.log10_lo; h.l_scale = (double)d.log_bins / (d.log10_hi - d.log10_lo);
+        h.a_lo = d.a_lo; h.a_scale = (double)d.a_bins / (d.a_hi - d.a_lo);
+        h.tau = sqrt(d.nu_ref / d.eps_ref);
+        const double trs = d.eps_ref / (2.0 * d.nu_ref);
+        h.inv_trs = 1.0 / trs;
+        h.inv_trs15 = 1.0 / pow(trs, 1.5);
+        h.inv_eps_ref = 1.0 / d.eps_ref;
+        h.om_scale = d.nu_ref / d.eps_ref;
+        const size_t n1d = 2 * (size_t)(h.lb + 3) + 2 * (size_t)(h.ab + 3);
+        // dynamic LDS budget: static LDS (transform tile + reduction) plus this stays below 64 KiB
+        const size_t budget = 65536 - (size_t)N * C::TX * sizeof(L2<P>) - 4 * 32 * sizeof(double) - 1024;
+        h.d1_in_lds = n1d * 4 <= budget;
+        const size_t left = budget - (h.d1_in_lds ? n1d * 4 : 0);
+        h.qr_in_lds = (size_t)(h.qb * h.qb + 3) * 4 <= left;
+        const size_t dyn = ((h.d1_in_lds ? n1d : 0) + (h.qr_in_lds ? (size_t)h.qb * h.qb + 3 : 0)) * 4;
+        k_gxstats<P, N><<<dim3((unsigned)((long long)N * N / C::TX), count), 256, dyn, s>>>(mem, twp, h);
+    } else {
+        k_stats_reduce<<<count, 256, 0, s>>>(mem, (long long)N * N / C::TX);
+    }
+    return hipGetLastError();
+}
+
+template <typename P>
+static hipError_t stats_n(int n, int pass, const MemberDev *mem, int count, const ens_hist_desc *hd, const void *tw, hipStream_t s) {
+    switch (n) {
+    case 16: return stats_pass<P, 16>(pass, mem, count, hd, tw, s);
+    case 32: return stats_pass<P, 32>(pass, mem, count, hd, tw, s);
+    case 64: return stats_pass<P, 64>(pass, mem, count, hd, tw, s);
+    case 128: return stats_pass<P, 128>(pass, mem, count, hd, tw, s);
+    case 256: return stats_pass<P, 256>(pass, mem, count, hd, tw, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+static hipError_t stats_dispatch(int n, int prec, int pass, const MemberDev *mem, int count, const ens_hist_desc *hd,
+                                 const void *tw, hipStream_t s) {
+    return prec == ENS_FP32 ? stats_n<float>(n, pass, mem, count, hd, tw, s) : stats_n<double>(n, pass, mem, count, hd, tw, s);
+}
+
+hipError_t launch_grad_zinv(int n, int prec, const MemberDev *mem, int count, const void *tw, hipStream_t s) {
+    return stats_dispatch(n, prec, 0, mem, count, nullptr, tw, s);
+}
+hipError_t launch_grad_yinv(int n, int prec, const MemberDev *mem, int count, const void *tw, hipStream_t s) {
+    return stats_dispatch(n, prec, 1, mem, count, nullptr, tw, s);
+}
+hipError_t launch_grad_xstats(int n, int prec, const MemberDev *mem, int count, const ens_hist_desc &h, const void *tw, hipStream_t s) {
+    return stats_dispatch(n, prec, 2, mem, count, &h, tw, s);
+}
+hipError_t launch_stats_reduce(int n, int prec, const MemberDev *mem, int count, hipStream_t s) {
+    return stats_dispatch(n, prec, 3, mem, count, nullptr, nullptr, s);
+}
+long long xstats_blocks(int n) { return (long long)n * n / (256 / (n / 8)); }
+
+// =================================================================== mixture
+struct MixIn {
+    const unsigned long long *counts;
+    const double *moments;
+    double lambda;
+    double ntot;      // samples per histogram (written by k_mix_prep)
+    double w;         // weight (written by k_mix_weights)
+    int order;        // member index at sorted rank (written by k_mix_weights)
+    int pad;
+};
+
+__global__ void __launch_bounds__(256) k_mix_prep(MixIn *mi, long long nqr) {
+    __shared__ unsigned long long red[256];
+    unsigned long long s = 0;
+    const unsigned long long *c = mi[blockIdx.x].counts;
+    for (long long i = threadIdx.x; i < nqr; i += 256) s += c[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) mi[blockIdx.x].ntot = (double)red[0];
+}
+
+// normal mass of [a, b) with erfc tails
+__device__ double nmass(double a, double b, double mu, double sig) {
+    const double r = 1.0 / (sig * sqrt(2.0));
+    auto upper = [&](double x) { return isinf(x) && x > 0 ? 0.0 : 0.5 * erfc((x - mu) * r); };
+    auto lower = [&](double x) { return isinf(x) && x < 0 ? 0.0 : 0.5 * erfc((mu - x) * r); };
+    if (a >= mu) return upper(a) - upper(b);
+    if (b <= mu) return lower(b) - lower(a);
+    return 1.0 - lower(a) - upper(b);
+}
+
+constexpr int kMaxMix = 1023;
+
+__global__ void __launch_bounds__(1024) k_mix_weights(MixIn *mi, int count, double c, double Z, int mode, double qs, double *out) {
+    __shared__ double raw[kMaxMix + 1];
+    const int i = threadIdx.x;
+    double w = 0.0;
+    if (i < count) {
+        const double li = mi[i].lambda;
+        int rank = 0;
+        double prev = -INFINITY, next = INFINITY;
+        bool has_prev = false, has_next = false;
+        for (int j = 0; j < count; j++) {
+            const double lj = mi[j].lambda;
+            const bool before = lj < li || (lj == li && j < i);
+            if (before) { rank++; if (!has_prev || lj >= prev) { prev = lj; has_prev = true; } }
+            else if (j != i) { if (!has_next || lj < next) { next = lj; has_next = true; } }
+        }
+        mi[rank].order = i;
+        double a = has_prev ? 0.5 * (prev + li) : -INFINITY;
+        double b = has_next ? 0.5 * (li + next) : INFINITY;
+        if (mode == 1 && count > 1) {
+            if (!has_prev) a = li - (b - li);
+            if (!has_next) b = li + (li - a);
+        }
+        if (mode == 2) {
+            const double mu = -4.5 * c * Z, sig = sqrt(9.0 * c * Z);
+            const double p = exp(-(li - mu) * (li - mu) / (2.0 * sig * sig)) / sig;
+            const double q = exp(-li * li / (2.0 * qs * qs)) / qs;
+            w = p / q;
+        } else if (Z <= 0.0) {
+            w = (a <= 0.0 && 0.0 < b) ? 1.0 : 0.0;
+        } else {
+            w = nmass(a, b, -4.5 * c * Z, sqrt(9.0 * c * Z));
+        }
+    }
+    raw[i] = w;
+    __syncthreads();
+    if (i == 0 && (mode == 1 || mode == 2)) {
+        double s = 0.0;
+        for (int r = 0; r < count; r++) s += raw[mi[r].order];
+        raw[kMaxMix] = s;    // count <= kMaxMix keeps this slot free
+    }
+    __syncthreads();
+    if (i < count) {
+        if (mode == 1 || mode == 2) w = w / raw[kMaxMix];
+        mi[i].w = w;
+        out[i] = w;
+    }
+}
+
+struct MixGeom {
+    int qb, lb, ab, count;
+    long long off_le, off_lw, off_al, off_at;
+    double area_qr, w_l, w_a;
+    long long o_qr, o_le, o_lw, o_al, o_at, o_mom, o_der;
+};
+
+__global__ void __launch_bounds__(256) k_mix_pdf(const MixIn *__restrict__ mi, MixGeom g, double *out) {
+    const long long nqr = (long long)g.qb * g.qb;
+    const long long total = nqr + 2LL * g.lb + 2LL * g.ab;
+    const long long b = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (b >= total) return;
+    long long src, dst;
+    double width, mult;
+    if (b < nqr) { src = b; dst = g.o_qr + b; width = g.area_qr; mult = 1.0; }
+    else if (b < nqr + g.lb) { src = g.off_le + (b - nqr); dst = g.o_le + (b - nqr); width = g.w_l; mult = 1.0; }
+    else if (b < nqr + 2 * g.lb) { const long long k = b - nqr - g.lb; src = g.off_lw + k; dst = g.o_lw + k; width = g.w_l; mult = 1.0; }
+    else if (b < nqr + 2 * g.lb + g.ab) { const long long k = b - nqr - 2 * g.lb; src = g.off_al + k; dst = g.o_al + k; width = g.w_a; mult = 3.0; }
+    else { const long long k = b - nqr - 2 * g.lb - g.ab; src = g.off_at + k; dst = g.o_at + k; width = g.w_a; mult = 6.0; }
+    double acc = 0.0;
+    for (int r = 0; r < g.count; r++) {
+        const MixIn &m = mi[mi[r].order];
+        const double n = m.ntot * mult;
+        if (n > 0.0) acc += m.w * ((double)m.counts[src] / (n * width));
+    }
+    out[dst] = acc;
+}
+
+__global__ void __launch_bounds__(64) k_mix_moments(const MixIn *__restrict__ mi, MixGeom g, double *out) {
+    __shared__ double mm[32];
+    const int k = threadIdx.x;
+    if (k < 32) {
+        const double mult = k < 6 ? 3.0 : (k < 12 ? 6.0 : 1.0);
+        double acc = 0.0;
+        if (k < 26) {
+            for (int r = 0; r < g.count; r++) {
+                const MixIn &m = mi[mi[r].order];
+                if (m.ntot > 0.0) acc += m.w * (m.moments[k] / (m.ntot * mult));
+            }
+        }
+        mm[k] = acc;
+        out[g.o_mom + k] = acc;
+    }
+    __syncthreads();
+    if (k == 0) {
+        double *d = out + g.o_der;
+        d[0] = mm[2] / pow(mm[1], 1.5);
+        d[1] = mm[3] / (mm[1] * mm[1]);
+        d[2] = mm[5] / (mm[1] * mm[1] * mm[1]);
+        d[3] = mm[9] / (mm[7] * mm[7]);
+        d[4] = mm[11] / (mm[7] * mm[7] * mm[7]);
+        d[5] = mm[12];
+        d[6] = mm[16];
+        d[7] = 0.0;
+    }
+}
+
+size_t mix_scratch_bytes(int count) { return sizeof(MixIn) * (size_t)(count > 0 ? count : 1); }
+int mix_max_members() { return kMaxMix; }
+
+hipError_t launch_mix(const MemberDev *const *members_host, const double *lambdas, int count, const ens_hist_desc &h,
+                      double c, double Z, int mode, double q_sigma, double *out, void *scratch, hipStream_t s) {
+    if (count <= 0 || count > kMaxMix || !scratch) return hipErrorInvalidValue;
+    const HistGeom hg = make_hist_geom(h);
+    std::vector<MixIn> tmp(count);
+    for (int i = 0; i < count; i++) {
+        tmp[i].counts = members_host[i]->counts;
+        tmp[i].moments = members_host[i]->moments;
+        tmp[i].lambda = lambdas[i];
+        tmp[i].ntot = 0.0; tmp[i].w = 0.0; tmp[i].order = 0; tmp[i].pad = 0;
+    }
+    MixIn *mi = reinterpret_cast<MixIn *>(scratch);
+    hipError_t e = hipMemcpyAsync(mi, tmp.data(), sizeof(MixIn) * count, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(s);       // tmp is freed on return
+    if (e != hipSuccess) return e;
+    k_mix_prep<<<count, 256, 0, s>>>(mi, hg.off_le);
+    k_mix_weights<<<1, 1024, 0, s>>>(mi, count, c, Z, mode, q_sigma, out);
+    MixGeom g;
+    g.qb = hg.qb; g.lb = hg.lb; g.ab = hg.ab; g.count = count;
+    g.off_le = hg.off_le; g.off_lw = hg.off_lw; g.off_al = hg.off_al; g.off_at = hg.off_at;
+    g.area_qr = ((h.q_hi - h.q_lo) / h.qr_bins) * ((h.r_hi - h.r_lo) / h.qr_bins);
+    g.w_l = (h.log10_hi - h.log10_lo) / h.log_bins;
+    g.w_a = (h.a_hi - h.a_lo) / h.a_bins;
+    g.o_qr = count;
+    g.o_le = g.o_qr + (long long)hg.qb * hg.qb;
+    g.o_lw = g.o_le + hg.lb;
+    g.o_al = g.o_lw + hg.lb;
+    g.o_at = g.o_al + hg.ab;
+    g.o_mom = g.o_at + hg.ab;
+    g.o_der = g.o_mom + ENS_NMOM;
+    const long long total = (long long)hg.qb * hg.qb + 2LL * hg.lb + 2LL * hg.ab;
+    k_mix_pdf<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(mi, g, out);
+    k_mix_moments<<<1, 64, 0, s>>>(mi, g, out);
+    return hipGetLastError();
+}
+
+}  // namespace ens

@@ -1,0 +1,233 @@
+"""Python view of the ensemble: members, stepping, statistics and the mixture.
+
+Every computation happens in libensdns (HIP kernels for gfx950); this module
+allocates device memory with torch, passes raw pointers and the current HIP
+stream, and wraps results as tensors / dicts.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from dataclasses import dataclass, field
+
+import torch
+
+from . import _lib
+from ._lib import check, lib
+
+
+@dataclass
+class MemberSpec:
+    """One member: DNS at injection exp(lambda) * eps_ref, fixed band, viscosity nu."""
+    n: int
+    nu: float
+    eps_ref: float = 1.0
+    lam: float = 0.0
+    kf_lo: float = 0.0
+    kf_hi: float = 2.5
+    dt: float = 0.0            # > 0 fixed step, else CFL step
+    cfl: float = 0.5
+    precision: str = "fp64"    # "fp64" or "fp32"
+    box: float = 2 * math.pi
+    seed: int = 23712
+    k_peak: float = 2.0
+    e0: float = 0.5
+    visc_mode: int = 0
+
+    def desc(self) -> _lib.MemberDesc:
+        p = {"fp64": _lib.ENS_FP64, "fp32": _lib.ENS_FP32}[self.precision]
+        return _lib.MemberDesc(self.n, p, self.box, self.nu, self.eps_ref, self.lam, self.kf_lo, self.kf_hi,
+                               self.dt, self.cfl, self.seed, self.k_peak, self.e0, self.visc_mode, 0)
+
+
+@dataclass
+class HistSpec:
+    """Histogram axes, in units of the reference (lambda = 0) member."""
+    qr_bins: int = 64
+    q_lo: float = -30.0
+    q_hi: float = 30.0
+    r_lo: float = -60.0
+    r_hi: float = 60.0
+    log_bins: int = 512
+    log10_lo: float = -8.0
+    log10_hi: float = 5.0
+    a_bins: int = 1024
+    a_lo: float = -100.0
+    a_hi: float = 100.0
+    eps_ref: float = 1.0
+    nu_ref: float = 0.01
+
+    def desc(self) -> _lib.HistDesc:
+        return _lib.HistDesc(self.qr_bins, self.q_lo, self.q_hi, self.r_lo, self.r_hi, self.log_bins,
+                             self.log10_lo, self.log10_hi, self.a_bins, self.a_lo, self.a_hi,
+                             self.eps_ref, self.nu_ref)
+
+    def split(self, counts):
+        """Split a flat counts vector into named histograms (bins, specials)."""
+        q, l, a = self.qr_bins, self.log_bins, self.a_bins
+        out, o = {}, 0
+        for name, nb in (("qr", q * q), ("log_eps", l), ("log_ens", l), ("a_long", a), ("a_trans", a)):
+            out[name] = counts[o:o + nb]
+            out[name + "_special"] = counts[o + nb:o + nb + 3]
+            o += nb + 3
+        out["qr"] = out["qr"].reshape(q, q)
+        return out
+
+
+def _stream_ptr() -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ids(members) -> ctypes.Array:
+    ids = [m.id for m in members]
+    return (ctypes.c_int32 * len(ids))(*ids)
+
+
+class Member:
+    def __init__(self, ens: "Ensemble", spec: MemberSpec, mid: int, workspace: torch.Tensor):
+        self.ens, self.spec, self.id, self.workspace = ens, spec, mid, workspace
+
+    @property
+    def n(self) -> int:
+        return self.spec.n
+
+    def state(self) -> torch.Tensor:
+        """Velocity in the canonical layout: complex128 (3, N, N, N/2+1) on the device."""
+        n = self.spec.n
+        out = torch.empty((3, n, n, n // 2 + 1), dtype=torch.complex128, device=self.ens.device)
+        check(lib().ens_member_get_state(self.ens.ctx, self.id, ctypes.c_void_p(out.data_ptr()), _stream_ptr()))
+        return out
+
+    def set_state(self, uhat: torch.Tensor) -> None:
+        n = self.spec.n
+        u = uhat.to(device=self.ens.device, dtype=torch.complex128).contiguous()
+        if tuple(u.shape) != (3, n, n, n // 2 + 1):
+            raise ValueError(f"state must have shape (3, {n}, {n}, {n // 2 + 1})")
+        check(lib().ens_member_set_state(self.ens.ctx, self.id, ctypes.c_void_p(u.data_ptr()), _stream_ptr()))
+        self._keep = u      # alive until the copy has run on the stream
+        torch.cuda.current_stream().synchronize()
+
+    def diag(self) -> dict:
+        d = _lib.Diag()
+        st = lib().ens_get_diag(self.ens.ctx, self.id, ctypes.byref(d))
+        out = {name: getattr(d, name) for name, _ in _lib.Diag._fields_ if name != "reserved"}
+        if st not in (_lib.ENS_OK, _lib.ENS_E_DIVERGED):
+            check(st)
+        out["diverged"] = st == _lib.ENS_E_DIVERGED
+        return out
+
+    def stats(self):
+        """(counts uint64 tensor, moments float64 tensor, grid points summed)."""
+        n = ctypes.c_size_t()
+        check(lib().ens_stats_len(self.ens.ctx, ctypes.byref(n)))
+        counts = torch.zeros(n.value, dtype=torch.int64)
+        mom = torch.zeros(_lib.ENS_NMOM, dtype=torch.float64)
+        npts = ctypes.c_uint64()
+        check(lib().ens_get_stats(self.ens.ctx, self.id,
+                                  ctypes.cast(counts.data_ptr(), ctypes.POINTER(ctypes.c_uint64)),
+                                  ctypes.cast(mom.data_ptr(), ctypes.POINTER(ctypes.c_double)),
+                                  ctypes.byref(npts)))
+        return counts, mom, npts.value
+
+    def reset_stats(self) -> None:
+        check(lib().ens_reset_stats(self.ens.ctx, self.id, _stream_ptr()))
+
+
+class Ensemble:
+    def __init__(self, hist: HistSpec | None = None, device: int = 0, graphs: bool = True):
+        if not torch.cuda.is_available():
+            raise RuntimeError("a ROCm GPU is required (libensdns has no CPU path)")
+        self.device = torch.device("cuda", device)
+        self.hist = hist
+        L = lib()
+        self.ctx = ctypes.c_void_p()
+        hd = hist.desc() if hist is not None else None
+        with torch.cuda.device(self.device):
+            check(L.ens_create(ctypes.byref(self.ctx), device, ctypes.byref(hd) if hd is not None else None))
+            check(L.ens_set_graphs(self.ctx, 1 if graphs else 0))
+        self.members: list[Member] = []
+
+    # ---------------------------------------------------------------- members
+    def workspace_bytes(self, spec: MemberSpec) -> int:
+        b = ctypes.c_size_t()
+        d = spec.desc()
+        check(lib().ens_member_workspace_bytes(self.ctx, ctypes.byref(d), ctypes.byref(b)))
+        return b.value
+
+    def add_member(self, spec: MemberSpec) -> Member:
+        nbytes = self.workspace_bytes(spec)
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-ws.data_ptr()) % 256
+        d = spec.desc()
+        mid = ctypes.c_int32()
+        check(lib().ens_member_init(self.ctx, ctypes.byref(d), ctypes.c_void_p(ws.data_ptr() + off), nbytes,
+                                    _stream_ptr(), ctypes.byref(mid)))
+        m = Member(self, spec, mid.value, ws)
+        self.members.append(m)
+        return m
+
+    # ----------------------------------------------------------------- stepping
+    def step(self, nsteps: int = 1, members=None) -> None:
+        ms = members if members is not None else self.members
+        check(lib().ens_step(self.ctx, _ids(ms), len(ms), nsteps, _stream_ptr()))
+
+    def profile_step(self, members=None) -> dict:
+        ms = members if members is not None else self.members
+        out = (ctypes.c_double * _lib.ENS_NPASS)()
+        check(lib().ens_profile_step(self.ctx, _ids(ms), len(ms), _stream_ptr(), out))
+        return dict(zip(_lib.PASS_NAMES, list(out)))
+
+    # --------------------------------------------------------------- statistics
+    def accumulate_stats(self, members=None) -> None:
+        ms = members if members is not None else self.members
+        check(lib().ens_accumulate_stats(self.ctx, _ids(ms), len(ms), _stream_ptr()))
+
+    def mix(self, c: float, Z: float, mode: int = 0, q_sigma: float = 1.0, members=None) -> dict:
+        ms = members if members is not None else self.members
+        n = ctypes.c_size_t()
+        check(lib().ens_mix_len(self.ctx, len(ms), ctypes.byref(n)))
+        out = torch.zeros(n.value, dtype=torch.float64, device=self.device)
+        check(lib().ens_mix(self.ctx, _ids(ms), len(ms), c, Z, mode, q_sigma, ctypes.c_void_p(out.data_ptr()),
+                            _stream_ptr()))
+        o = out.cpu()
+        h = self.hist
+        q, l, a, k = h.qr_bins, h.log_bins, h.a_bins, len(ms)
+        res, pos = {}, 0
+        for name, size in (("weights", k), ("qr", q * q), ("log_eps", l), ("log_ens", l), ("a_long", a),
+                           ("a_trans", a), ("moments", _lib.ENS_NMOM), ("derived", 8)):
+            res[name] = o[pos:pos + size]
+            pos += size
+        res["qr"] = res["qr"].reshape(q, q)
+        d = res["derived"]
+        res.update(S_long=float(d[0]), F_long=float(d[1]), H_long=float(d[2]), F_trans=float(d[3]),
+                   H_trans=float(d[4]), mean_eps=float(d[5]), mean_ens=float(d[6]))
+        return res
+
+    def close(self) -> None:
+        if self.ctx:
+            torch.cuda.synchronize(self.device)
+            lib().ens_destroy(self.ctx)
+            self.ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fft_pencils(x: torch.Tensor, sign: int) -> torch.Tensor:
+    """Batched FFT of the columns of a (n, lines) complex device tensor (unnormalised)."""
+    if x.dim() != 2 or not x.is_cuda:
+        raise ValueError("x must be a 2-D device tensor (n, lines)")
+    if x.dtype == torch.complex128:
+        prec = _lib.ENS_FP64
+    elif x.dtype == torch.complex64:
+        prec = _lib.ENS_FP32
+    else:
+        raise ValueError("x must be complex64 or complex128")
+    x = x.contiguous()
+    out = torch.empty_like(x)
+    check(lib().ens_fft_pencils(x.shape[0], prec, sign, x.shape[1], ctypes.c_void_p(x.data_ptr()),
+                                ctypes.c_void_p(out.data_ptr()), _stream_ptr()))
+    return out

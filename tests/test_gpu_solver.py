@@ -1,0 +1,168 @@
+"""Parity of the HIP solver with the CPU oracle (same seeded inputs), and
+invariants at the full 256^3 size."""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TAU = 2 * math.pi
+
+
+def ens_mod():
+    import paper_2506_23712_amd as ens
+    return ens
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def make(n, nu, eps, kf_lo, kf_hi, dt, cfl=0.5, prec="fp64", seed=23712, lam=0.0, visc=0, graphs=True, hist=None):
+    ens = ens_mod()
+    E = ens.Ensemble(hist=hist, graphs=graphs)
+    m = E.add_member(ens.MemberSpec(n=n, nu=nu, eps_ref=eps, lam=lam, kf_lo=kf_lo, kf_hi=kf_hi, dt=dt, cfl=cfl,
+                                    precision=prec, seed=seed, visc_mode=visc))
+    return E, m
+
+
+def oracle_member(n, nu, eps, kf_lo, kf_hi, dt, cfl=0.5, visc=0):
+    import oracle
+    return oracle.Member(n=n, nu=nu, eps=eps, kf_lo=kf_lo, kf_hi=kf_hi, dt=dt, cfl=cfl, visc_mode=visc)
+
+
+@pytest.mark.parametrize("n", [16, 32, 64, 128])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_initial_field_matches_oracle(orc, n, prec):
+    E, m = make(n, 0.02, 0.1, 0, 2, 0.01, prec=prec, seed=1000 + n)
+    got = m.state().cpu().numpy()
+    ref = orc.init_field(n, 1000 + n, k_peak=2.0, e0=0.5)
+    tol = 1e-14 if prec == "fp64" else 1e-7
+    assert rel(got, ref) <= tol
+    E.close()
+
+
+def test_state_roundtrip_and_truncation(orc):
+    import torch
+    n = 32
+    E, m = make(n, 0.02, 0.1, 0, 2, 0.01)
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal((3, n, n, n // 2 + 1)) + 1j * rng.standard_normal((3, n, n, n // 2 + 1))
+    m.set_state(torch.from_numpy(x))
+    got = m.state().cpu().numpy()
+    mask = orc.retained_mask(n)
+    assert np.array_equal(got[:, mask], x[:, mask])
+    assert np.all(got[:, ~mask] == 0)
+    E.close()
+
+
+CASES = {
+    # name: (n, nu, eps, kf_lo, kf_hi, dt, cfl)
+    "c1_32_fixed_dt": (32, 0.02, 0.1, 0.0, 2.0, 0.01, 0.5),
+    "n16_cfl": (16, 0.05, 0.3, 0.0, 2.5, 0.0, 0.5),
+    "n64_cfl_band_paper": (64, 0.01, 1.0, 1.4, 2.3, 0.0, 0.5),
+    "n128_cfl": (128, 0.02964, 1.0, 0.0, 2.5, 0.0, 0.5),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_twenty_steps_match_oracle_fp64(orc, case):
+    n, nu, eps, lo, hi, dt, cfl = CASES[case]
+    steps = 20 if n <= 64 else 6
+    E, m = make(n, nu, eps, lo, hi, dt, cfl, seed=77 + n)
+    E.step(steps)
+    got = m.state().cpu().numpy()
+    d = m.diag()
+    u0 = orc.init_field(n, 77 + n)
+    ref, rd = orc.run(oracle_member(n, nu, eps, lo, hi, dt, cfl), u0, steps)
+    err = rel(got, ref)
+    print(f"{case}: rel L2 after {steps} steps = {err:.3e}")
+    assert err <= 1e-11
+    assert abs(d["t"] - rd[-1, 0]) <= 1e-12 * rd[-1, 0]
+    assert abs(d["E"] - rd[-1, 2]) <= 1e-12 * rd[-1, 2]
+    assert abs(d["D"] - rd[-1, 3]) <= 1e-11 * rd[-1, 3]
+    assert abs(d["dt"] - rd[-1, 1]) <= 1e-12 * rd[-1, 1]
+    assert abs(d["umax"] - rd[-1, 6]) <= 1e-12 * rd[-1, 6]
+    assert abs(d["E_f"] - rd[-1, 5]) <= 1e-12 * rd[-1, 5]
+    assert d["step"] == steps and not d["diverged"]
+    E.close()
+
+
+def test_explicit_viscous_variant_matches_oracle(orc):
+    n, nu, eps = 32, 0.02, 0.1
+    E, m = make(n, nu, eps, 0.0, 2.0, 0.01, visc=1, seed=5)
+    E.step(10)
+    ref, _ = orc.run(oracle_member(n, nu, eps, 0.0, 2.0, 0.01, visc=1), orc.init_field(n, 5), 10)
+    assert rel(m.state().cpu().numpy(), ref) <= 1e-11
+    E.close()
+
+
+@pytest.mark.parametrize("n", [32, 64])
+def test_twenty_steps_fp32_within_bound(orc, n):
+    nu, eps = (0.02, 0.1) if n == 32 else (0.01, 1.0)
+    dt = 0.01 if n == 32 else 0.0
+    E, m = make(n, nu, eps, 0.0, 2.0, dt, prec="fp32", seed=31 + n)
+    E.step(20)
+    ref, _ = orc.run(oracle_member(n, nu, eps, 0.0, 2.0, dt), orc.init_field(n, 31 + n), 20)
+    err = rel(m.state().cpu().numpy(), ref)
+    print(f"fp32 n={n}: rel L2 after 20 steps = {err:.3e}")
+    assert err <= 2e-5
+    E.close()
+
+
+def test_graph_and_direct_launch_agree_bitwise():
+    outs = []
+    for graphs in (True, False):
+        E, m = make(32, 0.02, 0.1, 0.0, 2.0, 0.0, graphs=graphs, seed=9)
+        E.step(7)
+        outs.append(m.state().cpu().numpy())
+        E.close()
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_repeat_runs_are_bitwise_identical():
+    outs = []
+    for _ in range(2):
+        E, m = make(64, 0.01, 1.0, 0.0, 2.5, 0.0, seed=4)
+        E.step(5)
+        outs.append((m.state().cpu().numpy(), m.diag()["E"]))
+        E.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1] == outs[1][1]
+
+
+def test_batched_members_equal_single_runs():
+    ens = ens_mod()
+    specs = [ens.MemberSpec(n=32, nu=0.02, eps_ref=0.1, lam=l, kf_hi=2.0, dt=0.0, cfl=0.5, seed=100 + i)
+             for i, l in enumerate([-1.0, 0.0, 0.7])]
+    specs.append(ens.MemberSpec(n=64, nu=0.02, eps_ref=0.1, lam=0.3, kf_hi=2.0, dt=0.0, cfl=0.5, seed=200,
+                                precision="fp32"))
+    E = ens.Ensemble()
+    ms = [E.add_member(s) for s in specs]
+    E.step(4)
+    batched = [m.state().cpu().numpy() for m in ms]
+    E.close()
+    for s, b in zip(specs, batched):
+        E1 = ens.Ensemble()
+        m1 = E1.add_member(s)
+        E1.step(4)
+        assert np.array_equal(m1.state().cpu().numpy(), b)
+        E1.close()
+
+
+def test_full_size_256_invariants(orc):
+    """256^3 at the benchmark's configuration: properties that hold at any size."""
+    n, nu = 256, 4.594e-3
+    E, m = make(n, nu, 1.0, 0.0, 2.5, 0.0, 0.5, seed=23712)
+    E.step(3)
+    u = m.state().cpu().numpy()
+    d = m.diag()
+    assert orc.divergence_ratio(u) <= 1e-13
+    assert np.all(u[:, ~orc.retained_mask(n)] == 0)
+    assert abs(orc.energy(u) - d["E"]) <= 1e-12 * d["E"]
+    assert abs(orc.dissipation(u, nu) - d["D"]) <= 1e-11 * d["D"]
+    assert abs(d["inj"] - 1.0) <= 1e-14 and abs(d["cfl"] - 0.5) <= 1e-12
+    p = u[:, :, :, 0]
+    mirrored = np.conj(p[:, (-np.arange(n)) % n][:, :, (-np.arange(n)) % n])
+    assert np.max(np.abs(p - mirrored)) <= 1e-13 * np.max(np.abs(p))
+    E.close()

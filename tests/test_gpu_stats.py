@@ -1,0 +1,98 @@
+"""Parity of the gradient statistics and of the ensemble mixture with the oracle."""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+HK = dict(qr_bins=64, q_lo=-30.0, q_hi=30.0, r_lo=-60.0, r_hi=60.0, log_bins=512, log10_lo=-8.0,
+          log10_hi=5.0, a_bins=1024, a_lo=-100.0, a_hi=100.0, eps_ref=0.1, nu_ref=0.02)
+
+
+def counts_close(got, ref, near):
+    """Counts must agree except for points whose bin coordinate sits within
+    rounding of an edge (the oracle counts those)."""
+    diff = int(np.abs(got.astype(np.int64) - ref.astype(np.int64)).sum())
+    assert diff <= 2 * int(near), (diff, int(near))
+
+
+@pytest.mark.parametrize("n,steps,prec", [(32, 20, "fp64"), (64, 5, "fp64"), (16, 3, "fp64")])
+def test_snapshot_statistics_match_oracle(orc, n, steps, prec):
+    import paper_2506_23712_amd as ens
+    E = ens.Ensemble(hist=ens.HistSpec(**HK))
+    spec = ens.MemberSpec(n=n, nu=0.02, eps_ref=0.1, kf_hi=2.0, dt=0.01, seed=3 + n, precision=prec)
+    m = E.add_member(spec)
+    E.step(steps)
+    E.accumulate_stats()
+    counts, mom, npts = m.stats()
+    state = m.state().cpu().numpy()
+    E.close()
+    h = orc.Hist(**HK)
+    om = orc.Member(n=n, nu=0.02, eps=0.1, kf_hi=2.0, dt=0.01)
+    rc, rm, near, _ = orc.stats(om, h, state)           # same field on both sides
+    got = h.split(counts.numpy().astype(np.uint64))
+    ref = h.split(rc)
+    assert npts == n ** 3
+    for k, name in enumerate(("qr", "log_eps", "log_ens", "a_long", "a_trans")):
+        counts_close(np.concatenate([got[name].ravel(), got[name + "_special"]]),
+                     np.concatenate([ref[name].ravel(), ref[name + "_special"]]), near[k])
+    m = mom.numpy()
+    scale = np.abs(rm) + 1e-300
+    for i in range(26):
+        if i in (20, 21):     # <Q>, <R> vanish: compare against the size of <Q^2>, <R^2>
+            s = math.sqrt(rm[24 if i == 20 else 25] * n ** 3)
+            assert abs(m[i] - rm[i]) <= 1e-12 * s, i
+        elif i == 23:         # (Tr A)^2 is pure rounding
+            assert m[i] <= 1e-24 * rm[22] * 1e3 + 1e-20
+        else:
+            assert abs(m[i] - rm[i]) <= 1e-10 * scale[i], (i, m[i], rm[i])
+
+
+def test_statistics_accumulate_and_reset(orc):
+    import paper_2506_23712_amd as ens
+    E = ens.Ensemble(hist=ens.HistSpec(**HK))
+    m = E.add_member(ens.MemberSpec(n=32, nu=0.02, eps_ref=0.1, kf_hi=2.0, dt=0.01, seed=8))
+    E.accumulate_stats()
+    c1, m1, p1 = m.stats()
+    E.accumulate_stats()
+    c2, m2, p2 = m.stats()
+    assert p2 == 2 * p1 and np.array_equal(c2.numpy(), 2 * c1.numpy())
+    assert np.allclose(m2.numpy(), 2 * m1.numpy(), rtol=1e-15, atol=0)
+    m.reset_stats()
+    c3, m3, p3 = m.stats()
+    assert p3 == 0 and not c3.numpy().any() and not m3.numpy().any()
+    E.close()
+
+
+def test_mixture_matches_oracle(orc):
+    import paper_2506_23712_amd as ens
+    from oracle import mixture as mx
+    lams = [0.6, -0.9, 0.0, 1.5, -2.2]
+    hs = ens.HistSpec(**HK)
+    E = ens.Ensemble(hist=hs)
+    ms = [E.add_member(ens.MemberSpec(n=16, nu=0.02, eps_ref=0.1, lam=l, kf_hi=2.0, dt=0.01, seed=50 + i))
+          for i, l in enumerate(lams)]
+    E.step(3)
+    E.accumulate_stats()
+    states = [m.state().cpu().numpy() for m in ms]
+    h = orc.Hist(**HK)
+    per = []
+    for l, s in zip(lams, states):
+        c, mom, near, _ = orc.stats(orc.Member(n=16, nu=0.02, eps=0.1 * math.exp(l), kf_hi=2.0, dt=0.01), h, s)
+        per.append((c, mom))
+    for mode, Z in ((0, math.log(8)), (1, math.log(4)), (0, 0.0), (2, math.log(2))):
+        res = E.mix(0.023, Z, mode=mode, q_sigma=math.sqrt(2))
+        w = mx.weights(lams, 0.023, Z, mode=mode, q_sigma=math.sqrt(2))
+        assert np.allclose(res["weights"].numpy(), w, rtol=1e-13, atol=1e-16)
+        npts = 16 ** 3
+        area = (60 / 64) * (120 / 64)
+        pdfs = [h.split(c)["qr"].ravel() / (npts * area) for c, _ in per]
+        ref = np.array(mx.mix(w, pdfs))
+        assert np.allclose(res["qr"].numpy().ravel(), ref, rtol=1e-12, atol=1e-300)
+        means = [[mom[i] / (npts * (3 if i < 6 else 6 if i < 12 else 1)) for i in range(26)] for _, mom in per]
+        mm = np.array(mx.mix(w, means))
+        assert np.allclose(res["moments"].numpy()[:26], mm, rtol=1e-10, atol=1e-300)
+        assert math.isclose(res["S_long"], mx.skewness(mm[1], mm[2]), rel_tol=1e-10)
+        assert math.isclose(res["F_trans"], mx.flatness(mm[7], mm[9]), rel_tol=1e-10)
+    E.close()
