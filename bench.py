@@ -1,0 +1,212 @@
+#!/usr/bin/env python3
+"""Throughput of the ensemble-DNS hot path on one MI355X.
+
+Metric: grid-point RK steps per second, sum over members of N^3 x RK3 steps
+per wall second (the cost unit N^3 M of the paper's cost-ratio estimate,
+section "Extrapolating to the frontier of current turbulence simulations").
+
+A timed step is one RK3 step of every member of the workload; gradient
+statistics are accumulated every 10th step (as in the workloads' recipe) and
+the Gaussian mixture of all members is formed once at the end, all inside the
+timed region.  Inputs are seeded synthetic fields (E(k) ~ k^4 exp(-2(k/2)^2),
+energy 0.5) resident in HBM before timing starts.
+
+Workloads
+  ens96_mixed_fp32 : 96 members, lambda = linspace(-5, 6, 96), eps = e^lambda,
+                     nu = 0.03395, band |m| <= 2.5, CFL 0.5, grid = smallest of
+                     64/128/256 with K eta(lambda) >= 1.5 (47 x 64^3, 24 x 128^3,
+                     25 x 256^3), FP32 transforms/RHS with FP64 reductions.
+  single256_fp64   : one 256^3 member, nu = 4.594e-3 (k_max eta ~ 1.5),
+                     eps = 1, band |m| <= 2.5, CFL 0.5, FP64.
+The JSON line reports the first as `value` and the second beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def ens96_specs(ens):
+    nu, specs = 0.03395, []
+    lams = [-5.0 + 11.0 * i / 95 for i in range(96)]
+    for i, lam in enumerate(lams):
+        eta = (nu ** 3 / math.exp(lam)) ** 0.25
+        n = next((g for g in (64, 128, 256) if (g // 3) * eta >= 1.5), 256)
+        specs.append(ens.MemberSpec(n=n, nu=nu, eps_ref=1.0, lam=lam, kf_lo=0.0, kf_hi=2.5, dt=0.0, cfl=0.5,
+                                    precision="fp32", seed=23712 + i))
+    return specs
+
+
+def single256_specs(ens):
+    return [ens.MemberSpec(n=256, nu=4.594e-3, eps_ref=1.0, lam=0.0, kf_lo=0.0, kf_hi=2.5, dt=0.0, cfl=0.5,
+                           precision="fp64", seed=23712)]
+
+
+def hist_for(ens, nu):
+    return ens.HistSpec(qr_bins=256, q_lo=-30, q_hi=30, r_lo=-60, r_hi=60, log_bins=512, log10_lo=-8,
+                        log10_hi=5, a_bins=1024, a_lo=-100, a_hi=100, eps_ref=1.0, nu_ref=nu)
+
+
+def pass_bytes(n: int, prec: str) -> dict:
+    """Algorithmic HBM bytes of one launch of each pass for one member: the
+    pass's inputs read once and outputs written once (truncated storage)."""
+    K = n // 3
+    cs = 16 if prec == "fp64" else 8
+    S = (2 * K + 1) ** 2 * (K + 1)
+    zl = n * (2 * K + 1) * (K + 1)          # one field of z-pencils
+    yl = n * n * (K + 1)                    # one field of y-pencils
+    return {
+        "zinv": (3 * S + 5 * zl) * cs,
+        "yinv": (5 * zl + 6 * yl) * cs,
+        "xpass": (6 * yl + 3 * yl) * cs,
+        "yfwd": (3 * yl + 3 * zl) * cs,
+        # stages 2 and 3 read the RK register too; average over the 3 stages
+        "zfwd_update": (3 * zl + 3 * S + 2 * 3 * S / 3 + 6 * S) * cs,
+    }
+
+
+def run_workload(ens, torch, name, specs, steps, warmup, stats_every, hist_nu):
+    E = ens.Ensemble(hist=hist_for(ens, hist_nu), graphs=True)
+    members = [E.add_member(s) for s in specs]
+    torch.cuda.synchronize()
+    for i in range(warmup):
+        E.step(1)
+        if stats_every and (i + 1) % stats_every == 0:
+            E.accumulate_stats()
+    for m in members:
+        m.reset_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        E.step(1)
+        if stats_every and (i + 1) % stats_every == 0:
+            E.accumulate_stats()
+    mix = E.mix(0.023, math.log(8), mode=0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    pts = sum(s.n ** 3 for s in specs)
+    diverged = [m.id for m in members if m.diag()["diverged"]]
+    # per-kernel times with HIP events on the launch stream, per grid size
+    groups = sorted({(s.n, s.precision) for s in specs}, reverse=True)
+    prof = {}
+    for (n, prec) in groups:
+        sel = [m for m in members if m.spec.n == n and m.spec.precision == prec]
+        acc = None
+        reps = 3
+        for _ in range(reps):
+            p = E.profile_step(sel)
+            acc = p if acc is None else {k: acc[k] + p[k] for k in p}
+        prof[(n, prec)] = ({k: v / reps for k, v in acc.items()}, len(sel))
+    E.close()
+    return {"name": name, "seconds": t1 - t0, "points": pts, "rate": pts * steps / (t1 - t0),
+            "ms_per_step": 1e3 * (t1 - t0) / steps, "prof": prof, "diverged": diverged,
+            "mix_weight_sum": float(mix["weights"].sum())}
+
+
+def roofline(res):
+    """Dominant kernel of the workload (largest summed event time per step)."""
+    best = None
+    for (n, prec), (ms, count) in res["prof"].items():
+        by = pass_bytes(n, prec)
+        for k, v in ms.items():
+            if k in by and (best is None or v > best[3]):
+                best = ((n, prec), k, count, v)
+    (n, prec), k, count, ms_step = best
+    launches = 3                                        # one launch per RK stage
+    avg_ms = ms_step / launches
+    bytes_launch = pass_bytes(n, prec)[k] * count
+    gbs = bytes_launch / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": f"k_{k}<{'float' if prec == 'fp32' else 'double'},{n}>", "avg_launch_ms": round(avg_ms, 4),
+            "bytes_per_launch": int(bytes_launch), "members_per_launch": count}
+
+
+def cpu_baseline(specs):
+    """The oracle, as it stands, on one RK3 step of one member of each grid size."""
+    import oracle
+    sizes = sorted({s.n for s in specs})
+    threads = oracle.num_threads()
+    t0 = time.perf_counter()
+    pts = 0
+    for n in sizes:
+        s = next(x for x in specs if x.n == n)
+        u = oracle.init_field(n, s.seed, k_peak=s.k_peak, e0=s.e0)
+        m = oracle.Member(n=n, nu=s.nu, eps=s.eps_ref * math.exp(s.lam), kf_lo=s.kf_lo, kf_hi=s.kf_hi, dt=s.dt,
+                          cfl=s.cfl)
+        oracle.run(m, u, 1)
+        pts += n ** 3
+    dt = time.perf_counter() - t0
+    return {"value": round(pts / dt, 1), "unit": "grid-pt RK steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"one FP64 RK3 step of one member at each of {sizes} (oracle, {threads} OpenMP threads), "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--stats-every", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=["ens96_mixed_fp32", "single256_fp64"], default=None)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (members shard across GPUs by design, "
+              "not implemented here); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2506_23712_amd as ens
+
+    res = {}
+    if args.only in (None, "ens96_mixed_fp32"):
+        res["ens"] = run_workload(ens, torch, "ens96_mixed_fp32", ens96_specs(ens), args.steps, args.warmup,
+                                  args.stats_every, 0.03395)
+    if args.only in (None, "single256_fp64"):
+        res["single"] = run_workload(ens, torch, "single256_fp64", single256_specs(ens), args.steps, args.warmup,
+                                     args.stats_every, 4.594e-3)
+    head = res.get("ens") or res["single"]
+    out = {
+        "metric": "grid-pt RK steps/s (batched FP32 ensemble; FP64 single member beside it)",
+        "value": round(head["rate"], 1),
+        "unit": "grid-pt RK steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if head["name"].endswith("fp32") else "f64",
+        "data": "synthetic (seeded random solenoidal fields)",
+        "config": {"workload": head["name"],
+                   "members": 96 if head["name"].startswith("ens") else 1,
+                   "grid_points_per_step": head["points"], "stats_every": args.stats_every,
+                   "mixture": "c=0.023, Z=ln 8, open end bins"},
+        "roofline": roofline(head),
+    }
+    if "ens" in res and "single" in res:
+        out["fp64_single_256"] = {"value": round(res["single"]["rate"], 1),
+                                  "ms_per_step": round(res["single"]["ms_per_step"], 4),
+                                  "roofline": roofline(res["single"])}
+        out["ratio_fp32_ensemble_vs_fp64_single"] = round(res["ens"]["rate"] / res["single"]["rate"], 3)
+    out["per_pass_ms"] = {f"{n}_{p}": {k: round(v, 4) for k, v in ms.items()}
+                          for (n, p), (ms, c) in head["prof"].items()}
+    out["diverged_members"] = head["diverged"]
+    if not args.no_cpu_baseline:
+        specs = ens96_specs(ens) if head["name"].startswith("ens") else single256_specs(ens)
+        out["cpu_baseline"] = cpu_baseline(specs)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()
