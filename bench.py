@@ -74,10 +74,11 @@ def pass_bytes(n: int, prec: str) -> dict:
     }
 
 
-def run_workload(ens, torch, name, specs, steps, warmup, stats_every, hist_nu):
+def run_workload(ens, torch, name, specs, steps, warmup, stats_every, hist_nu, autotune=True):
     E = ens.Ensemble(hist=hist_for(ens, hist_nu), graphs=True)
     members = [E.add_member(s) for s in specs]
     torch.cuda.synchronize()
+    variants = E.autotune() if autotune else {}
     for i in range(warmup):
         E.step(1)
         if stats_every and (i + 1) % stats_every == 0:
@@ -106,10 +107,17 @@ def run_workload(ens, torch, name, specs, steps, warmup, stats_every, hist_nu):
             p = E.profile_step(sel)
             acc = p if acc is None else {k: acc[k] + p[k] for k in p}
         prof[(n, prec)] = ({k: v / reps for k, v in acc.items()}, len(sel))
+    # one statistics snapshot of the whole workload, HIP events on the launch stream
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    E.accumulate_stats()
+    ev1.record()
+    torch.cuda.synchronize()
+    stats_ms = ev0.elapsed_time(ev1)
     E.close()
-    return {"name": name, "seconds": t1 - t0, "points": pts, "rate": pts * steps / (t1 - t0),
+    return {"name": name, "seconds": t1 - t0, "points": pts, "rate": pts * steps / (t1 - t0), "variants": variants,
             "ms_per_step": 1e3 * (t1 - t0) / steps, "prof": prof, "diverged": diverged,
-            "mix_weight_sum": float(mix["weights"].sum())}
+            "mix_weight_sum": float(mix["weights"].sum()), "stats_snapshot_ms": stats_ms}
 
 
 def roofline(res):
@@ -158,6 +166,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--stats-every", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--only", choices=["ens96_mixed_fp32", "single256_fp64"], default=None)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -170,10 +179,10 @@ def main():
     res = {}
     if args.only in (None, "ens96_mixed_fp32"):
         res["ens"] = run_workload(ens, torch, "ens96_mixed_fp32", ens96_specs(ens), args.steps, args.warmup,
-                                  args.stats_every, 0.03395)
+                                  args.stats_every, 0.03395, not args.no_autotune)
     if args.only in (None, "single256_fp64"):
         res["single"] = run_workload(ens, torch, "single256_fp64", single256_specs(ens), args.steps, args.warmup,
-                                     args.stats_every, 4.594e-3)
+                                     args.stats_every, 4.594e-3, not args.no_autotune)
     head = res.get("ens") or res["single"]
     out = {
         "metric": "grid-pt RK steps/s (batched FP32 ensemble; FP64 single member beside it)",
@@ -202,6 +211,8 @@ def main():
     out["per_pass_ms"] = {f"{n}_{p}": {k: round(v, 4) for k, v in ms.items()}
                           for (n, p), (ms, c) in head["prof"].items()}
     out["diverged_members"] = head["diverged"]
+    out["stats_snapshot_ms"] = {r["name"]: round(r["stats_snapshot_ms"], 3) for r in res.values()}
+    out["kernel_variants"] = {k: v for r in res.values() for k, v in r["variants"].items()}
     if not args.no_cpu_baseline:
         specs = ens96_specs(ens) if head["name"].startswith("ens") else single256_specs(ens)
         out["cpu_baseline"] = cpu_baseline(specs)

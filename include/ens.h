@@ -172,8 +172,24 @@ ens_status ens_step(ens_ctx *ctx, const int32_t *members, int32_t count, int32_t
 ens_status ens_profile_step(ens_ctx *ctx, const int32_t *members, int32_t count, void *stream,
                             double *ms_out);
 
-/* Diagnostics of member m (synchronises `stream`... the context's last stream). */
+/* Diagnostics of member m (synchronises the stream of the member's last call). */
 ens_status ens_get_diag(ens_ctx *ctx, int32_t m, ens_diag *out);
+
+/* ---------------------------------------------------------------- tuning */
+
+/* Time the compiled variants of the transform passes (1 z inverse, 2 y
+ * inverse, 3 x pass, 4 y forward; variant 0 = 8, 1 = 16 complex values per
+ * thread) on the grid sizes and precisions of `members`, and keep the fastest
+ * per (pass, n, precision) for later steps.  Only scratch buffers are written:
+ * member state is unchanged.  `cache_path` (may be NULL) names a text file of
+ * "pass:n:precision variant" lines: entries found there are used without
+ * timing, and the file is rewritten with the full table.  Synchronises. */
+ens_status ens_autotune(ens_ctx *ctx, const int32_t *members, int32_t count, void *stream,
+                        const char *cache_path);
+
+/* Force / query the variant of one (pass, n, precision).  Invalidates graphs. */
+ens_status ens_set_variant(ens_ctx *ctx, int32_t pass, int32_t n, int32_t precision, int32_t variant);
+ens_status ens_get_variant(const ens_ctx *ctx, int32_t pass, int32_t n, int32_t precision, int32_t *variant);
 
 /* --------------------------------------------------------------- statistics */
 

@@ -6,6 +6,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <sstream>
+#include <tuple>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -153,6 +156,7 @@ struct ens_ctx {
     std::vector<void *> dev_allocs;   // library-owned small device tables
     void *mix_scratch = nullptr;      // member table of ens_mix (library-owned)
     size_t mix_scratch_bytes = 0;
+    std::map<std::tuple<int, int, int>, int> variant;   // (pass, n, precision) -> kernel variant
 };
 
 namespace {
@@ -239,7 +243,12 @@ struct Prof {
     std::vector<int> pass;
 };
 
-hipError_t enqueue_step(const Plan &pl, hipStream_t s, Prof *prof) {
+int variant_of(const ens_ctx *ctx, int pass, int n, int prec) {
+    auto it = ctx->variant.find(std::make_tuple(pass, n, prec));
+    return it != ctx->variant.end() ? it->second : default_variant(pass, n, prec);
+}
+
+hipError_t enqueue_step(const ens_ctx *ctx, const Plan &pl, hipStream_t s, Prof *prof) {
     hipError_t e = hipSuccess;
     auto rec = [&](int pass, auto &&fn) -> hipError_t {
         if (prof) {
@@ -261,17 +270,15 @@ hipError_t enqueue_step(const Plan &pl, hipStream_t s, Prof *prof) {
     for (int stage = 0; stage < 3; stage++) {
         for (const Group &g : pl.groups) {
             const int cnt = (int)g.ids.size();
-            if ((e = rec(P_BAND, [&] { return launch_band_energy(g.n, g.prec, g.dev, cnt, stage, s); }))) return e;
-            if ((e = rec(P_ZINV, [&] { return launch_zinv(g.n, g.prec, g.dev, cnt, g.tw, s); }))) return e;
-            if ((e = rec(P_YINV, [&] { return launch_yinv(g.n, g.prec, g.dev, cnt, 6, g.tw, s); }))) return e;
-            if ((e = rec(P_XPASS, [&] { return launch_xpass(g.n, g.prec, g.dev, cnt, stage, g.tw, s); }))) return e;
-            if ((e = rec(P_YFWD, [&] { return launch_yfwd(g.n, g.prec, g.dev, cnt, g.tw, s); }))) return e;
-            if ((e = rec(P_ZFWD, [&] { return launch_zfwd_update(g.n, g.prec, g.dev, cnt, stage, g.tw, s); }))) return e;
+            for (int pass = P_BAND; pass <= P_ZFWD; pass++) {
+                const int v = variant_of(ctx, pass, g.n, g.prec);
+                if ((e = rec(pass, [&] { return launch_pass(pass, v, g.n, g.prec, g.dev, cnt, stage, g.tw, s); }))) return e;
+            }
         }
     }
     for (const Group &g : pl.groups) {
         const int cnt = (int)g.ids.size();
-        if ((e = rec(P_END, [&] { return launch_end_step(g.n, g.prec, g.dev, cnt, s); }))) return e;
+        if ((e = rec(P_END, [&] { return launch_pass(P_END, 0, g.n, g.prec, g.dev, cnt, 0, g.tw, s); }))) return e;
     }
     return hipSuccess;
 }
@@ -441,7 +448,7 @@ ENS_API ens_status ens_step(ens_ctx *ctx, const int32_t *members, int32_t count,
     if (ctx->graphs) {
         if (!pl->exec) {
             HIPCK(ctx, hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
-            hipError_t e = enqueue_step(*pl, ctx->cap, nullptr);
+            hipError_t e = enqueue_step(ctx, *pl, ctx->cap, nullptr);
             hipGraph_t g = nullptr;
             hipError_t e2 = hipStreamEndCapture(ctx->cap, &g);
             HIPCK(ctx, e);
@@ -451,7 +458,7 @@ ENS_API ens_status ens_step(ens_ctx *ctx, const int32_t *members, int32_t count,
         }
         for (int i = 0; i < nsteps; i++) HIPCK(ctx, hipGraphLaunch(pl->exec, s));
     } else {
-        for (int i = 0; i < nsteps; i++) HIPCK(ctx, enqueue_step(*pl, s, nullptr));
+        for (int i = 0; i < nsteps; i++) HIPCK(ctx, enqueue_step(ctx, *pl, s, nullptr));
     }
     for (int id : ids) ctx->members[id]->last = s;
     return ENS_OK;
@@ -467,7 +474,7 @@ ENS_API ens_status ens_profile_step(ens_ctx *ctx, const int32_t *members, int32_
     if (ens_status st = make_plan(ctx, ids, &pl)) return st;
     hipStream_t s = (hipStream_t)stream;
     Prof prof;
-    hipError_t e = enqueue_step(*pl, s, &prof);
+    hipError_t e = enqueue_step(ctx, *pl, s, &prof);
     hipError_t e2 = hipStreamSynchronize(s);
     for (int p = 0; p < ENS_NPASS; p++) ms_out[p] = 0.0;
     for (size_t i = 0; i < prof.pass.size(); i++) {
@@ -611,5 +618,109 @@ ENS_API ens_status ens_fft_pencils(int32_t n, int32_t precision, int32_t sign, i
     if (e != hipSuccess) return fail(ENS_E_HIP, hipGetErrorString(e));
     e = launch_fft_pencils(n, precision, sign, lines, dev_in, dev_out, tw, (hipStream_t)stream);
     if (e != hipSuccess) return fail(ENS_E_HIP, hipGetErrorString(e));
+    return ENS_OK;
+}
+
+namespace {
+
+const char *pass_name(int p) {
+    static const char *names[ENS_NPASS] = {"band", "zinv", "yinv", "xpass", "yfwd", "zfwd_update", "end_step"};
+    return (p >= 0 && p < ENS_NPASS) ? names[p] : "?";
+}
+
+std::string variant_key(int pass, int n, int prec) {
+    return std::string(pass_name(pass)) + ":" + std::to_string(n) + ":" + (prec == ENS_FP32 ? "fp32" : "fp64");
+}
+
+// cache file: one "key variant" pair per line, '#' comments
+void read_cache(const char *path, std::map<std::string, int> &out) {
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        if (line.empty() || line[0] == '#') continue;
+        std::istringstream is(line);
+        std::string key;
+        int v;
+        if (is >> key >> v) out[key] = v;
+    }
+}
+
+void drop_graphs(ens_ctx *ctx) {
+    for (auto &kv : ctx->plans) {
+        if (kv.second->exec) (void)hipGraphExecDestroy(kv.second->exec);
+        if (kv.second->graph) (void)hipGraphDestroy(kv.second->graph);
+        kv.second->exec = nullptr;
+        kv.second->graph = nullptr;
+    }
+}
+
+}  // namespace
+
+ENS_API ens_status ens_set_variant(ens_ctx *ctx, int32_t pass, int32_t n, int32_t precision, int32_t variant) {
+    if (ens_status st = check_ctx(ctx)) return st;
+    if (pass < 0 || pass >= ENS_NPASS || variant < 0 || variant >= pass_variants(pass))
+        return fail(ENS_E_INVALID, "bad pass or variant");
+    if (!pow2_supported(n) || (precision != ENS_FP32 && precision != ENS_FP64)) return fail(ENS_E_INVALID, "bad n or precision");
+    ctx->variant[std::make_tuple(pass, n, precision)] = variant;
+    drop_graphs(ctx);
+    return ENS_OK;
+}
+
+ENS_API ens_status ens_get_variant(const ens_ctx *ctx, int32_t pass, int32_t n, int32_t precision, int32_t *variant) {
+    if (ens_status st = check_ctx(ctx)) return st;
+    if (!variant || pass < 0 || pass >= ENS_NPASS) return fail(ENS_E_INVALID, "bad arguments");
+    *variant = variant_of(ctx, pass, n, precision);
+    return ENS_OK;
+}
+
+ENS_API ens_status ens_autotune(ens_ctx *ctx, const int32_t *members, int32_t count, void *stream, const char *cache_path) {
+    if (ens_status st = check_ctx(ctx)) return st;
+    std::vector<int> ids;
+    if (ens_status st = collect_ids(ctx, members, count, ids)) return st;
+    HIPCK(ctx, hipSetDevice(ctx->device));
+    Plan *pl;
+    if (ens_status st = make_plan(ctx, ids, &pl)) return st;
+    hipStream_t s = (hipStream_t)stream;
+    std::map<std::string, int> cache;
+    if (cache_path) read_cache(cache_path, cache);
+    hipEvent_t a, b;
+    HIPCK(ctx, hipEventCreate(&a));
+    HIPCK(ctx, hipEventCreate(&b));
+    // Only the transform passes are timed: they write nothing but their
+    // scratch buffers, so the members' state is unchanged by tuning.
+    for (const Group &g : pl->groups) {
+        const int cnt = (int)g.ids.size();
+        for (int pass : {P_ZINV, P_YINV, P_XPASS, P_YFWD}) {
+            const std::string key = variant_key(pass, g.n, g.prec);
+            auto hit = cache.find(key);
+            if (hit != cache.end() && hit->second >= 0 && hit->second < pass_variants(pass)) {
+                ctx->variant[std::make_tuple(pass, g.n, g.prec)] = hit->second;
+                continue;
+            }
+            int best = 0;
+            float best_ms = 1e30f;
+            for (int v = 0; v < pass_variants(pass); v++) {
+                for (int w = 0; w < 2; w++) HIPCK(ctx, launch_pass(pass, v, g.n, g.prec, g.dev, cnt, 1, g.tw, s));
+                HIPCK(ctx, hipEventRecord(a, s));
+                const int reps = 5;
+                for (int r = 0; r < reps; r++) HIPCK(ctx, launch_pass(pass, v, g.n, g.prec, g.dev, cnt, 1, g.tw, s));
+                HIPCK(ctx, hipEventRecord(b, s));
+                HIPCK(ctx, hipEventSynchronize(b));
+                float ms = 0.f;
+                HIPCK(ctx, hipEventElapsedTime(&ms, a, b));
+                if (ms < best_ms) { best_ms = ms; best = v; }
+            }
+            ctx->variant[std::make_tuple(pass, g.n, g.prec)] = best;
+            cache[key] = best;
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    drop_graphs(ctx);
+    if (cache_path) {
+        std::ofstream f(cache_path);
+        f << "# libensdns kernel variants (pass:n:precision variant); 0 = 8, 1 = 16 values per thread\n";
+        for (auto &kv : cache) f << kv.first << " " << kv.second << "\n";
+    }
     return ENS_OK;
 }

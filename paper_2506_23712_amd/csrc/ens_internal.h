@@ -83,13 +83,12 @@ enum Pass { P_BAND = 0, P_ZINV = 1, P_YINV = 2, P_XPASS = 3, P_YFWD = 4, P_ZFWD 
 
 // Launchers (defined in the .hip files).  `mem` points to a device array of
 // `count` MemberDev of one size n and precision; grids cover all of them.
-hipError_t launch_band_energy(int n, int prec, const MemberDev *mem, int count, int stage, hipStream_t s);
-hipError_t launch_zinv(int n, int prec, const MemberDev *mem, int count, const void *tw, hipStream_t s);
-hipError_t launch_yinv(int n, int prec, const MemberDev *mem, int count, int nfields, const void *tw, hipStream_t s);
-hipError_t launch_xpass(int n, int prec, const MemberDev *mem, int count, int stage, const void *tw, hipStream_t s);
-hipError_t launch_yfwd(int n, int prec, const MemberDev *mem, int count, const void *tw, hipStream_t s);
-hipError_t launch_zfwd_update(int n, int prec, const MemberDev *mem, int count, int stage, const void *tw, hipStream_t s);
-hipError_t launch_end_step(int n, int prec, const MemberDev *mem, int count, hipStream_t s);
+// `variant` selects a compiled kernel variant (0: 8 values per thread,
+// 1: 16 values per thread) for passes with pass_variants(pass) > 1.
+hipError_t launch_pass(int pass, int variant, int n, int prec, const MemberDev *mem, int count, int stage,
+                       const void *tw, hipStream_t s);
+int pass_variants(int pass);
+int default_variant(int pass, int n, int prec);
 
 hipError_t launch_init_field(int n, int prec, const MemberDev *mem, uint64_t seed, double k_peak, double e0, hipStream_t s);
 hipError_t launch_set_state(int n, int prec, const MemberDev *mem, const double *src, hipStream_t s);

@@ -11,22 +11,15 @@
 //   end    : FP64 reduction of E and D partials, diagnostics, time
 // Pencils of the y/z passes are lines of one (x-mode, other-coordinate) pair;
 // the x-mode index is the fastest in memory, so consecutive lanes of a
-// workgroup read consecutive complex words.
+// workgroup read consecutive complex words.  Every buffer is addressed as a
+// workgroup-uniform base pointer per field plus a 32-bit per-lane offset, and
+// the loads of the next transform are issued before the current one is
+// computed, so that HBM latency overlaps the butterflies.
 #include "ens_internal.h"
 #include "fft.hpp"
+#include "gmem.hpp"
 
 namespace ens {
-
-template <typename P> using L2 = LdsT<P>;
-
-template <typename P> __device__ __forceinline__ Cx<P> ldc(const void *base, long long i) {
-    L2<P> v = reinterpret_cast<const L2<P> *>(base)[i];
-    return {v.x, v.y};
-}
-template <typename P> __device__ __forceinline__ void stc(void *base, long long i, Cx<P> c) {
-    L2<P> v; v.x = c.re; v.y = c.im;
-    reinterpret_cast<L2<P> *>(base)[i] = v;
-}
 
 __device__ __forceinline__ int mode_of(int n, int N) { return n <= N / 2 ? n : n - N; }
 
@@ -46,16 +39,18 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
 }
 
 // ------------------------------------------------------------ pass configs
-template <int N> struct Cfg {
+// E = complex values per thread (a line of N uses N/E threads).  Variants of
+// E are compiled for the pencil passes and the x pass; the host picks one per
+// (pass, N, precision) from its tuning table.
+template <typename P, int N, int E_> struct Cfg {
     static constexpr int K = N / 3;
-    static constexpr long long NZL = (long long)(2 * K + 1) * (K + 1);
-    static constexpr long long S = (long long)(2 * K + 1) * NZL;
-    static constexpr long long NYL = (long long)N * (K + 1);
-    // y/z inverse and y forward: 16 values per thread, 256 threads
-    static constexpr int E16 = 16, M16 = N / 16, T16 = 256 / M16;
-    // x pass and z forward: 8 values per thread
-    static constexpr int E8 = 8, M8 = N / 8, TX = 256 / M8;          // x pass: 256 threads
-    static constexpr int TZ = (512 / M8) < 1 ? 1 : 512 / M8;          // z forward: 512 threads
+    static constexpr int NZL = (2 * K + 1) * (K + 1);           // z-lines
+    static constexpr int S = (2 * K + 1) * NZL;                 // modes per component
+    static constexpr int NYL = N * (K + 1);                     // y-lines
+    static constexpr int E = E_ > N ? N : E_;
+    static constexpr int M = N / E, T = 256 / M;                // pencil / x passes: 256 threads
+    static constexpr int EZ = 8, MZ = N / 8;                    // z forward + update
+    static constexpr int TZ = (512 / MZ) < 1 ? 1 : 512 / MZ;    // 512 threads
 };
 
 // ================================================================== band
@@ -83,7 +78,7 @@ __global__ void __launch_bounds__(256) k_band_energy(const MemberDev *__restrict
         const double w = mx > 0 ? 1.0 : 0.5;
 #pragma unroll
         for (int comp = 0; comp < 3; comp++) {
-            Cx<P> v = ldc<P>(md.uh, comp * S + idx);
+            Cx<P> v = Fld<P>(md.uh, comp * S).ld((uint32_t)idx);
             acc += w * ((double)v.re * (double)v.re + (double)v.im * (double)v.im);
         }
     }
@@ -99,104 +94,122 @@ __global__ void __launch_bounds__(256) k_band_energy(const MemberDev *__restrict
     }
 }
 
+// Loads of one pencil (E values of line L at positions t + M m), truncated:
+// position p holds mode m = p or p - N; only |m| <= K is stored, at index
+// m (m >= 0) or m + 2K + 1, with stride `stride` between stored modes.
+template <typename P, int N, int E>
+__device__ __forceinline__ void load_trunc(Cx<P> *v, const Fld<P> &f, uint32_t base, uint32_t stride, int t, bool valid) {
+    constexpr int K = N / 3, M = N / E;
+#pragma unroll
+    for (int m = 0; m < E; m++) {
+        const int mm = mode_of(t + M * m, N);
+        const bool keep = valid && mm >= -K && mm <= K;
+        const uint32_t im = (uint32_t)(mm >= 0 ? mm : mm + 2 * K + 1);
+        v[m] = keep ? f.ld(base + im * stride) : czero<P>();
+    }
+}
+
 // ================================================================== zinv
 // z-lines L = iy (K+1) + kx of the retained (m_y, m_x) pairs.
 // out (bufA) [5][N (z)][NZL]: U_x, U_y, U_z, W_x = Z^-1[i k_z u_x], W_y = Z^-1[i k_z u_y]
-template <typename P, int N>
+template <typename P, int N, int EV>
 __global__ void __launch_bounds__(256) k_zinv(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw) {
-    using C = Cfg<N>;
-    constexpr int E = C::E16, M = C::M16, T = C::T16, K = C::K;
-    __shared__ L2<P> lds[N * T];
+    using C = Cfg<P, N, EV>;
+    constexpr int E = C::E, M = C::M, T = C::T, NZL = C::NZL;
+    __shared__ LdsT<P> lds[N * T];
     const MemberDev &md = mems[blockIdx.y];
     const int l = threadIdx.x % T, t = threadIdx.x / T;
-    const long long L = (long long)blockIdx.x * T + l;
-    const bool valid = L < C::NZL;
+    const int L = blockIdx.x * T + l;
+    const bool valid = L < NZL;
     const P dk = (P)md.dk;
-    Cx<P> a[E], b[E];
-#pragma unroll
-    for (int c = 0; c < 3; c++) {
-#pragma unroll
-        for (int m = 0; m < E; m++) {
-            const int mz = mode_of(t + M * m, N);
-            const bool keep = valid && mz >= -K && mz <= K;
-            const int iz = mz >= 0 ? mz : mz + 2 * K + 1;
-            a[m] = keep ? ldc<P>(md.uh, c * C::S + iz * C::NZL + L) : czero<P>();
-        }
-        if (c < 2) {
-#pragma unroll
-            for (int m = 0; m < E; m++) b[m] = mul_i(cscale(a[m], dk * (P)mode_of(t + M * m, N)));
-            line_fft<P, N, E, T, +1>(b, lds, l, t, tw);
-            if (valid) {
-#pragma unroll
-                for (int s = 0; s < E; s++)
-                    stc<P>(md.bufA, ((3 + c) * N + Plan<N, E>::out_pos(t, s)) * C::NZL + L, b[s]);
-            }
-        }
-        line_fft<P, N, E, T, +1>(a, lds, l, t, tw);
+    auto kz = [&](int m) { return dk * (P)mode_of(t + M * m, N); };
+    auto store = [&](const Cx<P> *v, int f) {
         if (valid) {
+            const Fld<P> o(md.bufA, (long long)f * N * NZL);
 #pragma unroll
-            for (int s = 0; s < E; s++) stc<P>(md.bufA, (c * N + Plan<N, E>::out_pos(t, s)) * C::NZL + L, a[s]);
+            for (int s = 0; s < E; s++) o.st((uint32_t)Plan<N, E>::out_pos(t, s) * NZL + L, v[s]);
         }
-    }
+    };
+    Cx<P> a[E], b[E], p[E];
+    load_trunc<P, N, E>(a, Fld<P>(md.uh, 0), L, NZL, t, valid);
+    load_trunc<P, N, E>(p, Fld<P>(md.uh, C::S), L, NZL, t, valid);
+#pragma unroll
+    for (int m = 0; m < E; m++) b[m] = mul_i(cscale(a[m], kz(m)));
+    line_fft<P, N, E, T, +1>(b, lds, l, t, tw);
+    store(b, 3);
+    line_fft<P, N, E, T, +1>(a, lds, l, t, tw);
+    store(a, 0);
+#pragma unroll
+    for (int m = 0; m < E; m++) a[m] = p[m];
+    load_trunc<P, N, E>(p, Fld<P>(md.uh, 2 * C::S), L, NZL, t, valid);
+#pragma unroll
+    for (int m = 0; m < E; m++) b[m] = mul_i(cscale(a[m], kz(m)));
+    line_fft<P, N, E, T, +1>(b, lds, l, t, tw);
+    store(b, 4);
+    line_fft<P, N, E, T, +1>(a, lds, l, t, tw);
+    store(a, 1);
+    line_fft<P, N, E, T, +1>(p, lds, l, t, tw);
+    store(p, 2);
 }
 
 // ================================================================== yinv
 // y-lines L = z (K+1) + kx.  in bufA [5][N][NZL]; out bufB [6][N (z)][N (y)][K+1]:
 // u_x, u_y, u_z, omega_x, omega_y, omega_z
-template <typename P, int N>
+template <typename P, int N, int EV>
 __global__ void __launch_bounds__(256) k_yinv(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw) {
-    using C = Cfg<N>;
-    constexpr int E = C::E16, M = C::M16, T = C::T16, K = C::K;
-    __shared__ L2<P> lds[N * T];
+    using C = Cfg<P, N, EV>;
+    constexpr int E = C::E, M = C::M, T = C::T, K = C::K, NZL = C::NZL;
+    __shared__ LdsT<P> lds[N * T];
     const MemberDev &md = mems[blockIdx.y];
     const int l = threadIdx.x % T, t = threadIdx.x / T;
-    const long long L = (long long)blockIdx.x * T + l;
+    const int L = blockIdx.x * T + l;
     const bool valid = L < C::NYL;
-    const long long z = valid ? L / (K + 1) : 0;
-    const int kx = valid ? (int)(L % (K + 1)) : 0;
+    const int z = valid ? L / (K + 1) : 0;
+    const int kx = valid ? L % (K + 1) : 0;
     const P dk = (P)md.dk;
     const P kxv = dk * (P)kx;
-    auto in_idx = [&](int f, int iy) -> long long { return (f * N + z) * C::NZL + (long long)iy * (K + 1) + kx; };
-    auto out_idx = [&](int f, int y) -> long long { return ((f * N + z) * N + y) * (long long)(K + 1) + kx; };
+    const uint32_t in_base = (uint32_t)z * NZL + kx;             // + iy (K+1)
+    const uint32_t out_base = (uint32_t)z * N * (K + 1) + kx;    // + y (K+1)
+    auto ky = [&](int m) { return dk * (P)mode_of(t + M * m, N); };
     auto load = [&](Cx<P> *v, int f) {
-#pragma unroll
-        for (int m = 0; m < E; m++) {
-            const int my = mode_of(t + M * m, N);
-            const bool keep = valid && my >= -K && my <= K;
-            v[m] = keep ? ldc<P>(md.bufA, in_idx(f, my >= 0 ? my : my + 2 * K + 1)) : czero<P>();
-        }
+        load_trunc<P, N, E>(v, Fld<P>(md.bufA, (long long)f * N * NZL), in_base, K + 1, t, valid);
     };
     auto store = [&](const Cx<P> *v, int f) {
         if (valid) {
+            const Fld<P> o(md.bufB, (long long)f * N * N * (K + 1));
 #pragma unroll
-            for (int s = 0; s < E; s++) stc<P>(md.bufB, out_idx(f, Plan<N, E>::out_pos(t, s)), v[s]);
+            for (int s = 0; s < E; s++) o.st(out_base + (uint32_t)Plan<N, E>::out_pos(t, s) * (K + 1), v[s]);
         }
     };
-    Cx<P> a[E], b[E];
-    // 1: b = Y^-1[i k_y U_x] (kept), u_x
-    load(a, 0);
+    Cx<P> a[E], b[E], p[E];
+    load(a, 0);                                   // U_x
+    load(p, 1);                                   // prefetch U_y
+    // b = Y^-1[i k_y U_x] = d_y u_x (kept), then u_x
 #pragma unroll
-    for (int m = 0; m < E; m++) b[m] = mul_i(cscale(a[m], dk * (P)mode_of(t + M * m, N)));
+    for (int m = 0; m < E; m++) b[m] = mul_i(cscale(a[m], ky(m)));
     line_fft<P, N, E, T, +1>(b, lds, l, t, tw);
     line_fft<P, N, E, T, +1>(a, lds, l, t, tw);
     store(a, 0);
-    // 2: u_y, omega_z = i k_x u_y - d_y u_x
-    load(a, 1);
+    // u_y and omega_z = i k_x u_y - d_y u_x
+#pragma unroll
+    for (int m = 0; m < E; m++) a[m] = p[m];
+    load(p, 2);                                   // prefetch U_z
     line_fft<P, N, E, T, +1>(a, lds, l, t, tw);
     store(a, 1);
 #pragma unroll
     for (int s = 0; s < E; s++) b[s] = mul_i(cscale(a[s], kxv)) - b[s];
     store(b, 5);
-    // 3: omega_x = Y^-1[i k_y U_z - W_y], omega_y = Y^-1[W_x - i k_x U_z], u_z
-    load(a, 2);
-    load(b, 4);
+    // omega_x = Y^-1[i k_y U_z - W_y], omega_y = Y^-1[W_x - i k_x U_z], u_z
 #pragma unroll
-    for (int m = 0; m < E; m++) b[m] = mul_i(cscale(a[m], dk * (P)mode_of(t + M * m, N))) - b[m];
+    for (int m = 0; m < E; m++) a[m] = p[m];
+    load(b, 4);                                   // W_y
+    load(p, 3);                                   // prefetch W_x
+#pragma unroll
+    for (int m = 0; m < E; m++) b[m] = mul_i(cscale(a[m], ky(m))) - b[m];
     line_fft<P, N, E, T, +1>(b, lds, l, t, tw);
     store(b, 3);
-    load(b, 3);
 #pragma unroll
-    for (int m = 0; m < E; m++) b[m] = b[m] - mul_i(cscale(a[m], kxv));
+    for (int m = 0; m < E; m++) b[m] = p[m] - mul_i(cscale(a[m], kxv));
     line_fft<P, N, E, T, +1>(b, lds, l, t, tw);
     store(b, 4);
     line_fft<P, N, E, T, +1>(a, lds, l, t, tw);
@@ -207,41 +220,48 @@ __global__ void __launch_bounds__(256) k_yinv(const MemberDev *__restrict__ mems
 // Rows R = z N + y.  in bufB [6][N][N][K+1]; out bufA [3][N][N][K+1] = x-transform
 // (unnormalised) of n = u x omega, truncated to m_x <= K.
 // Stage 0 also folds max(|u|+|v|+|w|) into st->umax_bits.
-template <typename P, int N>
+template <typename P, int N, int EV>
 __global__ void __launch_bounds__(256) k_xpass(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw, int stage) {
-    using C = Cfg<N>;
-    constexpr int E = C::E8, M = C::M8, T = C::TX, K = C::K;
-    __shared__ L2<P> lds[N * T];
+    using C = Cfg<P, N, EV>;
+    constexpr int E = C::E, M = C::M, T = C::T, K = C::K;
+    constexpr long long FS = (long long)N * N * (K + 1);      // elements per field
+    __shared__ LdsT<P> lds[N * T];
     __shared__ double redmax[256 / 64];
     const MemberDev &md = mems[blockIdx.y];
     const int l = threadIdx.x % T, t = threadIdx.x / T;
-    const long long R = (long long)blockIdx.x * T + l;
-    const long long plane = (long long)N * N;
-    auto in_idx = [&](int f, int kx) -> long long { return (f * plane + R) * (K + 1) + kx; };
-    P ph[6][E];
-    Cx<P> v[E];
-#pragma unroll
-    for (int pr = 0; pr < 3; pr++) {
-        const int fa = 2 * pr, fb = 2 * pr + 1;
+    const uint32_t R = blockIdx.x * T + l;
+    const uint32_t rb = R * (K + 1);
+    // packed two-for-one spectrum of the pair (fa, fb): C = A + i B, Hermitian fill
+    auto load_pair = [&](Cx<P> *A, Cx<P> *B, int fa) {
+        const Fld<P> fA(md.bufB, fa * FS), fB(md.bufB, (fa + 1) * FS);
 #pragma unroll
         for (int m = 0; m < E; m++) {
             const int n = t + M * m;
-            if (n == 0) {
-                Cx<P> A = ldc<P>(md.bufB, in_idx(fa, 0)), B = ldc<P>(md.bufB, in_idx(fb, 0));
-                v[m] = {A.re, B.re};
-            } else if (n <= K) {
-                Cx<P> A = ldc<P>(md.bufB, in_idx(fa, n)), B = ldc<P>(md.bufB, in_idx(fb, n));
-                v[m] = {A.re - B.im, A.im + B.re};
-            } else if (n >= N - K) {
-                Cx<P> A = ldc<P>(md.bufB, in_idx(fa, N - n)), B = ldc<P>(md.bufB, in_idx(fb, N - n));
-                v[m] = {A.re + B.im, B.re - A.im};
-            } else {
-                v[m] = czero<P>();
-            }
+            const bool lo = n <= K, hi = n >= N - K;
+            const uint32_t kx = lo ? n : N - n;
+            if (lo || hi) { A[m] = fA.ld(rb + kx); B[m] = fB.ld(rb + kx); }
+            else { A[m] = czero<P>(); B[m] = czero<P>(); }
         }
+    };
+    auto pack = [&](Cx<P> *v, const Cx<P> *A, const Cx<P> *B) {
+#pragma unroll
+        for (int m = 0; m < E; m++) {
+            const int n = t + M * m;
+            if (n == 0) v[m] = {A[m].re, B[m].re};
+            else if (n <= K) v[m] = {A[m].re - B[m].im, A[m].im + B[m].re};
+            else v[m] = {A[m].re + B[m].im, B[m].re - A[m].im};    // zero pairs stay zero
+        }
+    };
+    P ph[6][E];
+    Cx<P> v[E], A[E], B[E];
+    load_pair(A, B, 0);
+#pragma unroll
+    for (int pr = 0; pr < 3; pr++) {
+        pack(v, A, B);
+        if (pr < 2) load_pair(A, B, 2 * pr + 2);     // prefetch next pair
         line_fft<P, N, E, T, +1>(v, lds, l, t, tw);
 #pragma unroll
-        for (int s = 0; s < E; s++) { ph[fa][s] = v[s].re; ph[fb][s] = v[s].im; }
+        for (int s = 0; s < E; s++) { ph[2 * pr][s] = v[s].re; ph[2 * pr + 1][s] = v[s].im; }
     }
     // ph: 0 u_x, 1 u_y, 2 u_z, 3 omega_x, 4 omega_y, 5 omega_z
     if (stage == 0) {
@@ -279,6 +299,7 @@ __global__ void __launch_bounds__(256) k_xpass(const MemberDev *__restrict__ mem
         for (int w = 1; w < 256 / 64; w++) dm = redmax[w] > dm ? redmax[w] : dm;
         atomicMax(&md.st->umax_bits, (unsigned long long)__double_as_longlong(dm));
     }
+    const Fld<P> o0(md.bufA, 0), o1(md.bufA, FS), o2(md.bufA, 2 * FS);
 #pragma unroll
     for (int m = 0; m < E; m++) {
         const int k = t + M * m;
@@ -286,44 +307,51 @@ __global__ void __launch_bounds__(256) k_xpass(const MemberDev *__restrict__ mem
             const Cx<P> a = d1[m];
             const Cx<P> b = lds_get<P>(lds, ((N - k) % N) * T + l);
             const P h = P(0.5);
-            Cx<P> nxk = {h * (a.re + b.re), h * (a.im - b.im)};
-            Cx<P> nyk = {h * (a.im + b.im), h * (b.re - a.re)};
-            stc<P>(md.bufA, (0 * plane + R) * (K + 1) + k, nxk);
-            stc<P>(md.bufA, (1 * plane + R) * (K + 1) + k, nyk);
-            stc<P>(md.bufA, (2 * plane + R) * (K + 1) + k, d2[m]);
+            o0.st(rb + k, Cx<P>{h * (a.re + b.re), h * (a.im - b.im)});
+            o1.st(rb + k, Cx<P>{h * (a.im + b.im), h * (b.re - a.re)});
+            o2.st(rb + k, d2[m]);
         }
     }
 }
 
 // ================================================================== yfwd
 // y-lines L = z (K+1) + kx.  in bufA [3][N][N][K+1]; out bufB [3][N (z)][2K+1][K+1]
-template <typename P, int N>
+template <typename P, int N, int EV>
 __global__ void __launch_bounds__(256) k_yfwd(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw) {
-    using C = Cfg<N>;
-    constexpr int E = C::E16, M = C::M16, T = C::T16, K = C::K;
-    __shared__ L2<P> lds[N * T];
+    using C = Cfg<P, N, EV>;
+    constexpr int E = C::E, M = C::M, T = C::T, K = C::K, NZL = C::NZL;
+    constexpr long long FS = (long long)N * N * (K + 1);
+    __shared__ LdsT<P> lds[N * T];
     const MemberDev &md = mems[blockIdx.y];
     const int l = threadIdx.x % T, t = threadIdx.x / T;
-    const long long L = (long long)blockIdx.x * T + l;
+    const int L = blockIdx.x * T + l;
     const bool valid = L < C::NYL;
-    const long long z = valid ? L / (K + 1) : 0;
-    const int kx = valid ? (int)(L % (K + 1)) : 0;
-    Cx<P> a[E];
+    const int z = valid ? L / (K + 1) : 0;
+    const int kx = valid ? L % (K + 1) : 0;
+    const uint32_t in_base = (uint32_t)z * N * (K + 1) + kx;
+    const uint32_t out_base = (uint32_t)z * NZL + kx;
+    auto load = [&](Cx<P> *v, int f) {
+        const Fld<P> in(md.bufA, f * FS);
+#pragma unroll
+        for (int m = 0; m < E; m++) v[m] = valid ? in.ld(in_base + (uint32_t)(t + M * m) * (K + 1)) : czero<P>();
+    };
+    Cx<P> a[E], p[E];
+    load(a, 0);
 #pragma unroll
     for (int f = 0; f < 3; f++) {
-#pragma unroll
-        for (int m = 0; m < E; m++)
-            a[m] = valid ? ldc<P>(md.bufA, ((f * N + z) * N + (t + M * m)) * (long long)(K + 1) + kx) : czero<P>();
+        if (f < 2) load(p, f + 1);
         line_fft<P, N, E, T, -1>(a, lds, l, t, tw);
         if (valid) {
+            const Fld<P> o(md.bufB, (long long)f * N * NZL);
 #pragma unroll
             for (int s = 0; s < E; s++) {
                 const int my = mode_of(Plan<N, E>::out_pos(t, s), N);
-                if (my >= -K && my <= K) {
-                    const int iy = my >= 0 ? my : my + 2 * K + 1;
-                    stc<P>(md.bufB, (f * N + z) * C::NZL + (long long)iy * (K + 1) + kx, a[s]);
-                }
+                if (my >= -K && my <= K) o.st(out_base + (uint32_t)(my >= 0 ? my : my + 2 * K + 1) * (K + 1), a[s]);
             }
+        }
+        if (f < 2) {
+#pragma unroll
+            for (int m = 0; m < E; m++) a[m] = p[m];
         }
     }
 }
@@ -333,27 +361,28 @@ __global__ void __launch_bounds__(256) k_yfwd(const MemberDev *__restrict__ mems
 // |m_z| <= K, normalise by N^-3, project, add band forcing, RK stage update.
 template <typename P, int N>
 __global__ void __launch_bounds__(512) k_zfwd_update(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw, int stage) {
-    using C = Cfg<N>;
-    constexpr int E = C::E8, M = C::M8, T = C::TZ, K = C::K;
+    using C = Cfg<P, N, 8>;
+    constexpr int E = C::EZ, M = C::MZ, T = C::TZ, K = C::K, NZL = C::NZL, S = C::S;
     constexpr int NT = T * M;
-    static_assert(NT * sizeof(double) <= N * T * sizeof(L2<P>), "reduction scratch reuses the FFT LDS");
-    __shared__ L2<P> lds[N * T];
+    static_assert(NT * sizeof(double) <= N * T * sizeof(LdsT<P>), "reduction scratch reuses the FFT LDS");
+    __shared__ LdsT<P> lds[N * T];
     double *red = reinterpret_cast<double *>(lds);
     const MemberDev &md = mems[blockIdx.y];
     const int l = threadIdx.x % T, t = threadIdx.x / T;
-    const long long L = (long long)blockIdx.x * T + l;
-    const bool valid = L < C::NZL;
-    const int iy = valid ? (int)(L / (K + 1)) : 0;
-    const int kx = valid ? (int)(L % (K + 1)) : 0;
+    const int L = blockIdx.x * T + l;
+    const bool valid = L < NZL;
+    const int iy = valid ? L / (K + 1) : 0;
+    const int kx = valid ? L % (K + 1) : 0;
     const int my = iy <= K ? iy : iy - (2 * K + 1);
     Cx<P> a[3][E];
 #pragma unroll
     for (int f = 0; f < 3; f++) {
+        const Fld<P> in(md.bufB, (long long)f * N * NZL);
 #pragma unroll
-        for (int m = 0; m < E; m++)
-            a[f][m] = valid ? ldc<P>(md.bufB, (f * N + (t + M * m)) * C::NZL + L) : czero<P>();
-        line_fft<P, N, E, T, -1>(a[f], lds, l, t, tw);
+        for (int m = 0; m < E; m++) a[f][m] = valid ? in.ld((uint32_t)(t + M * m) * NZL + L) : czero<P>();
     }
+#pragma unroll
+    for (int f = 0; f < 3; f++) line_fft<P, N, E, T, -1>(a[f], lds, l, t, tw);
     // time step of this RK step
     double dt;
     if (md.dt_fixed > 0.0) dt = md.dt_fixed;
@@ -374,6 +403,8 @@ __global__ void __launch_bounds__(512) k_zfwd_update(const MemberDev *__restrict
     const double nh = md.nu * RKH[stage] * dt * md.dk * md.dk;   // exponent per |m|^2
     const P inv_n3 = (P)(1.0 / ((double)N * N * N));
     const P dk = (P)md.dk, nu = (P)md.nu;
+    const Fld<P> U[3] = {Fld<P>(md.uh, 0), Fld<P>(md.uh, S), Fld<P>(md.uh, 2 * S)};
+    const Fld<P> Q[3] = {Fld<P>(md.q, 0), Fld<P>(md.q, S), Fld<P>(md.q, 2 * S)};
     double eacc = 0.0, dacc = 0.0;
     if (valid) {
 #pragma unroll
@@ -381,13 +412,13 @@ __global__ void __launch_bounds__(512) k_zfwd_update(const MemberDev *__restrict
             const int mz = mode_of(Plan<N, E>::out_pos(t, s), N);
             if (mz < -K || mz > K) continue;
             const int iz = mz >= 0 ? mz : mz + 2 * K + 1;
-            const long long idx = (long long)iz * C::NZL + L;
+            const uint32_t idx = (uint32_t)iz * NZL + L;
             const int m2 = kx * kx + my * my + mz * mz;
             const P kxv = dk * (P)kx, kyv = dk * (P)my, kzv = dk * (P)mz;
             const P k2 = kxv * kxv + kyv * kyv + kzv * kzv;
             Cx<P> u[3], g[3];
 #pragma unroll
-            for (int c = 0; c < 3; c++) u[c] = ldc<P>(md.uh, c * C::S + idx);
+            for (int c = 0; c < 3; c++) u[c] = U[c].ld(idx);
             if (m2 == 0) {
                 g[0] = g[1] = g[2] = czero<P>();
             } else {
@@ -407,21 +438,21 @@ __global__ void __launch_bounds__(512) k_zfwd_update(const MemberDev *__restrict
                 for (int c = 0; c < 3; c++) g[c] = g[c] - cscale(u[c], nu * k2);
 #pragma unroll
                 for (int c = 0; c < 3; c++) {
-                    Cx<P> q = stage == 0 ? czero<P>() : ldc<P>(md.q, c * C::S + idx);
+                    Cx<P> q = stage == 0 ? czero<P>() : Q[c].ld(idx);
                     q = cscale(q, As) + cscale(g[c], Pdt);
                     u[c] = u[c] + cscale(q, Bs);
-                    stc<P>(md.q, c * C::S + idx, q);
-                    stc<P>(md.uh, c * C::S + idx, u[c]);
+                    Q[c].st(idx, q);
+                    U[c].st(idx, u[c]);
                 }
             } else {
                 const P es = (P)exp(-nh * (double)m2);
 #pragma unroll
                 for (int c = 0; c < 3; c++) {
-                    Cx<P> q = stage == 0 ? czero<P>() : ldc<P>(md.q, c * C::S + idx);
+                    Cx<P> q = stage == 0 ? czero<P>() : Q[c].ld(idx);
                     q = cscale(cscale(q, As) + cscale(g[c], Pdt), es);
                     u[c] = cscale(u[c], es) + cscale(q, Bs);
-                    stc<P>(md.q, c * C::S + idx, q);
-                    stc<P>(md.uh, c * C::S + idx, u[c]);
+                    Q[c].st(idx, q);
+                    U[c].st(idx, u[c]);
                 }
             }
             if (stage == 2) {
@@ -473,86 +504,68 @@ __global__ void __launch_bounds__(256) k_end_step(const MemberDev *__restrict__ 
 }
 
 // ================================================================== launchers
+template <typename P, int N, int EV>
+static hipError_t run_pencil(int pass, const MemberDev *mem, int count, int stage, const Cx<P> *tw, hipStream_t s) {
+    using C = Cfg<P, N, EV>;
+    switch (pass) {
+    case P_ZINV: k_zinv<P, N, EV><<<dim3((C::NZL + C::T - 1) / C::T, count), 256, 0, s>>>(mem, tw); break;
+    case P_YINV: k_yinv<P, N, EV><<<dim3((C::NYL + C::T - 1) / C::T, count), 256, 0, s>>>(mem, tw); break;
+    case P_XPASS: k_xpass<P, N, EV><<<dim3((unsigned)((long long)N * N / C::T), count), 256, 0, s>>>(mem, tw, stage); break;
+    case P_YFWD: k_yfwd<P, N, EV><<<dim3((C::NYL + C::T - 1) / C::T, count), 256, 0, s>>>(mem, tw); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <typename P, int N>
-static hipError_t run_pass(int pass, const MemberDev *mem, int count, int stage, const void *tw, hipStream_t s) {
-    using C = Cfg<N>;
+static hipError_t run_pass(int pass, int variant, const MemberDev *mem, int count, int stage, const void *tw, hipStream_t s) {
+    using C = Cfg<P, N, 8>;
     const Cx<P> *twp = reinterpret_cast<const Cx<P> *>(tw);
     switch (pass) {
-    case P_ZINV: {
-        dim3 g((unsigned)((C::NZL + C::T16 - 1) / C::T16), count);
-        k_zinv<P, N><<<g, 256, 0, s>>>(mem, twp);
+    case P_ZINV: case P_YINV: case P_XPASS: case P_YFWD:
+        return variant == 1 ? run_pencil<P, N, 16>(pass, mem, count, stage, twp, s)
+                            : run_pencil<P, N, 8>(pass, mem, count, stage, twp, s);
+    case P_ZFWD:
+        k_zfwd_update<P, N><<<dim3((C::NZL + C::TZ - 1) / C::TZ, count), C::TZ * C::MZ, 0, s>>>(mem, twp, stage);
         break;
-    }
-    case P_YINV: {
-        dim3 g((unsigned)((C::NYL + C::T16 - 1) / C::T16), count);
-        k_yinv<P, N><<<g, 256, 0, s>>>(mem, twp);
+    case P_END:
+        k_end_step<N><<<count, 256, 0, s>>>(mem, (C::NZL + C::TZ - 1) / C::TZ);
         break;
-    }
-    case P_XPASS: {
-        dim3 g((unsigned)((long long)N * N / C::TX), count);
-        k_xpass<P, N><<<g, 256, 0, s>>>(mem, twp, stage);
-        break;
-    }
-    case P_YFWD: {
-        dim3 g((unsigned)((C::NYL + C::T16 - 1) / C::T16), count);
-        k_yfwd<P, N><<<g, 256, 0, s>>>(mem, twp);
-        break;
-    }
-    case P_ZFWD: {
-        dim3 g((unsigned)((C::NZL + C::TZ - 1) / C::TZ), count);
-        k_zfwd_update<P, N><<<g, C::TZ * C::M8, 0, s>>>(mem, twp, stage);
-        break;
-    }
-    case P_END: {
-        k_end_step<N><<<count, 256, 0, s>>>(mem, (int)((C::NZL + C::TZ - 1) / C::TZ));
-        break;
-    }
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 template <typename P>
-static hipError_t dispatch_n(int n, int pass, const MemberDev *mem, int count, int stage, const void *tw, hipStream_t s) {
+static hipError_t dispatch_n(int n, int pass, int variant, const MemberDev *mem, int count, int stage, const void *tw, hipStream_t s) {
     switch (n) {
-    case 16: return run_pass<P, 16>(pass, mem, count, stage, tw, s);
-    case 32: return run_pass<P, 32>(pass, mem, count, stage, tw, s);
-    case 64: return run_pass<P, 64>(pass, mem, count, stage, tw, s);
-    case 128: return run_pass<P, 128>(pass, mem, count, stage, tw, s);
-    case 256: return run_pass<P, 256>(pass, mem, count, stage, tw, s);
+    case 16: return run_pass<P, 16>(pass, variant, mem, count, stage, tw, s);
+    case 32: return run_pass<P, 32>(pass, variant, mem, count, stage, tw, s);
+    case 64: return run_pass<P, 64>(pass, variant, mem, count, stage, tw, s);
+    case 128: return run_pass<P, 128>(pass, variant, mem, count, stage, tw, s);
+    case 256: return run_pass<P, 256>(pass, variant, mem, count, stage, tw, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-static hipError_t dispatch(int n, int prec, int pass, const MemberDev *mem, int count, int stage, const void *tw, hipStream_t s) {
-    return prec == ENS_FP32 ? dispatch_n<float>(n, pass, mem, count, stage, tw, s)
-                            : dispatch_n<double>(n, pass, mem, count, stage, tw, s);
+hipError_t launch_pass(int pass, int variant, int n, int prec, const MemberDev *mem, int count, int stage,
+                       const void *tw, hipStream_t s) {
+    if (pass == P_BAND) {
+        if (prec == ENS_FP32) k_band_energy<float><<<count, 256, 0, s>>>(mem, stage);
+        else k_band_energy<double><<<count, 256, 0, s>>>(mem, stage);
+        return hipGetLastError();
+    }
+    return prec == ENS_FP32 ? dispatch_n<float>(n, pass, variant, mem, count, stage, tw, s)
+                            : dispatch_n<double>(n, pass, variant, mem, count, stage, tw, s);
 }
 
-hipError_t launch_band_energy(int n, int prec, const MemberDev *mem, int count, int stage, hipStream_t s) {
+int pass_variants(int pass) { return (pass == P_ZINV || pass == P_YINV || pass == P_XPASS || pass == P_YFWD) ? 2 : 1; }
+
+int default_variant(int pass, int n, int prec) {
     (void)n;
-    if (prec == ENS_FP32) k_band_energy<float><<<count, 256, 0, s>>>(mem, stage);
-    else k_band_energy<double><<<count, 256, 0, s>>>(mem, stage);
-    return hipGetLastError();
-}
-hipError_t launch_zinv(int n, int prec, const MemberDev *mem, int count, const void *tw, hipStream_t s) {
-    return dispatch(n, prec, P_ZINV, mem, count, 0, tw, s);
-}
-hipError_t launch_yinv(int n, int prec, const MemberDev *mem, int count, int nfields, const void *tw, hipStream_t s) {
-    (void)nfields;
-    return dispatch(n, prec, P_YINV, mem, count, 0, tw, s);
-}
-hipError_t launch_xpass(int n, int prec, const MemberDev *mem, int count, int stage, const void *tw, hipStream_t s) {
-    return dispatch(n, prec, P_XPASS, mem, count, stage, tw, s);
-}
-hipError_t launch_yfwd(int n, int prec, const MemberDev *mem, int count, const void *tw, hipStream_t s) {
-    return dispatch(n, prec, P_YFWD, mem, count, 0, tw, s);
-}
-hipError_t launch_zfwd_update(int n, int prec, const MemberDev *mem, int count, int stage, const void *tw, hipStream_t s) {
-    return dispatch(n, prec, P_ZFWD, mem, count, stage, tw, s);
-}
-hipError_t launch_end_step(int n, int prec, const MemberDev *mem, int count, hipStream_t s) {
-    return dispatch(n, prec, P_END, mem, count, 0, nullptr, s);
+    if (pass == P_XPASS) return 0;                              // 8 values per thread
+    if (pass == P_ZINV || pass == P_YINV || pass == P_YFWD) return prec == ENS_FP32 ? 1 : 0;
+    return 0;
 }
 
 long long zfwd_blocks(int n) {

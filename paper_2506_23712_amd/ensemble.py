@@ -177,6 +177,24 @@ class Ensemble:
         check(lib().ens_profile_step(self.ctx, _ids(ms), len(ms), _stream_ptr(), out))
         return dict(zip(_lib.PASS_NAMES, list(out)))
 
+    def autotune(self, members=None, cache_path: str | None = None) -> dict:
+        """Pick the fastest kernel variant per (pass, n, precision); returns the table."""
+        ms = members if members is not None else self.members
+        cp = cache_path.encode() if cache_path else None
+        check(lib().ens_autotune(self.ctx, _ids(ms), len(ms), _stream_ptr(), cp))
+        out = {}
+        for n, prec in sorted({(m.spec.n, m.spec.precision) for m in ms}):
+            p = _lib.ENS_FP32 if prec == "fp32" else _lib.ENS_FP64
+            for pid in (1, 2, 3, 4):
+                v = ctypes.c_int32()
+                check(lib().ens_get_variant(self.ctx, pid, n, p, ctypes.byref(v)))
+                out[f"{_lib.PASS_NAMES[pid]}:{n}:{prec}"] = v.value
+        return out
+
+    def set_variant(self, pass_name: str, n: int, precision: str, variant: int) -> None:
+        p = _lib.ENS_FP32 if precision == "fp32" else _lib.ENS_FP64
+        check(lib().ens_set_variant(self.ctx, _lib.PASS_NAMES.index(pass_name), n, p, variant))
+
     # --------------------------------------------------------------- statistics
     def accumulate_stats(self, members=None) -> None:
         ms = members if members is not None else self.members

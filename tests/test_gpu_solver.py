@@ -166,3 +166,32 @@ def test_full_size_256_invariants(orc):
     mirrored = np.conj(p[:, (-np.arange(n)) % n][:, :, (-np.arange(n)) % n])
     assert np.max(np.abs(p - mirrored)) <= 1e-13 * np.max(np.abs(p))
     E.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_every_kernel_variant_matches_oracle(orc, prec):
+    """Each compiled variant (8 or 16 values per thread) of each transform pass."""
+    n, nu, eps = 64, 0.01, 1.0
+    ref, _ = orc.run(oracle_member(n, nu, eps, 0.0, 2.5, 0.0), orc.init_field(n, 12), 5)
+    tol = 1e-12 if prec == "fp64" else 2e-5
+    for variant in (0, 1):
+        E, m = make(n, nu, eps, 0.0, 2.5, 0.0, prec=prec, seed=12)
+        for p in ("zinv", "yinv", "xpass", "yfwd"):
+            E.set_variant(p, n, prec, variant)
+        E.step(5)
+        err = rel(m.state().cpu().numpy(), ref)
+        print(f"{prec} variant {variant}: rel L2 {err:.3e}")
+        assert err <= tol
+        E.close()
+
+
+def test_autotune_keeps_state_and_writes_cache(tmp_path):
+    E, m = make(32, 0.02, 0.1, 0.0, 2.0, 0.01, seed=3)
+    before = m.state().cpu().numpy()
+    cache = tmp_path / "variants.txt"
+    table = E.autotune(cache_path=str(cache))
+    assert np.array_equal(m.state().cpu().numpy(), before)
+    assert set(table.values()) <= {0, 1} and len(table) == 4
+    text = cache.read_text()
+    assert "zinv:32:fp64" in text
+    E.close()
