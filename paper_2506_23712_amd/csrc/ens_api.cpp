@@ -200,6 +200,7 @@ ens_status validate_hist(const ens_hist_desc *h) {
     if (!(h->q_hi > h->q_lo) || !(h->r_hi > h->r_lo) || !(h->log10_hi > h->log10_lo) || !(h->a_hi > h->a_lo))
         return fail(ENS_E_INVALID, "histogram ranges need hi > lo");
     if (!(h->eps_ref > 0) || !(h->nu_ref > 0)) return fail(ENS_E_INVALID, "eps_ref and nu_ref must be positive");
+    if (!stats_hist_fits(*h)) return fail(ENS_E_UNSUPPORTED, "log_bins + a_bins too large for the statistics kernel");
     return ENS_OK;
 }
 

@@ -115,6 +115,7 @@ int mix_max_members();
 // Number of workgroups that write FP64 partials, per member.
 long long zfwd_blocks(int n);
 long long xstats_blocks(int n);
+bool stats_hist_fits(const ens_hist_desc &h);   // 1-D histograms fit the statistics kernel's LDS
 long long init_blocks(int n);
 
 }  // namespace ens

@@ -10,106 +10,120 @@
 
 #include "ens_internal.h"
 #include "fft.hpp"
+#include "gmem.hpp"
+#include <cmath>
 
 namespace ens {
 
 template <typename P> using L2 = LdsT<P>;
 
-template <typename P> __device__ __forceinline__ Cx<P> ldc(const void *base, long long i) {
-    L2<P> v = reinterpret_cast<const L2<P> *>(base)[i];
-    return {v.x, v.y};
-}
-template <typename P> __device__ __forceinline__ void stc(void *base, long long i, Cx<P> c) {
-    L2<P> v; v.x = c.re; v.y = c.im;
-    reinterpret_cast<L2<P> *>(base)[i] = v;
-}
 __device__ __forceinline__ int mode_of(int n, int N) { return n <= N / 2 ? n : n - N; }
 
-template <int N> struct SCfg {
+template <typename P, int N, int EV> struct SCfg {
     static constexpr int K = N / 3;
-    static constexpr long long NZL = (long long)(2 * K + 1) * (K + 1);
-    static constexpr long long S = (long long)(2 * K + 1) * NZL;
-    static constexpr long long NYL = (long long)N * (K + 1);
-    static constexpr int E16 = 16, M16 = N / 16, T16 = 256 / M16;
-    static constexpr int E8 = 8, M8 = N / 8, TX = 256 / M8;
+    static constexpr int NZL = (2 * K + 1) * (K + 1);
+    static constexpr int S = (2 * K + 1) * NZL;
+    static constexpr int NYL = N * (K + 1);
+    static constexpr int E = EV > N ? N : EV, M = N / E, T = 256 / M;
 };
 
-// ------------------------------------------------------------------ gzinv
-template <typename P, int N>
-__global__ void __launch_bounds__(256) k_gzinv(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw) {
-    using C = SCfg<N>;
-    constexpr int E = C::E16, M = C::M16, T = C::T16, K = C::K;
-    __shared__ L2<P> lds[N * T];
-    const MemberDev &md = mems[blockIdx.y];
-    const int l = threadIdx.x % T, t = threadIdx.x / T;
-    const long long L = (long long)blockIdx.x * T + l;
-    const bool valid = L < C::NZL;
-    const P dk = (P)md.dk;
-    Cx<P> a[E], b[E];
+// values per thread of the gradient pencil passes
+template <typename P> constexpr int grad_e() { return sizeof(P) == 4 ? 16 : 8; }
+
+template <typename P, int N, int E>
+__device__ __forceinline__ void gload_trunc(Cx<P> *v, const Fld<P> &f, uint32_t base, uint32_t stride, int t, bool valid) {
+    constexpr int K = N / 3, M = N / E;
 #pragma unroll
-    for (int c = 0; c < 3; c++) {
-#pragma unroll
-        for (int m = 0; m < E; m++) {
-            const int mz = mode_of(t + M * m, N);
-            const bool keep = valid && mz >= -K && mz <= K;
-            a[m] = keep ? ldc<P>(md.uh, c * C::S + (mz >= 0 ? mz : mz + 2 * K + 1) * C::NZL + L) : czero<P>();
-            b[m] = mul_i(cscale(a[m], dk * (P)mz));
-        }
-        line_fft<P, N, E, T, +1>(b, lds, l, t, tw);
-        line_fft<P, N, E, T, +1>(a, lds, l, t, tw);
-        if (valid) {
-#pragma unroll
-            for (int s = 0; s < E; s++) {
-                const int z = Plan<N, E>::out_pos(t, s);
-                stc<P>(md.bufA, ((3 + c) * N + z) * C::NZL + L, b[s]);
-                stc<P>(md.bufA, (c * N + z) * C::NZL + L, a[s]);
-            }
-        }
+    for (int m = 0; m < E; m++) {
+        const int mm = mode_of(t + M * m, N);
+        const bool keep = valid && mm >= -K && mm <= K;
+        v[m] = keep ? f.ld(base + (uint32_t)(mm >= 0 ? mm : mm + 2 * K + 1) * stride) : czero<P>();
     }
 }
 
-// ------------------------------------------------------------------ gyinv
+// ------------------------------------------------------------------ gzinv
+// out bufA [6][N][NZL]: U_c = Z^-1[u_c] (fields 0..2), W_c = Z^-1[i k_z u_c] (3..5)
 template <typename P, int N>
-__global__ void __launch_bounds__(256) k_gyinv(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw) {
-    using C = SCfg<N>;
-    constexpr int E = C::E16, M = C::M16, T = C::T16, K = C::K;
-    __shared__ L2<P> lds[N * T];
+__global__ void __launch_bounds__(256) k_gzinv(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw) {
+    using C = SCfg<P, N, grad_e<P>()>;
+    constexpr int E = C::E, M = C::M, T = C::T, NZL = C::NZL;
+    __shared__ LdsT<P> lds[N * T];
     const MemberDev &md = mems[blockIdx.y];
     const int l = threadIdx.x % T, t = threadIdx.x / T;
-    const long long L = (long long)blockIdx.x * T + l;
-    const bool valid = L < C::NYL;
-    const long long z = valid ? L / (K + 1) : 0;
-    const int kx = valid ? (int)(L % (K + 1)) : 0;
+    const int L = blockIdx.x * T + l;
+    const bool valid = L < NZL;
     const P dk = (P)md.dk;
-    auto load = [&](Cx<P> *v, int f) {
-#pragma unroll
-        for (int m = 0; m < E; m++) {
-            const int my = mode_of(t + M * m, N);
-            const bool keep = valid && my >= -K && my <= K;
-            v[m] = keep ? ldc<P>(md.bufA, (f * N + z) * C::NZL + (long long)(my >= 0 ? my : my + 2 * K + 1) * (K + 1) + kx)
-                        : czero<P>();
-        }
-    };
     auto store = [&](const Cx<P> *v, int f) {
         if (valid) {
+            const Fld<P> o(md.bufA, (long long)f * N * NZL);
 #pragma unroll
-            for (int s = 0; s < E; s++)
-                stc<P>(md.bufB, ((f * N + z) * N + Plan<N, E>::out_pos(t, s)) * (long long)(K + 1) + kx, v[s]);
+            for (int s = 0; s < E; s++) o.st((uint32_t)Plan<N, E>::out_pos(t, s) * NZL + L, v[s]);
         }
     };
-    Cx<P> a[E], b[E];
+    Cx<P> a[E], b[E], p[E];
+    gload_trunc<P, N, E>(a, Fld<P>(md.uh, 0), L, NZL, t, valid);
 #pragma unroll
     for (int c = 0; c < 3; c++) {
-        load(a, c);
+        if (c < 2) gload_trunc<P, N, E>(p, Fld<P>(md.uh, (long long)(c + 1) * C::S), L, NZL, t, valid);
 #pragma unroll
         for (int m = 0; m < E; m++) b[m] = mul_i(cscale(a[m], dk * (P)mode_of(t + M * m, N)));
         line_fft<P, N, E, T, +1>(b, lds, l, t, tw);
         store(b, 3 + c);
         line_fft<P, N, E, T, +1>(a, lds, l, t, tw);
         store(a, c);
-        load(a, 3 + c);
+        if (c < 2) {
+#pragma unroll
+            for (int m = 0; m < E; m++) a[m] = p[m];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ gyinv
+// out bufB [9][N][N][K+1]: U_c (0..2), V_c = d_y u_c (3..5), W_c = d_z u_c (6..8)
+template <typename P, int N>
+__global__ void __launch_bounds__(256) k_gyinv(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw) {
+    using C = SCfg<P, N, grad_e<P>()>;
+    constexpr int E = C::E, M = C::M, T = C::T, K = C::K, NZL = C::NZL;
+    __shared__ LdsT<P> lds[N * T];
+    const MemberDev &md = mems[blockIdx.y];
+    const int l = threadIdx.x % T, t = threadIdx.x / T;
+    const int L = blockIdx.x * T + l;
+    const bool valid = L < C::NYL;
+    const int z = valid ? L / (K + 1) : 0;
+    const int kx = valid ? L % (K + 1) : 0;
+    const P dk = (P)md.dk;
+    const uint32_t in_base = (uint32_t)z * NZL + kx;
+    const uint32_t out_base = (uint32_t)z * N * (K + 1) + kx;
+    auto load = [&](Cx<P> *v, int f) {
+        gload_trunc<P, N, E>(v, Fld<P>(md.bufA, (long long)f * N * NZL), in_base, K + 1, t, valid);
+    };
+    auto store = [&](const Cx<P> *v, int f) {
+        if (valid) {
+            const Fld<P> o(md.bufB, (long long)f * N * N * (K + 1));
+#pragma unroll
+            for (int s = 0; s < E; s++) o.st(out_base + (uint32_t)Plan<N, E>::out_pos(t, s) * (K + 1), v[s]);
+        }
+    };
+    Cx<P> a[E], b[E], p[E];
+    load(a, 0);
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        load(p, 3 + c);                                        // prefetch W_c
+#pragma unroll
+        for (int m = 0; m < E; m++) b[m] = mul_i(cscale(a[m], dk * (P)mode_of(t + M * m, N)));
+        line_fft<P, N, E, T, +1>(b, lds, l, t, tw);
+        store(b, 3 + c);
+        line_fft<P, N, E, T, +1>(a, lds, l, t, tw);
+        store(a, c);
+#pragma unroll
+        for (int m = 0; m < E; m++) a[m] = p[m];
+        if (c < 2) load(p, c + 1);                             // prefetch U_(c+1)
         line_fft<P, N, E, T, +1>(a, lds, l, t, tw);
         store(a, 6 + c);
+        if (c < 2) {
+#pragma unroll
+            for (int m = 0; m < E; m++) a[m] = p[m];
+        }
     }
 }
 
@@ -119,7 +133,8 @@ struct HistArgs {
     long long off_le, off_lw, off_al, off_at;
     double q_lo, q_scale, r_lo, r_scale, l_lo, l_scale, a_lo, a_scale;
     double tau, inv_trs, inv_trs15, inv_eps_ref, om_scale;
-    int qr_in_lds, d1_in_lds;
+    int win0, win;             // QR bins [win0, win0 + win)^2 are counted in LDS, the rest globally
+    int tiles_per_block;
 };
 
 // -1 under, -2 over, -3 nan, else bin
@@ -132,115 +147,116 @@ __device__ __forceinline__ int bin_of(double x, double lo, double scale, int nb)
 }
 __device__ __forceinline__ int slot_1d(int b, int nb) { return b >= 0 ? b : (b == -1 ? nb : (b == -2 ? nb + 1 : nb + 2)); }
 
+// Persistent x pass of the gradient fields: each workgroup takes row tiles
+// blockIdx.x, blockIdx.x + gridDim.x, ...; per-point values are formed in FP64;
+// 1-D histograms and a central window of the QR histogram are accumulated in
+// LDS (32-bit) and flushed once; moments stay in registers and are reduced
+// in a fixed order to one partial per workgroup.
 template <typename P, int N>
 __global__ void __launch_bounds__(256) k_gxstats(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw, HistArgs h) {
-    using C = SCfg<N>;
-    constexpr int E = C::E8, M = C::M8, T = C::TX, K = C::K;
-    extern __shared__ unsigned int hs[];                    // dynamic: 1-D histograms (+ QR)
-    __shared__ L2<P> lds[N * T];
+    constexpr int E = 4, M = N / E, T = 256 / M, K = N / 3;
+    constexpr long long FS = (long long)N * N * (K + 1);
+    extern __shared__ unsigned int hs[];                    // 1-D histograms, then the QR window
+    __shared__ LdsT<P> lds[N * T];
     __shared__ double red[4][32];
     const MemberDev &md = mems[blockIdx.y];
     const int l = threadIdx.x % T, t = threadIdx.x / T;
-    const long long R = (long long)blockIdx.x * T + l;
-    const long long plane = (long long)N * N;
     const P dk = (P)md.dk;
     const int n1d = 2 * (h.lb + 3) + 2 * (h.ab + 3);
-    const int nqr = h.qr_in_lds ? h.qb * h.qb + 3 : 0;
-    const int nh_lds = (h.d1_in_lds ? n1d : 0) + nqr;
-    for (int i = threadIdx.x; i < nh_lds; i += 256) hs[i] = 0u;
-    // spectral value of gradient field f = 3 c + j at kx
-    auto spec = [&](int f, int kx) -> Cx<P> {
-        const int c = f / 3, j = f % 3;
-        if (j == 0) return mul_i(cscale(ldc<P>(md.bufB, (c * plane + R) * (K + 1) + kx), dk * (P)kx));
-        return ldc<P>(md.bufB, (((j == 1 ? 3 : 6) + c) * plane + R) * (K + 1) + kx);
-    };
-    P g[9][E];
-    Cx<P> v[E];
-#pragma unroll
-    for (int pr = 0; pr < 5; pr++) {
-        const int fa = 2 * pr, fb = 2 * pr + 1;
-#pragma unroll
-        for (int m = 0; m < E; m++) {
-            const int n = t + M * m;
-            Cx<P> A = czero<P>(), B = czero<P>();
-            if (n <= K) { A = spec(fa, n); if (fb < 9) B = spec(fb, n); }
-            else if (n >= N - K) { A = cconj(spec(fa, N - n)); if (fb < 9) B = cconj(spec(fb, N - n)); }
-            if (n == 0) { A.im = P(0); B.im = P(0); }
-            v[m] = {A.re - B.im, A.im + B.re};
-        }
-        line_fft<P, N, E, T, +1>(v, lds, l, t, tw);
-#pragma unroll
-        for (int s = 0; s < E; s++) { g[fa][s] = v[s].re; if (fb < 9) g[fb][s] = v[s].im; }
-    }
-    __syncthreads();   // LDS histograms zeroed before use
+    const int nwin = h.win * h.win;
+    for (int i = threadIdx.x; i < n1d + nwin; i += 256) hs[i] = 0u;
     unsigned int *h_le = hs, *h_lw = hs + (h.lb + 3), *h_al = hs + 2 * (h.lb + 3), *h_at = h_al + (h.ab + 3);
-    unsigned int *h_qr = hs + (h.d1_in_lds ? n1d : 0);
+    unsigned int *h_qr = hs + n1d;
     unsigned long long *G = md.counts;
     double mom[26];
 #pragma unroll
     for (int i = 0; i < 26; i++) mom[i] = 0.0;
     const double nu = md.nu;
+    const int ntiles = N * N / T;
+    __syncthreads();
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint32_t rb = (uint32_t)(tile * T + l) * (K + 1);
+        auto spec = [&](int f, uint32_t kx) -> Cx<P> {
+            const int c = f / 3, j = f % 3;
+            if (j == 0) return mul_i(cscale(Fld<P>(md.bufB, c * FS).ld(rb + kx), dk * (P)kx));
+            return Fld<P>(md.bufB, ((j == 1 ? 3 : 6) + c) * FS).ld(rb + kx);
+        };
+        P g[9][E];
+        Cx<P> v[E];
 #pragma unroll
-    for (int s = 0; s < E; s++) {
-        double a[3][3];
+        for (int pr = 0; pr < 5; pr++) {
+            const int fa = 2 * pr, fb = 2 * pr + 1;
 #pragma unroll
-        for (int i = 0; i < 3; i++)
-#pragma unroll
-            for (int j = 0; j < 3; j++) a[i][j] = (double)g[3 * i + j][s];
-        const double tr = a[0][0] + a[1][1] + a[2][2];
-        double q = 0.0, r = 0.0, ss = 0.0;
-#pragma unroll
-        for (int i = 0; i < 3; i++)
-#pragma unroll
-            for (int j = 0; j < 3; j++) {
-                q += a[i][j] * a[j][i];
-                const double sij = 0.5 * (a[i][j] + a[j][i]);
-                ss += sij * sij;
-#pragma unroll
-                for (int k = 0; k < 3; k++) r += a[i][j] * a[j][k] * a[k][i];
+            for (int m = 0; m < E; m++) {
+                const int n = t + M * m;
+                Cx<P> A = czero<P>(), B = czero<P>();
+                if (n <= K) { A = spec(fa, n); if (fb < 9) B = spec(fb, n); }
+                else if (n >= N - K) { A = cconj(spec(fa, N - n)); if (fb < 9) B = cconj(spec(fb, N - n)); }
+                if (n == 0) { A.im = P(0); B.im = P(0); }
+                v[m] = {A.re - B.im, A.im + B.re};
             }
-        q *= -0.5; r *= -1.0 / 3.0;
-        const double w0 = a[2][1] - a[1][2], w1 = a[0][2] - a[2][0], w2 = a[1][0] - a[0][1];
-        const double ens = w0 * w0 + w1 * w1 + w2 * w2;
-        const double qs = q * h.inv_trs, rs = r * h.inv_trs15;
-        const double es = 2.0 * nu * ss * h.inv_eps_ref, ws = ens * h.om_scale;
-        // QR
-        {
-            int idx;
-            if (qs != qs || rs != rs) idx = h.qb * h.qb + 2;
-            else {
-                const int bq = bin_of(qs, h.q_lo, h.q_scale, h.qb), br = bin_of(rs, h.r_lo, h.r_scale, h.qb);
-                idx = (bq < 0 || br < 0) ? h.qb * h.qb : bq * h.qb + br;
-            }
-            if (h.qr_in_lds) atomicAdd(&h_qr[idx], 1u);
-            else atomicAdd(&G[idx], 1ull);
+            line_fft<P, N, E, T, +1>(v, lds, l, t, tw);
+#pragma unroll
+            for (int s = 0; s < E; s++) { g[fa][s] = v[s].re; if (fb < 9) g[fb][s] = v[s].im; }
         }
-        const int ble = slot_1d(es > 0.0 ? bin_of(log10(es), h.l_lo, h.l_scale, h.lb) : (es != es ? -3 : -1), h.lb);
-        const int blw = slot_1d(ws > 0.0 ? bin_of(log10(ws), h.l_lo, h.l_scale, h.lb) : (ws != ws ? -3 : -1), h.lb);
-        if (h.d1_in_lds) { atomicAdd(&h_le[ble], 1u); atomicAdd(&h_lw[blw], 1u); }
-        else { atomicAdd(&G[h.off_le + ble], 1ull); atomicAdd(&G[h.off_lw + blw], 1ull); }
 #pragma unroll
-        for (int i = 0; i < 3; i++)
+        for (int s = 0; s < E; s++) {
+            double a[3][3];
 #pragma unroll
-            for (int j = 0; j < 3; j++) {
-                const double x = a[i][j] * h.tau;
-                const int b = slot_1d(bin_of(x, h.a_lo, h.a_scale, h.ab), h.ab);
-                if (i == j) {
-                    if (h.d1_in_lds) atomicAdd(&h_al[b], 1u); else atomicAdd(&G[h.off_al + b], 1ull);
-                } else {
-                    if (h.d1_in_lds) atomicAdd(&h_at[b], 1u); else atomicAdd(&G[h.off_at + b], 1ull);
+            for (int i = 0; i < 3; i++)
+#pragma unroll
+                for (int j = 0; j < 3; j++) a[i][j] = (double)g[3 * i + j][s];
+            const double tr = a[0][0] + a[1][1] + a[2][2];
+            double q = 0.0, r = 0.0, ss = 0.0;
+#pragma unroll
+            for (int i = 0; i < 3; i++)
+#pragma unroll
+                for (int j = 0; j < 3; j++) {
+                    q += a[i][j] * a[j][i];
+                    const double sij = 0.5 * (a[i][j] + a[j][i]);
+                    ss += sij * sij;
+#pragma unroll
+                    for (int k = 0; k < 3; k++) r += a[i][j] * a[j][k] * a[k][i];
                 }
-                double xp = 1.0;
-#pragma unroll
-                for (int p = 0; p < 6; p++) { xp *= x; mom[(i == j ? 0 : 6) + p] += xp; }
+            q *= -0.5; r *= -1.0 / 3.0;
+            const double w0 = a[2][1] - a[1][2], w1 = a[0][2] - a[2][0], w2 = a[1][0] - a[0][1];
+            const double ens = w0 * w0 + w1 * w1 + w2 * w2;
+            const double qs = q * h.inv_trs, rs = r * h.inv_trs15;
+            const double es = 2.0 * nu * ss * h.inv_eps_ref, ws = ens * h.om_scale;
+            {   // QR: window in LDS, elsewhere global
+                int gidx = -1, widx = -1;
+                if (qs != qs || rs != rs) gidx = h.qb * h.qb + 2;
+                else {
+                    const int bq = bin_of(qs, h.q_lo, h.q_scale, h.qb), br = bin_of(rs, h.r_lo, h.r_scale, h.qb);
+                    if (bq < 0 || br < 0) gidx = h.qb * h.qb;
+                    else if (bq >= h.win0 && bq < h.win0 + h.win && br >= h.win0 && br < h.win0 + h.win)
+                        widx = (bq - h.win0) * h.win + (br - h.win0);
+                    else gidx = bq * h.qb + br;
+                }
+                if (widx >= 0) atomicAdd(&h_qr[widx], 1u);
+                else atomicAdd(&G[gidx], 1ull);
             }
-        double ep = 1.0, wp = 1.0;
+            atomicAdd(&h_le[slot_1d(es > 0.0 ? bin_of(log10(es), h.l_lo, h.l_scale, h.lb) : (es != es ? -3 : -1), h.lb)], 1u);
+            atomicAdd(&h_lw[slot_1d(ws > 0.0 ? bin_of(log10(ws), h.l_lo, h.l_scale, h.lb) : (ws != ws ? -3 : -1), h.lb)], 1u);
 #pragma unroll
-        for (int p = 0; p < 4; p++) { ep *= es; wp *= ws; mom[12 + p] += ep; mom[16 + p] += wp; }
-        mom[20] += qs; mom[21] += rs;
-        mom[22] += ss * h.tau * h.tau;
-        mom[23] += tr * tr * h.tau * h.tau;
-        mom[24] += qs * qs; mom[25] += rs * rs;
+            for (int i = 0; i < 3; i++)
+#pragma unroll
+                for (int j = 0; j < 3; j++) {
+                    const double x = a[i][j] * h.tau;
+                    const int b = slot_1d(bin_of(x, h.a_lo, h.a_scale, h.ab), h.ab);
+                    atomicAdd(i == j ? &h_al[b] : &h_at[b], 1u);
+                    double xp = 1.0;
+#pragma unroll
+                    for (int p = 0; p < 6; p++) { xp *= x; mom[(i == j ? 0 : 6) + p] += xp; }
+                }
+            double ep = 1.0, wp = 1.0;
+#pragma unroll
+            for (int p = 0; p < 4; p++) { ep *= es; wp *= ws; mom[12 + p] += ep; mom[16 + p] += wp; }
+            mom[20] += qs; mom[21] += rs;
+            mom[22] += ss * h.tau * h.tau;
+            mom[23] += tr * tr * h.tau * h.tau;
+            mom[24] += qs * qs; mom[25] += rs * rs;
+        }
     }
     // deterministic reduction of the moments: wave butterfly, then waves in order
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -252,29 +268,26 @@ __global__ void __launch_bounds__(256) k_gxstats(const MemberDev *__restrict__ m
         if (lane == 0) red[wave][i] = x;
     }
     __syncthreads();
+    const long long pbase = ((long long)blockIdx.x) * 32;
     if (threadIdx.x < 32) {
         double x = 0.0;
         if (threadIdx.x < 26) x = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
-        md.partials[(long long)blockIdx.x * 32 + threadIdx.x] = x;
+        md.partials[pbase + threadIdx.x] = x;
     }
-    // flush LDS histograms
-    if (h.d1_in_lds) {
-        for (int i = threadIdx.x; i < n1d; i += 256) {
-            const unsigned int c = hs[i];
-            if (!c) continue;
-            long long gi;
-            if (i < h.lb + 3) gi = h.off_le + i;
-            else if (i < 2 * (h.lb + 3)) gi = h.off_lw + (i - (h.lb + 3));
-            else if (i < 2 * (h.lb + 3) + h.ab + 3) gi = h.off_al + (i - 2 * (h.lb + 3));
-            else gi = h.off_at + (i - 2 * (h.lb + 3) - (h.ab + 3));
-            atomicAdd(&G[gi], (unsigned long long)c);
+    // flush LDS histograms (non-zero bins only)
+    for (int i = threadIdx.x; i < n1d + nwin; i += 256) {
+        const unsigned int c = hs[i];
+        if (!c) continue;
+        long long gi;
+        if (i < h.lb + 3) gi = h.off_le + i;
+        else if (i < 2 * (h.lb + 3)) gi = h.off_lw + (i - (h.lb + 3));
+        else if (i < 2 * (h.lb + 3) + h.ab + 3) gi = h.off_al + (i - 2 * (h.lb + 3));
+        else if (i < n1d) gi = h.off_at + (i - 2 * (h.lb + 3) - (h.ab + 3));
+        else {
+            const int w = i - n1d;
+            gi = (long long)(h.win0 + w / h.win) * h.qb + (h.win0 + w % h.win);
         }
-    }
-    if (h.qr_in_lds) {
-        for (int i = threadIdx.x; i < nqr; i += 256) {
-            const unsigned int c = h_qr[i];
-            if (c) atomicAdd(&G[i], (unsigned long long)c);
-        }
+        atomicAdd(&G[gi], (unsigned long long)c);
     }
 }
 
@@ -296,15 +309,25 @@ __global__ void __launch_bounds__(256) k_stats_reduce(const MemberDev *__restric
     }
 }
 
+// Workgroups per member of the persistent statistics pass: about 2048 in
+// total over the launch, at most one per row tile.
+static int xstats_grid(int n, int count) {
+    const int tiles = n * n / (256 / (n / 4));
+    int per = (2048 + count - 1) / count;
+    if (per > tiles) per = tiles;
+    if (per > 512) per = 512;
+    return per < 1 ? 1 : per;
+}
+
 // ---------------------------------------------------------------- launchers
 template <typename P, int N>
 static hipError_t stats_pass(int pass, const MemberDev *mem, int count, const ens_hist_desc *hd, const void *tw, hipStream_t s) {
-    using C = SCfg<N>;
+    using C = SCfg<P, N, grad_e<P>()>;
     const Cx<P> *twp = reinterpret_cast<const Cx<P> *>(tw);
     if (pass == 0) {
-        k_gzinv<P, N><<<dim3((unsigned)((C::NZL + C::T16 - 1) / C::T16), count), 256, 0, s>>>(mem, twp);
+        k_gzinv<P, N><<<dim3((C::NZL + C::T - 1) / C::T, count), 256, 0, s>>>(mem, twp);
     } else if (pass == 1) {
-        k_gyinv<P, N><<<dim3((unsigned)((C::NYL + C::T16 - 1) / C::T16), count), 256, 0, s>>>(mem, twp);
+        k_gyinv<P, N><<<dim3((C::NYL + C::T - 1) / C::T, count), 256, 0, s>>>(mem, twp);
     } else if (pass == 2) {
         const ens_hist_desc &d = *hd;
         HistArgs h;
@@ -321,16 +344,21 @@ static hipError_t stats_pass(int pass, const MemberDev *mem, int count, const en
         h.inv_trs15 = 1.0 / pow(trs, 1.5);
         h.inv_eps_ref = 1.0 / d.eps_ref;
         h.om_scale = d.nu_ref / d.eps_ref;
+        // LDS: transform tile + reduction (static) + 1-D histograms + QR window (dynamic) <= 64 KiB
+        constexpr int T = 256 / (N / 4);
+        const size_t stat = (size_t)N * T * sizeof(LdsT<P>) + 4 * 32 * sizeof(double);
         const size_t n1d = 2 * (size_t)(h.lb + 3) + 2 * (size_t)(h.ab + 3);
-        // dynamic LDS budget: static LDS (transform tile + reduction) plus this stays below 64 KiB
-        const size_t budget = 65536 - (size_t)N * C::TX * sizeof(L2<P>) - 4 * 32 * sizeof(double) - 1024;
-        h.d1_in_lds = n1d * 4 <= budget;
-        const size_t left = budget - (h.d1_in_lds ? n1d * 4 : 0);
-        h.qr_in_lds = (size_t)(h.qb * h.qb + 3) * 4 <= left;
-        const size_t dyn = ((h.d1_in_lds ? n1d : 0) + (h.qr_in_lds ? (size_t)h.qb * h.qb + 3 : 0)) * 4;
-        k_gxstats<P, N><<<dim3((unsigned)((long long)N * N / C::TX), count), 256, dyn, s>>>(mem, twp, h);
+        const size_t budget = 65536 - stat - 512;
+        if (n1d * 4 > budget) return hipErrorInvalidValue;      // rejected on the host beforehand
+        int win = (int)std::sqrt((double)((budget - n1d * 4) / 4));
+        if (win > h.qb) win = h.qb;
+        h.win = win;
+        h.win0 = (h.qb - win) / 2;
+        const size_t dyn = (n1d + (size_t)win * win) * 4;
+        const int per = xstats_grid(N, count);
+        k_gxstats<P, N><<<dim3(per, count), 256, dyn, s>>>(mem, twp, h);
     } else {
-        k_stats_reduce<<<count, 256, 0, s>>>(mem, (long long)N * N / C::TX);
+        k_stats_reduce<<<count, 256, 0, s>>>(mem, (long long)xstats_grid(N, count));
     }
     return hipGetLastError();
 }
@@ -363,7 +391,12 @@ hipError_t launch_grad_xstats(int n, int prec, const MemberDev *mem, int count, 
 hipError_t launch_stats_reduce(int n, int prec, const MemberDev *mem, int count, hipStream_t s) {
     return stats_dispatch(n, prec, 3, mem, count, nullptr, nullptr, s);
 }
-long long xstats_blocks(int n) { return (long long)n * n / (256 / (n / 8)); }
+// upper bound of workgroup partials per member (the grid depends on the batch)
+long long xstats_blocks(int n) { return 512; }
+bool stats_hist_fits(const ens_hist_desc &h) {
+    const size_t n1d = 2 * (size_t)(h.log_bins + 3) + 2 * (size_t)(h.a_bins + 3);
+    return n1d * 4 <= 65536 - 16384 - 4 * 32 * 8 - 512 - 4096;
+}
 
 // =================================================================== mixture
 struct MixIn {
