@@ -217,7 +217,8 @@ def main():
     if "ens" in res and "single" in res:
         out["fp64_single_256"] = {"value": round(res["single"]["rate"], 1),
                                   "ms_per_step": round(res["single"]["ms_per_step"], 4),
-                                  "roofline": roofline(res["single"])}
+                                  "roofline": roofline(res["single"]),
+                                  "per_pass_ms": {k: round(v, 4) for k, v in res["single"]["prof"][(256, "fp64")][0].items()}}
         out["ratio_fp32_ensemble_vs_fp64_single"] = round(res["ens"]["rate"] / res["single"]["rate"], 3)
     out["per_pass_ms"] = {f"{n}_{p}": {k: round(v, 4) for k, v in ms.items()}
                           for (n, p), (ms, c) in head["prof"].items()}

@@ -38,4 +38,19 @@ template <typename P> struct Fld {
     }
 };
 
+// XCD-aware workgroup placement.  Workgroups are handed to the 8 XCDs of the
+// chip round-robin by linear id, and each XCD has its own L2.  Neighbouring
+// tiles of a pass share cache lines at their edges, so the linear id is
+// permuted such that XCD x processes one contiguous range of tiles: the
+// neighbours of a tile then run on the same XCD at about the same time and the
+// shared lines are fetched from HBM once.  Returns (tile, member).
+__device__ __forceinline__ void xcd_tile(unsigned &tile, unsigned &member) {
+    const unsigned gx = gridDim.x, G = gridDim.x * gridDim.y;
+    const unsigned g = blockIdx.y * gx + blockIdx.x;
+    const unsigned q = G >> 3, r = G & 7u, x = g & 7u;
+    const unsigned gp = x * q + (x < r ? x : r) + (g >> 3);
+    member = gp / gx;
+    tile = gp - member * gx;
+}
+
 }  // namespace ens

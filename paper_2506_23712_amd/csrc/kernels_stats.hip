@@ -48,9 +48,11 @@ __global__ void __launch_bounds__(256) k_gzinv(const MemberDev *__restrict__ mem
     using C = SCfg<P, N, grad_e<P>()>;
     constexpr int E = C::E, M = C::M, T = C::T, NZL = C::NZL;
     __shared__ LdsT<P> lds[N * T];
-    const MemberDev &md = mems[blockIdx.y];
+    unsigned tile, mem_i;
+    xcd_tile(tile, mem_i);
+    const MemberDev &md = mems[mem_i];
     const int l = threadIdx.x % T, t = threadIdx.x / T;
-    const int L = blockIdx.x * T + l;
+    const int L = tile * T + l;
     const bool valid = L < NZL;
     const P dk = (P)md.dk;
     auto store = [&](const Cx<P> *v, int f) {
@@ -85,9 +87,11 @@ __global__ void __launch_bounds__(256) k_gyinv(const MemberDev *__restrict__ mem
     using C = SCfg<P, N, grad_e<P>()>;
     constexpr int E = C::E, M = C::M, T = C::T, K = C::K, NZL = C::NZL;
     __shared__ LdsT<P> lds[N * T];
-    const MemberDev &md = mems[blockIdx.y];
+    unsigned tile, mem_i;
+    xcd_tile(tile, mem_i);
+    const MemberDev &md = mems[mem_i];
     const int l = threadIdx.x % T, t = threadIdx.x / T;
-    const int L = blockIdx.x * T + l;
+    const int L = tile * T + l;
     const bool valid = L < C::NYL;
     const int z = valid ? L / (K + 1) : 0;
     const int kx = valid ? L % (K + 1) : 0;

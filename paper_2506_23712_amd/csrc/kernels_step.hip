@@ -117,9 +117,11 @@ __global__ void __launch_bounds__(256) k_zinv(const MemberDev *__restrict__ mems
     using C = Cfg<P, N, EV>;
     constexpr int E = C::E, M = C::M, T = C::T, NZL = C::NZL;
     __shared__ LdsT<P> lds[N * T];
-    const MemberDev &md = mems[blockIdx.y];
+    unsigned tile, mem_i;
+    xcd_tile(tile, mem_i);
+    const MemberDev &md = mems[mem_i];
     const int l = threadIdx.x % T, t = threadIdx.x / T;
-    const int L = blockIdx.x * T + l;
+    const int L = tile * T + l;
     const bool valid = L < NZL;
     const P dk = (P)md.dk;
     auto kz = [&](int m) { return dk * (P)mode_of(t + M * m, N); };
@@ -160,9 +162,11 @@ __global__ void __launch_bounds__(256) k_yinv(const MemberDev *__restrict__ mems
     using C = Cfg<P, N, EV>;
     constexpr int E = C::E, M = C::M, T = C::T, K = C::K, NZL = C::NZL;
     __shared__ LdsT<P> lds[N * T];
-    const MemberDev &md = mems[blockIdx.y];
+    unsigned tile, mem_i;
+    xcd_tile(tile, mem_i);
+    const MemberDev &md = mems[mem_i];
     const int l = threadIdx.x % T, t = threadIdx.x / T;
-    const int L = blockIdx.x * T + l;
+    const int L = tile * T + l;
     const bool valid = L < C::NYL;
     const int z = valid ? L / (K + 1) : 0;
     const int kx = valid ? L % (K + 1) : 0;
@@ -219,49 +223,76 @@ __global__ void __launch_bounds__(256) k_yinv(const MemberDev *__restrict__ mems
 // ================================================================== xpass
 // Rows R = z N + y.  in bufB [6][N][N][K+1]; out bufA [3][N][N][K+1] = x-transform
 // (unnormalised) of n = u x omega, truncated to m_x <= K.
-// Stage 0 also folds max(|u|+|v|+|w|) into st->umax_bits.
+// The T rows of a workgroup are contiguous in every field, so inputs are
+// copied into LDS (and outputs out of it) with linear, fully coalesced
+// accesses; the next field pair is fetched into registers while the current
+// pair is transformed.  Stage 0 also folds max(|u|+|v|+|w|) into st->umax_bits.
 template <typename P, int N, int EV>
 __global__ void __launch_bounds__(256) k_xpass(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw, int stage) {
     using C = Cfg<P, N, EV>;
     constexpr int E = C::E, M = C::M, T = C::T, K = C::K;
     constexpr long long FS = (long long)N * N * (K + 1);      // elements per field
+    constexpr int RW = T * (K + 1);                            // elements of the tile per field
+    constexpr int PER = (RW + 255) / 256;                      // staged elements per thread per field
     __shared__ LdsT<P> lds[N * T];
+    __shared__ LdsT<P> sb[2 * RW];                             // staged pair / two output fields
     __shared__ double redmax[256 / 64];
-    const MemberDev &md = mems[blockIdx.y];
+    unsigned tile, mem_i;
+    xcd_tile(tile, mem_i);
+    const MemberDev &md = mems[mem_i];
     const int l = threadIdx.x % T, t = threadIdx.x / T;
-    const uint32_t R = blockIdx.x * T + l;
-    const uint32_t rb = R * (K + 1);
-    // packed two-for-one spectrum of the pair (fa, fb): C = A + i B, Hermitian fill
-    auto load_pair = [&](Cx<P> *A, Cx<P> *B, int fa) {
-        const Fld<P> fA(md.bufB, fa * FS), fB(md.bufB, (fa + 1) * FS);
+    const uint32_t tb = tile * RW;                             // first element of the tile in a field
+    Cx<P> st[2][PER];
+    auto fetch = [&](int fa) {                                 // global -> registers, linear
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const Fld<P> f(md.bufB, (fa + h) * FS);
+#pragma unroll
+            for (int i = 0; i < PER; i++) {
+                const int e = threadIdx.x + 256 * i;
+                st[h][i] = e < RW ? f.ld(tb + e) : czero<P>();
+            }
+        }
+    };
+    auto park = [&]() {                                        // registers -> LDS
+#pragma unroll
+        for (int h = 0; h < 2; h++)
+#pragma unroll
+            for (int i = 0; i < PER; i++) {
+                const int e = threadIdx.x + 256 * i;
+                if (e < RW) lds_put<P>(sb, h * RW + e, st[h][i]);
+            }
+    };
+    // packed two-for-one spectrum of the staged pair: C = A + i B, Hermitian fill
+    auto gather = [&](Cx<P> *v) {
 #pragma unroll
         for (int m = 0; m < E; m++) {
             const int n = t + M * m;
             const bool lo = n <= K, hi = n >= N - K;
-            const uint32_t kx = lo ? n : N - n;
-            if (lo || hi) { A[m] = fA.ld(rb + kx); B[m] = fB.ld(rb + kx); }
-            else { A[m] = czero<P>(); B[m] = czero<P>(); }
-        }
-    };
-    auto pack = [&](Cx<P> *v, const Cx<P> *A, const Cx<P> *B) {
-#pragma unroll
-        for (int m = 0; m < E; m++) {
-            const int n = t + M * m;
-            if (n == 0) v[m] = {A[m].re, B[m].re};
-            else if (n <= K) v[m] = {A[m].re - B[m].im, A[m].im + B[m].re};
-            else v[m] = {A[m].re + B[m].im, B[m].re - A[m].im};    // zero pairs stay zero
+            const int kx = lo ? n : N - n;
+            Cx<P> A = czero<P>(), B = czero<P>();
+            if (lo || hi) { A = lds_get<P>(sb, l * (K + 1) + kx); B = lds_get<P>(sb, RW + l * (K + 1) + kx); }
+            if (n == 0) v[m] = {A.re, B.re};
+            else if (lo) v[m] = {A.re - B.im, A.im + B.re};
+            else v[m] = {A.re + B.im, B.re - A.im};            // zero pairs stay zero
         }
     };
     P ph[6][E];
-    Cx<P> v[E], A[E], B[E];
-    load_pair(A, B, 0);
+    Cx<P> v[E];
+    fetch(0);
+    park();
 #pragma unroll
     for (int pr = 0; pr < 3; pr++) {
-        pack(v, A, B);
-        if (pr < 2) load_pair(A, B, 2 * pr + 2);     // prefetch next pair
+        __syncthreads();                                       // staged pair visible
+        gather(v);
+        if (pr < 2) fetch(2 * pr + 2);                         // next pair in flight during the transform
         line_fft<P, N, E, T, +1>(v, lds, l, t, tw);
 #pragma unroll
         for (int s = 0; s < E; s++) { ph[2 * pr][s] = v[s].re; ph[2 * pr + 1][s] = v[s].im; }
+        if (pr < 2) {
+            __syncthreads();                                   // every thread has gathered
+            park();
+        }
     }
     // ph: 0 u_x, 1 u_y, 2 u_z, 3 omega_x, 4 omega_y, 5 omega_z
     if (stage == 0) {
@@ -299,7 +330,9 @@ __global__ void __launch_bounds__(256) k_xpass(const MemberDev *__restrict__ mem
         for (int w = 1; w < 256 / 64; w++) dm = redmax[w] > dm ? redmax[w] : dm;
         atomicMax(&md.st->umax_bits, (unsigned long long)__double_as_longlong(dm));
     }
-    const Fld<P> o0(md.bufA, 0), o1(md.bufA, FS), o2(md.bufA, 2 * FS);
+    // split D1 into the x-spectra of n_x and n_y; stage all three in LDS:
+    // n_x, n_y -> sb (free since the last gather), n_z -> lds rows after D1 reads
+    Cx<P> ox[E], oy[E];
 #pragma unroll
     for (int m = 0; m < E; m++) {
         const int k = t + M * m;
@@ -307,9 +340,29 @@ __global__ void __launch_bounds__(256) k_xpass(const MemberDev *__restrict__ mem
             const Cx<P> a = d1[m];
             const Cx<P> b = lds_get<P>(lds, ((N - k) % N) * T + l);
             const P h = P(0.5);
-            o0.st(rb + k, Cx<P>{h * (a.re + b.re), h * (a.im - b.im)});
-            o1.st(rb + k, Cx<P>{h * (a.im + b.im), h * (b.re - a.re)});
-            o2.st(rb + k, d2[m]);
+            ox[m] = {h * (a.re + b.re), h * (a.im - b.im)};
+            oy[m] = {h * (a.im + b.im), h * (b.re - a.re)};
+        }
+    }
+    __syncthreads();                                           // D1 partner reads done
+#pragma unroll
+    for (int m = 0; m < E; m++) {
+        const int k = t + M * m;
+        if (k <= K) {
+            lds_put<P>(sb, l * (K + 1) + k, ox[m]);
+            lds_put<P>(sb, RW + l * (K + 1) + k, oy[m]);
+            lds_put<P>(lds, l * (K + 1) + k, d2[m]);
+        }
+    }
+    __syncthreads();
+    const Fld<P> o0(md.bufA, 0), o1(md.bufA, FS), o2(md.bufA, 2 * FS);
+#pragma unroll
+    for (int i = 0; i < PER; i++) {
+        const int e = threadIdx.x + 256 * i;
+        if (e < RW) {
+            o0.st(tb + e, lds_get<P>(sb, e));
+            o1.st(tb + e, lds_get<P>(sb, RW + e));
+            o2.st(tb + e, lds_get<P>(lds, e));
         }
     }
 }
@@ -322,9 +375,11 @@ __global__ void __launch_bounds__(256) k_yfwd(const MemberDev *__restrict__ mems
     constexpr int E = C::E, M = C::M, T = C::T, K = C::K, NZL = C::NZL;
     constexpr long long FS = (long long)N * N * (K + 1);
     __shared__ LdsT<P> lds[N * T];
-    const MemberDev &md = mems[blockIdx.y];
+    unsigned tile, mem_i;
+    xcd_tile(tile, mem_i);
+    const MemberDev &md = mems[mem_i];
     const int l = threadIdx.x % T, t = threadIdx.x / T;
-    const int L = blockIdx.x * T + l;
+    const int L = tile * T + l;
     const bool valid = L < C::NYL;
     const int z = valid ? L / (K + 1) : 0;
     const int kx = valid ? L % (K + 1) : 0;
@@ -367,9 +422,11 @@ __global__ void __launch_bounds__(512) k_zfwd_update(const MemberDev *__restrict
     static_assert(NT * sizeof(double) <= N * T * sizeof(LdsT<P>), "reduction scratch reuses the FFT LDS");
     __shared__ LdsT<P> lds[N * T];
     double *red = reinterpret_cast<double *>(lds);
-    const MemberDev &md = mems[blockIdx.y];
+    unsigned tile, mem_i;
+    xcd_tile(tile, mem_i);
+    const MemberDev &md = mems[mem_i];
     const int l = threadIdx.x % T, t = threadIdx.x / T;
-    const int L = blockIdx.x * T + l;
+    const int L = tile * T + l;
     const bool valid = L < NZL;
     const int iy = valid ? L / (K + 1) : 0;
     const int kx = valid ? L % (K + 1) : 0;
@@ -390,7 +447,7 @@ __global__ void __launch_bounds__(512) k_zfwd_update(const MemberDev *__restrict
         const double um = __longlong_as_double((long long)md.st->umax_bits);
         dt = um > 0.0 ? md.cfl * (md.box / N) / um : 0.0;
     } else dt = md.st->dt;
-    if (stage == 0 && blockIdx.x == 0 && threadIdx.x == 0) {
+    if (stage == 0 && tile == 0 && threadIdx.x == 0) {
         md.st->dt = dt;
         if (!(dt > 0.0)) md.st->diag.flags |= 4;
     }
@@ -470,8 +527,8 @@ __global__ void __launch_bounds__(512) k_zfwd_update(const MemberDev *__restrict
         const double es = block_sum<NT>(eacc, red);
         const double ds = block_sum<NT>(dacc, red);
         if (threadIdx.x == 0) {
-            md.partials[2 * blockIdx.x] = es;
-            md.partials[2 * blockIdx.x + 1] = ds;
+            md.partials[2 * tile] = es;
+            md.partials[2 * tile + 1] = ds;
         }
     }
 }
