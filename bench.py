@@ -120,6 +120,22 @@ def run_workload(ens, torch, name, specs, steps, warmup, stats_every, hist_nu, a
             "mix_weight_sum": float(mix["weights"].sum()), "stats_snapshot_ms": stats_ms}
 
 
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary of
+    this workload, if it was taken on the current kernel sources; else None."""
+    from paper_2506_23712_amd import profiling
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    t = json.load(open(path))
+    if t.get("source_hash") != profiling.source_hash():
+        return None
+    for name, v in t["kernels"].items():
+        if name.replace(" ", "").startswith(kernel.replace(" ", "")):
+            return v["bytes_per_launch"]
+    return None
+
+
 def roofline(res):
     """Dominant kernel of the workload (largest summed event time per step)."""
     best = None
@@ -133,9 +149,11 @@ def roofline(res):
     avg_ms = ms_step / launches
     bytes_launch = pass_bytes(n, prec)[k] * count
     gbs = bytes_launch / (avg_ms * 1e-3) / 1e9
+    v = res["variants"].get(f"{k}:{n}:{prec}")
+    pname = f"ens::k_{k}<{'float' if prec == 'fp32' else 'double'}, {n}" + (f", {8 if v == 0 else 16}>" if v is not None else "")
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": f"k_{k}<{'float' if prec == 'fp32' else 'double'},{n}>", "avg_launch_ms": round(avg_ms, 4),
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(res["name"], pname),
+            "kernel": pname.replace("ens::", ""), "avg_launch_ms": round(avg_ms, 4),
             "bytes_per_launch": int(bytes_launch), "members_per_launch": count}
 
 

@@ -1,0 +1,128 @@
+"""Summaries of rocprofv3 output for the libensdns kernels.
+
+* ``stats``: per-kernel calls / total / average duration from a
+  ``rocprofv3 --kernel-trace --stats`` database (rocpd SQLite).
+* ``traffic``: per-launch HBM bytes of each kernel from two ``--pmc`` runs
+  (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch), each scaled by what the same
+  counter reads for a plain device copy of known size.  The result records a
+  hash of the kernel sources, so a later change of the kernels invalidates it.
+
+Command line::
+
+    python -m paper_2506_23712_amd.profiling stats DB_DIR --out FILE.md [--title T] [--command C]
+    python -m paper_2506_23712_amd.profiling traffic --copy-fetch D --copy-write D --copy-bytes B \
+        --fetch D --write D --out FILE.json [--command C]
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import glob
+import hashlib
+import json
+import os
+import re
+import sqlite3
+import statistics
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def source_hash() -> str:
+    """sha256 over the HIP/C++ sources of the library."""
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
+        if p.endswith((".hip", ".hpp", ".h", ".cpp")):
+            with open(p, "rb") as f:
+                h.update(os.path.basename(p).encode())
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _db(path: str) -> sqlite3.Connection:
+    if os.path.isdir(path):
+        found = glob.glob(os.path.join(path, "**", "*.db"), recursive=True)
+        if not found:
+            raise FileNotFoundError(f"no rocpd database under {path}")
+        path = found[0]
+    return sqlite3.connect(path)
+
+
+def short_name(name: str) -> str:
+    n = re.sub(r"\(.*", "", name)
+    return n.replace("void ", "").strip()
+
+
+def kernel_stats(path: str):
+    """[(kernel, calls, total_us, average_us, percent)] sorted by total time."""
+    db = _db(path)
+    rows = db.execute("select name, total_calls, total_duration, average, percentage from top_kernels").fetchall()
+    return [(short_name(r[0]), int(r[1]), float(r[2]), float(r[3]), float(r[4])) for r in rows]
+
+
+def pmc_per_kernel(path: str, counter: str) -> dict:
+    """kernel -> list of per-dispatch counter values."""
+    out = collections.defaultdict(list)
+    for name, val in _db(path).execute("select name, counter_value from pmc_events where counter_name = ?", (counter,)):
+        out[short_name(name)].append(float(val))
+    return dict(out)
+
+
+def copy_factor(path: str, counter: str, true_bytes: int) -> float:
+    """true bytes / counter bytes for the device copy kernel of the calibration run."""
+    vals = [v for k, vs in pmc_per_kernel(path, counter).items() if "copyBuffer" in k or "copy" in k.lower()
+            for v in vs]
+    if not vals:
+        raise ValueError(f"no copy kernel in {path}")
+    return true_bytes / (statistics.median(vals) * 1024.0)
+
+
+def traffic(copy_fetch: str, copy_write: str, copy_bytes: int, fetch: str, write: str) -> dict:
+    ff = copy_factor(copy_fetch, "FETCH_SIZE", copy_bytes)
+    fw = copy_factor(copy_write, "WRITE_SIZE", copy_bytes)
+    f = pmc_per_kernel(fetch, "FETCH_SIZE")
+    w = pmc_per_kernel(write, "WRITE_SIZE")
+    kernels = {}
+    for k in sorted(set(f) | set(w)):
+        fb = statistics.mean(f.get(k, [0.0])) * 1024.0 * ff
+        wb = statistics.mean(w.get(k, [0.0])) * 1024.0 * fw
+        kernels[k] = {"fetch_bytes": round(fb), "write_bytes": round(wb), "bytes_per_launch": round(fb + wb),
+                      "launches": max(len(f.get(k, [])), len(w.get(k, [])))}
+    return {"source_hash": source_hash(), "fetch_factor": round(ff, 4), "write_factor": round(fw, 4),
+            "kernels": kernels}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(prog="python -m paper_2506_23712_amd.profiling")
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("db")
+    s.add_argument("--out", required=True)
+    s.add_argument("--title", default="Kernel statistics")
+    s.add_argument("--command", default="")
+    s.add_argument("--top", type=int, default=25)
+    t = sub.add_parser("traffic")
+    for a in ("--copy-fetch", "--copy-write", "--fetch", "--write", "--out"):
+        t.add_argument(a, required=True)
+    t.add_argument("--copy-bytes", type=int, required=True)
+    t.add_argument("--command", default="")
+    a = ap.parse_args(argv)
+    if a.cmd == "stats":
+        rows = kernel_stats(a.db)[: a.top]
+        with open(a.out, "w") as f:
+            f.write(f"# {a.title}\n\n")
+            if a.command:
+                f.write("Command:\n\n```\n" + a.command + "\n```\n\n")
+            f.write(f"Kernel source hash: `{source_hash()}`. Durations in microseconds.\n\n")
+            f.write("| kernel | calls | total us | average us | % |\n|---|---|---|---|---|\n")
+            for r in rows:
+                f.write(f"| `{r[0]}` | {r[1]} | {r[2]:.0f} | {r[3]:.1f} | {r[4]:.2f} |\n")
+    else:
+        res = traffic(a.copy_fetch, a.copy_write, a.copy_bytes, a.fetch, a.write)
+        res["command"] = a.command
+        with open(a.out, "w") as f:
+            json.dump(res, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()
