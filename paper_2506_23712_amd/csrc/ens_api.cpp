@@ -30,7 +30,7 @@ ens_status fail(ens_status s, const std::string &msg) {
     return s;
 }
 
-bool pow2_supported(int n) { return n == 16 || n == 32 || n == 64 || n == 128 || n == 256; }
+bool pow2_supported(int n) { return n == 16 || n == 32 || n == 64 || n == 128 || n == 256 || n == 512 || n == 1024; }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -108,7 +108,7 @@ Layout member_layout(const ens_member_desc &d, const HistGeom *hg) {
     const size_t a_elems = std::max((size_t)6 * n * g.nzl, (size_t)3 * n * n * (g.K + 1));
     L.off_a = o; o += align256(a_elems * cs);
     L.off_b = o; o += align256((size_t)9 * n * n * (g.K + 1) * cs);
-    const size_t nparts = std::max({(size_t)(2 * zfwd_blocks(d.n)), (size_t)init_blocks(d.n),
+    const size_t nparts = std::max({(size_t)(2 * zfwd_blocks(d.n, d.precision)), (size_t)init_blocks(d.n),
                                     (size_t)(ENS_NMOM * xstats_blocks(d.n))});
     L.off_part = o; o += align256(nparts * sizeof(double));
     const size_t ncounts = hg ? (size_t)hg->n_counts : 0;
@@ -178,8 +178,9 @@ ens_status check_ctx(const ens_ctx *ctx) {
 
 ens_status validate_desc(const ens_member_desc *d) {
     if (!d) return fail(ENS_E_INVALID, "null member descriptor");
-    if (!pow2_supported(d->n)) return fail(ENS_E_UNSUPPORTED, "n must be one of 16, 32, 64, 128, 256");
+    if (!pow2_supported(d->n)) return fail(ENS_E_UNSUPPORTED, "n must be one of 16, 32, 64, 128, 256, 512, 1024");
     if (d->precision != ENS_FP64 && d->precision != ENS_FP32) return fail(ENS_E_INVALID, "precision must be 0 or 1");
+    if (d->n == 1024 && d->precision != ENS_FP32) return fail(ENS_E_UNSUPPORTED, "n = 1024 is supported in FP32 only");
     if (!(d->box > 0) || !std::isfinite(d->box)) return fail(ENS_E_INVALID, "box must be positive");
     if (!(d->nu >= 0) || !std::isfinite(d->nu)) return fail(ENS_E_INVALID, "nu must be >= 0");
     if (!(d->eps_ref >= 0) || !std::isfinite(d->eps_ref)) return fail(ENS_E_INVALID, "eps_ref must be >= 0");
@@ -605,7 +606,7 @@ ENS_API ens_status ens_mix(ens_ctx *ctx, const int32_t *members, int32_t count, 
 
 ENS_API ens_status ens_fft_pencils(int32_t n, int32_t precision, int32_t sign, int64_t lines, const void *dev_in,
                                    void *dev_out, void *stream) {
-    if (!pow2_supported(n)) return fail(ENS_E_UNSUPPORTED, "n must be one of 16, 32, 64, 128, 256");
+    if (!pow2_supported(n)) return fail(ENS_E_UNSUPPORTED, "n must be one of 16, 32, 64, 128, 256, 512, 1024");
     if (precision != ENS_FP64 && precision != ENS_FP32) return fail(ENS_E_INVALID, "bad precision");
     if (sign != 1 && sign != -1) return fail(ENS_E_INVALID, "sign must be +1 or -1");
     if (lines < 0) return fail(ENS_E_INVALID, "lines must be >= 0");

@@ -113,7 +113,7 @@ size_t mix_scratch_bytes(int count);
 int mix_max_members();
 
 // Number of workgroups that write FP64 partials, per member.
-long long zfwd_blocks(int n);
+long long zfwd_blocks(int n, int prec);
 long long xstats_blocks(int n);
 bool stats_hist_fits(const ens_hist_desc &h);   // 1-D histograms fit the statistics kernel's LDS
 long long init_blocks(int n);

@@ -291,6 +291,8 @@ static hipError_t pencils_p(int n, int sign, long long lines, const void *in, vo
     case 64: return pencils_n<P, 64>(sign, lines, in, out, tw, s);
     case 128: return pencils_n<P, 128>(sign, lines, in, out, tw, s);
     case 256: return pencils_n<P, 256>(sign, lines, in, out, tw, s);
+    case 512: return pencils_n<P, 512>(sign, lines, in, out, tw, s);
+    case 1024: return pencils_n<P, 1024>(sign, lines, in, out, tw, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -24,7 +24,11 @@ template <typename P, int N, int EV> struct SCfg {
     static constexpr int NZL = (2 * K + 1) * (K + 1);
     static constexpr int S = (2 * K + 1) * NZL;
     static constexpr int NYL = N * (K + 1);
-    static constexpr int E = EV > N ? N : EV, M = N / E, T = 256 / M;
+    static constexpr int E = EV > N ? N : EV, M = N / E;
+    static constexpr int TL = 128 / (int)sizeof(Cx<P>);       // lines for 128-byte runs
+    static constexpr int MAXT = E >= 16 ? 512 : 1024;
+    static constexpr int T = N <= 256 ? 256 / M : (TL * M <= MAXT ? TL : MAXT / M);
+    static constexpr int NT = T * M;
 };
 
 // values per thread of the gradient pencil passes
@@ -44,7 +48,7 @@ __device__ __forceinline__ void gload_trunc(Cx<P> *v, const Fld<P> &f, uint32_t 
 // ------------------------------------------------------------------ gzinv
 // out bufA [6][N][NZL]: U_c = Z^-1[u_c] (fields 0..2), W_c = Z^-1[i k_z u_c] (3..5)
 template <typename P, int N>
-__global__ void __launch_bounds__(256) k_gzinv(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw) {
+__global__ void __launch_bounds__((SCfg<P, N, grad_e<P>()>::NT)) k_gzinv(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw) {
     using C = SCfg<P, N, grad_e<P>()>;
     constexpr int E = C::E, M = C::M, T = C::T, NZL = C::NZL;
     __shared__ LdsT<P> lds[N * T];
@@ -83,7 +87,7 @@ __global__ void __launch_bounds__(256) k_gzinv(const MemberDev *__restrict__ mem
 // ------------------------------------------------------------------ gyinv
 // out bufB [9][N][N][K+1]: U_c (0..2), V_c = d_y u_c (3..5), W_c = d_z u_c (6..8)
 template <typename P, int N>
-__global__ void __launch_bounds__(256) k_gyinv(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw) {
+__global__ void __launch_bounds__((SCfg<P, N, grad_e<P>()>::NT)) k_gyinv(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw) {
     using C = SCfg<P, N, grad_e<P>()>;
     constexpr int E = C::E, M = C::M, T = C::T, K = C::K, NZL = C::NZL;
     __shared__ LdsT<P> lds[N * T];
@@ -329,9 +333,9 @@ static hipError_t stats_pass(int pass, const MemberDev *mem, int count, const en
     using C = SCfg<P, N, grad_e<P>()>;
     const Cx<P> *twp = reinterpret_cast<const Cx<P> *>(tw);
     if (pass == 0) {
-        k_gzinv<P, N><<<dim3((C::NZL + C::T - 1) / C::T, count), 256, 0, s>>>(mem, twp);
+        k_gzinv<P, N><<<dim3((C::NZL + C::T - 1) / C::T, count), C::NT, 0, s>>>(mem, twp);
     } else if (pass == 1) {
-        k_gyinv<P, N><<<dim3((C::NYL + C::T - 1) / C::T, count), 256, 0, s>>>(mem, twp);
+        k_gyinv<P, N><<<dim3((C::NYL + C::T - 1) / C::T, count), C::NT, 0, s>>>(mem, twp);
     } else if (pass == 2) {
         const ens_hist_desc &d = *hd;
         HistArgs h;
@@ -375,6 +379,10 @@ static hipError_t stats_n(int n, int pass, const MemberDev *mem, int count, cons
     case 64: return stats_pass<P, 64>(pass, mem, count, hd, tw, s);
     case 128: return stats_pass<P, 128>(pass, mem, count, hd, tw, s);
     case 256: return stats_pass<P, 256>(pass, mem, count, hd, tw, s);
+    case 512: return stats_pass<P, 512>(pass, mem, count, hd, tw, s);
+    case 1024:
+        if constexpr (sizeof(P) == 4) return stats_pass<P, 1024>(pass, mem, count, hd, tw, s);
+        else return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
 }

@@ -48,9 +48,21 @@ template <typename P, int N, int E_> struct Cfg {
     static constexpr int S = (2 * K + 1) * NZL;                 // modes per component
     static constexpr int NYL = N * (K + 1);                     // y-lines
     static constexpr int E = E_ > N ? N : E_;
-    static constexpr int M = N / E, T = 256 / M;                // pencil / x passes: 256 threads
-    static constexpr int EZ = 8, MZ = N / 8;                    // z forward + update
-    static constexpr int TZ = (512 / MZ) < 1 ? 1 : 512 / MZ;    // 512 threads
+    static constexpr int M = N / E;
+    // Lines per workgroup of the y/z pencil passes: 256 threads up to N = 256;
+    // for longer lines, enough lines for 128-byte runs per position (16 FP32 /
+    // 8 FP64), at most 1024 threads (512 with 16 values per thread, so that a
+    // wave may use 256 VGPRs); gfx950 gives a workgroup up to 160 KiB of LDS.
+    static constexpr int TL = 128 / (int)sizeof(Cx<P>);
+    static constexpr int MAXT = E >= 16 ? 512 : 1024;             // 16 values/thread: keep 256 VGPRs available
+    static constexpr int T = N <= 256 ? 256 / M : (TL * M <= MAXT ? TL : MAXT / M);
+    static constexpr int NT = T * M;
+    static constexpr int TX = 256 / M;                          // x pass: 256 threads
+    // z forward + update: 8 values per thread, 512 threads up to N = 256;
+    // 16 values per thread and the pencil rule above for longer lines
+    static constexpr int EZ = N <= 256 ? 8 : 16, MZ = N / EZ;
+    static constexpr int TZ = N <= 256 ? ((512 / MZ) < 1 ? 1 : 512 / MZ) : (TL * MZ <= 512 ? TL : 512 / MZ);
+    static constexpr int NTZ = TZ * MZ;
 };
 
 // ================================================================== band
@@ -113,7 +125,7 @@ __device__ __forceinline__ void load_trunc(Cx<P> *v, const Fld<P> &f, uint32_t b
 // z-lines L = iy (K+1) + kx of the retained (m_y, m_x) pairs.
 // out (bufA) [5][N (z)][NZL]: U_x, U_y, U_z, W_x = Z^-1[i k_z u_x], W_y = Z^-1[i k_z u_y]
 template <typename P, int N, int EV>
-__global__ void __launch_bounds__(256) k_zinv(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw) {
+__global__ void __launch_bounds__((Cfg<P, N, EV>::NT)) k_zinv(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw) {
     using C = Cfg<P, N, EV>;
     constexpr int E = C::E, M = C::M, T = C::T, NZL = C::NZL;
     __shared__ LdsT<P> lds[N * T];
@@ -158,7 +170,7 @@ __global__ void __launch_bounds__(256) k_zinv(const MemberDev *__restrict__ mems
 // y-lines L = z (K+1) + kx.  in bufA [5][N][NZL]; out bufB [6][N (z)][N (y)][K+1]:
 // u_x, u_y, u_z, omega_x, omega_y, omega_z
 template <typename P, int N, int EV>
-__global__ void __launch_bounds__(256) k_yinv(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw) {
+__global__ void __launch_bounds__((Cfg<P, N, EV>::NT)) k_yinv(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw) {
     using C = Cfg<P, N, EV>;
     constexpr int E = C::E, M = C::M, T = C::T, K = C::K, NZL = C::NZL;
     __shared__ LdsT<P> lds[N * T];
@@ -230,7 +242,7 @@ __global__ void __launch_bounds__(256) k_yinv(const MemberDev *__restrict__ mems
 template <typename P, int N, int EV>
 __global__ void __launch_bounds__(256) k_xpass(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw, int stage) {
     using C = Cfg<P, N, EV>;
-    constexpr int E = C::E, M = C::M, T = C::T, K = C::K;
+    constexpr int E = C::E, M = C::M, T = C::TX, K = C::K;
     constexpr long long FS = (long long)N * N * (K + 1);      // elements per field
     constexpr int RW = T * (K + 1);                            // elements of the tile per field
     constexpr int PER = (RW + 255) / 256;                      // staged elements per thread per field
@@ -370,7 +382,7 @@ __global__ void __launch_bounds__(256) k_xpass(const MemberDev *__restrict__ mem
 // ================================================================== yfwd
 // y-lines L = z (K+1) + kx.  in bufA [3][N][N][K+1]; out bufB [3][N (z)][2K+1][K+1]
 template <typename P, int N, int EV>
-__global__ void __launch_bounds__(256) k_yfwd(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw) {
+__global__ void __launch_bounds__((Cfg<P, N, EV>::NT)) k_yfwd(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw) {
     using C = Cfg<P, N, EV>;
     constexpr int E = C::E, M = C::M, T = C::T, K = C::K, NZL = C::NZL;
     constexpr long long FS = (long long)N * N * (K + 1);
@@ -415,10 +427,10 @@ __global__ void __launch_bounds__(256) k_yfwd(const MemberDev *__restrict__ mems
 // z-lines L = iy (K+1) + kx.  in bufB [3][N][NZL].  Forward along z, keep
 // |m_z| <= K, normalise by N^-3, project, add band forcing, RK stage update.
 template <typename P, int N>
-__global__ void __launch_bounds__(512) k_zfwd_update(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw, int stage) {
+__global__ void __launch_bounds__((Cfg<P, N, 8>::NTZ)) k_zfwd_update(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw, int stage) {
     using C = Cfg<P, N, 8>;
     constexpr int E = C::EZ, M = C::MZ, T = C::TZ, K = C::K, NZL = C::NZL, S = C::S;
-    constexpr int NT = T * M;
+    constexpr int NT = C::NTZ;
     static_assert(NT * sizeof(double) <= N * T * sizeof(LdsT<P>), "reduction scratch reuses the FFT LDS");
     __shared__ LdsT<P> lds[N * T];
     double *red = reinterpret_cast<double *>(lds);
@@ -565,10 +577,10 @@ template <typename P, int N, int EV>
 static hipError_t run_pencil(int pass, const MemberDev *mem, int count, int stage, const Cx<P> *tw, hipStream_t s) {
     using C = Cfg<P, N, EV>;
     switch (pass) {
-    case P_ZINV: k_zinv<P, N, EV><<<dim3((C::NZL + C::T - 1) / C::T, count), 256, 0, s>>>(mem, tw); break;
-    case P_YINV: k_yinv<P, N, EV><<<dim3((C::NYL + C::T - 1) / C::T, count), 256, 0, s>>>(mem, tw); break;
-    case P_XPASS: k_xpass<P, N, EV><<<dim3((unsigned)((long long)N * N / C::T), count), 256, 0, s>>>(mem, tw, stage); break;
-    case P_YFWD: k_yfwd<P, N, EV><<<dim3((C::NYL + C::T - 1) / C::T, count), 256, 0, s>>>(mem, tw); break;
+    case P_ZINV: k_zinv<P, N, EV><<<dim3((C::NZL + C::T - 1) / C::T, count), C::NT, 0, s>>>(mem, tw); break;
+    case P_YINV: k_yinv<P, N, EV><<<dim3((C::NYL + C::T - 1) / C::T, count), C::NT, 0, s>>>(mem, tw); break;
+    case P_XPASS: k_xpass<P, N, EV><<<dim3((unsigned)((long long)N * N / C::TX), count), 256, 0, s>>>(mem, tw, stage); break;
+    case P_YFWD: k_yfwd<P, N, EV><<<dim3((C::NYL + C::T - 1) / C::T, count), C::NT, 0, s>>>(mem, tw); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -583,7 +595,7 @@ static hipError_t run_pass(int pass, int variant, const MemberDev *mem, int coun
         return variant == 1 ? run_pencil<P, N, 16>(pass, mem, count, stage, twp, s)
                             : run_pencil<P, N, 8>(pass, mem, count, stage, twp, s);
     case P_ZFWD:
-        k_zfwd_update<P, N><<<dim3((C::NZL + C::TZ - 1) / C::TZ, count), C::TZ * C::MZ, 0, s>>>(mem, twp, stage);
+        k_zfwd_update<P, N><<<dim3((C::NZL + C::TZ - 1) / C::TZ, count), C::NTZ, 0, s>>>(mem, twp, stage);
         break;
     case P_END:
         k_end_step<N><<<count, 256, 0, s>>>(mem, (C::NZL + C::TZ - 1) / C::TZ);
@@ -601,6 +613,10 @@ static hipError_t dispatch_n(int n, int pass, int variant, const MemberDev *mem,
     case 64: return run_pass<P, 64>(pass, variant, mem, count, stage, tw, s);
     case 128: return run_pass<P, 128>(pass, variant, mem, count, stage, tw, s);
     case 256: return run_pass<P, 256>(pass, variant, mem, count, stage, tw, s);
+    case 512: return run_pass<P, 512>(pass, variant, mem, count, stage, tw, s);
+    case 1024:
+        if constexpr (sizeof(P) == 4) return run_pass<P, 1024>(pass, variant, mem, count, stage, tw, s);
+        else return hipErrorInvalidValue;                      // 1024^3 is FP32 only
     default: return hipErrorInvalidValue;
     }
 }
@@ -625,11 +641,19 @@ int default_variant(int pass, int n, int prec) {
     return 0;
 }
 
-long long zfwd_blocks(int n) {
-    const int K = n / 3;
-    const long long nzl = (long long)(2 * K + 1) * (K + 1);
-    const int TZ = 512 / (n / 8) < 1 ? 1 : 512 / (n / 8);
-    return (nzl + TZ - 1) / TZ;
+long long zfwd_blocks(int n, int prec) {
+    auto blocks = [](auto cfg) { using C = decltype(cfg); return (long long)((C::NZL + C::TZ - 1) / C::TZ); };
+    const bool f = prec == ENS_FP32;
+    switch (n) {
+    case 16: return f ? blocks(Cfg<float, 16, 8>{}) : blocks(Cfg<double, 16, 8>{});
+    case 32: return f ? blocks(Cfg<float, 32, 8>{}) : blocks(Cfg<double, 32, 8>{});
+    case 64: return f ? blocks(Cfg<float, 64, 8>{}) : blocks(Cfg<double, 64, 8>{});
+    case 128: return f ? blocks(Cfg<float, 128, 8>{}) : blocks(Cfg<double, 128, 8>{});
+    case 256: return f ? blocks(Cfg<float, 256, 8>{}) : blocks(Cfg<double, 256, 8>{});
+    case 512: return f ? blocks(Cfg<float, 512, 8>{}) : blocks(Cfg<double, 512, 8>{});
+    case 1024: return blocks(Cfg<float, 1024, 8>{});
+    default: return 0;
+    }
 }
 
 }  // namespace ens

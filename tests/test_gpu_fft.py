@@ -6,7 +6,7 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("n", [16, 32, 64, 128, 256])
+@pytest.mark.parametrize("n", [16, 32, 64, 128, 256, 512, 1024])
 @pytest.mark.parametrize("lines", [1, 37, 1000])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_pencils_match_library_fft(n, lines, prec):
