@@ -167,15 +167,44 @@ __global__ void __launch_bounds__(256) k_gxstats(const MemberDev *__restrict__ m
     extern __shared__ unsigned int hs[];                    // 1-D histograms, then the QR window
     __shared__ LdsT<P> lds[N * T];
     __shared__ double red[4][32];
+    // Hot bins are replicated: the central CW bins of each 1-D histogram and
+    // the central CQ x CQ bins of the QR histogram get NC copies, one per
+    // lane group (lane mod NC), so that lanes of a wavefront landing in the
+    // same bin collide at most NC ways.  Copies are merged before the flush.
+    constexpr int NC = 8, CW = 64, CQ = 16;
+    __shared__ unsigned int cen1[4][NC][CW];                // log eps, log Omega, A_L, A_T
+    __shared__ unsigned int cenq[NC][CQ * CQ];
     const MemberDev &md = mems[blockIdx.y];
     const int l = threadIdx.x % T, t = threadIdx.x / T;
+    const int grp = threadIdx.x & (NC - 1);
     const P dk = (P)md.dk;
     const int n1d = 2 * (h.lb + 3) + 2 * (h.ab + 3);
     const int nwin = h.win * h.win;
     for (int i = threadIdx.x; i < n1d + nwin; i += 256) hs[i] = 0u;
+    for (int i = threadIdx.x; i < 4 * NC * CW; i += 256) (&cen1[0][0][0])[i] = 0u;
+    for (int i = threadIdx.x; i < NC * CQ * CQ; i += 256) (&cenq[0][0])[i] = 0u;
     unsigned int *h_le = hs, *h_lw = hs + (h.lb + 3), *h_al = hs + 2 * (h.lb + 3), *h_at = h_al + (h.ab + 3);
     unsigned int *h_qr = hs + n1d;
     unsigned long long *G = md.counts;
+    // first bin of each replicated window (clamped inside the real bins; -1 = none)
+    auto c0_of = [](double centre_bin, int nb, int w) -> int {
+        if (nb < w) return -1;
+        int c = (int)floor(centre_bin) - w / 2;
+        return c < 0 ? 0 : (c > nb - w ? nb - w : c);
+    };
+    int c0[4];
+    c0[0] = c0_of((log10(md.eps_m * h.inv_eps_ref) - h.l_lo) * h.l_scale, h.lb, CW);
+    c0[1] = c0_of((log10(md.eps_m / md.nu * h.om_scale) - h.l_lo) * h.l_scale, h.lb, CW);
+    c0[2] = c0_of((0.0 - h.a_lo) * h.a_scale, h.ab, CW);
+    c0[3] = c0[2];
+    if (!(md.eps_m > 0.0) || !(md.nu > 0.0)) { c0[0] = -1; c0[1] = -1; }
+    const int q0 = c0_of((0.0 - h.q_lo) * h.q_scale, h.qb, CQ), r0 = c0_of((0.0 - h.r_lo) * h.r_scale, h.qb, CQ);
+    unsigned int *single[4] = {h_le, h_lw, h_al, h_at};
+    auto add1 = [&](int hist, int slot) {
+        const int rel = slot - c0[hist];
+        if (c0[hist] >= 0 && rel >= 0 && rel < CW) atomicAdd(&cen1[hist][grp][rel], 1u);
+        else atomicAdd(&single[hist][slot], 1u);
+    };
     double mom[26];
 #pragma unroll
     for (int i = 0; i < 26; i++) mom[i] = 0.0;
@@ -231,28 +260,30 @@ __global__ void __launch_bounds__(256) k_gxstats(const MemberDev *__restrict__ m
             const double ens = w0 * w0 + w1 * w1 + w2 * w2;
             const double qs = q * h.inv_trs, rs = r * h.inv_trs15;
             const double es = 2.0 * nu * ss * h.inv_eps_ref, ws = ens * h.om_scale;
-            {   // QR: window in LDS, elsewhere global
-                int gidx = -1, widx = -1;
+            {   // QR: replicated centre, then the LDS window, elsewhere global
+                int gidx = -1, widx = -1, cidx = -1;
                 if (qs != qs || rs != rs) gidx = h.qb * h.qb + 2;
                 else {
                     const int bq = bin_of(qs, h.q_lo, h.q_scale, h.qb), br = bin_of(rs, h.r_lo, h.r_scale, h.qb);
                     if (bq < 0 || br < 0) gidx = h.qb * h.qb;
+                    else if (q0 >= 0 && r0 >= 0 && bq >= q0 && bq < q0 + CQ && br >= r0 && br < r0 + CQ)
+                        cidx = (bq - q0) * CQ + (br - r0);
                     else if (bq >= h.win0 && bq < h.win0 + h.win && br >= h.win0 && br < h.win0 + h.win)
                         widx = (bq - h.win0) * h.win + (br - h.win0);
                     else gidx = bq * h.qb + br;
                 }
-                if (widx >= 0) atomicAdd(&h_qr[widx], 1u);
+                if (cidx >= 0) atomicAdd(&cenq[grp][cidx], 1u);
+                else if (widx >= 0) atomicAdd(&h_qr[widx], 1u);
                 else atomicAdd(&G[gidx], 1ull);
             }
-            atomicAdd(&h_le[slot_1d(es > 0.0 ? bin_of(log10(es), h.l_lo, h.l_scale, h.lb) : (es != es ? -3 : -1), h.lb)], 1u);
-            atomicAdd(&h_lw[slot_1d(ws > 0.0 ? bin_of(log10(ws), h.l_lo, h.l_scale, h.lb) : (ws != ws ? -3 : -1), h.lb)], 1u);
+            add1(0, slot_1d(es > 0.0 ? bin_of(log10(es), h.l_lo, h.l_scale, h.lb) : (es != es ? -3 : -1), h.lb));
+            add1(1, slot_1d(ws > 0.0 ? bin_of(log10(ws), h.l_lo, h.l_scale, h.lb) : (ws != ws ? -3 : -1), h.lb));
 #pragma unroll
             for (int i = 0; i < 3; i++)
 #pragma unroll
                 for (int j = 0; j < 3; j++) {
                     const double x = a[i][j] * h.tau;
-                    const int b = slot_1d(bin_of(x, h.a_lo, h.a_scale, h.ab), h.ab);
-                    atomicAdd(i == j ? &h_al[b] : &h_at[b], 1u);
+                    add1(i == j ? 2 : 3, slot_1d(bin_of(x, h.a_lo, h.a_scale, h.ab), h.ab));
                     double xp = 1.0;
 #pragma unroll
                     for (int p = 0; p < 6; p++) { xp *= x; mom[(i == j ? 0 : 6) + p] += xp; }
@@ -266,6 +297,22 @@ __global__ void __launch_bounds__(256) k_gxstats(const MemberDev *__restrict__ m
             mom[24] += qs * qs; mom[25] += rs * rs;
         }
     }
+    // merge the replicated 1-D windows into the single-copy histograms
+    __syncthreads();
+    for (int i = threadIdx.x; i < 4 * CW; i += 256) {
+        const int hh = i / CW, rel = i % CW;
+        if (c0[hh] < 0) continue;
+        unsigned int sum = 0;
+#pragma unroll
+        for (int c = 0; c < NC; c++) sum += cen1[hh][c][rel];
+        single[hh][c0[hh] + rel] += sum;
+    }
+    for (int i = threadIdx.x; i < CQ * CQ; i += 256) {
+        unsigned int sum = 0;
+#pragma unroll
+        for (int c = 0; c < NC; c++) sum += cenq[c][i];
+        if (sum) atomicAdd(&G[(long long)(q0 + i / CQ) * h.qb + (r0 + i % CQ)], (unsigned long long)sum);
+    }
     // deterministic reduction of the moments: wave butterfly, then waves in order
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
@@ -276,7 +323,7 @@ __global__ void __launch_bounds__(256) k_gxstats(const MemberDev *__restrict__ m
         if (lane == 0) red[wave][i] = x;
     }
     __syncthreads();
-    const long long pbase = ((long long)blockIdx.x) * 32;
+    const long long pbase = ((long long)blockIdx.x) * 32;  // (the flush below is after a barrier)
     if (threadIdx.x < 32) {
         double x = 0.0;
         if (threadIdx.x < 26) x = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
@@ -354,7 +401,7 @@ static hipError_t stats_pass(int pass, const MemberDev *mem, int count, const en
         h.om_scale = d.nu_ref / d.eps_ref;
         // LDS: transform tile + reduction (static) + 1-D histograms + QR window (dynamic) <= 64 KiB
         constexpr int T = 256 / (N / 4);
-        const size_t stat = (size_t)N * T * sizeof(LdsT<P>) + 4 * 32 * sizeof(double);
+        const size_t stat = (size_t)N * T * sizeof(LdsT<P>) + 4 * 32 * sizeof(double) + (4 * 8 * 64 + 8 * 16 * 16) * 4;
         const size_t n1d = 2 * (size_t)(h.lb + 3) + 2 * (size_t)(h.ab + 3);
         const size_t budget = 65536 - stat - 512;
         if (n1d * 4 > budget) return hipErrorInvalidValue;      // rejected on the host beforehand
@@ -407,7 +454,7 @@ hipError_t launch_stats_reduce(int n, int prec, const MemberDev *mem, int count,
 long long xstats_blocks(int n) { return 512; }
 bool stats_hist_fits(const ens_hist_desc &h) {
     const size_t n1d = 2 * (size_t)(h.log_bins + 3) + 2 * (size_t)(h.a_bins + 3);
-    return n1d * 4 <= 65536 - 16384 - 4 * 32 * 8 - 512 - 4096;
+    return n1d * 4 <= 65536 - 16384 - 4 * 32 * 8 - 16384 - 512 - 4096;
 }
 
 // =================================================================== mixture
