@@ -150,6 +150,7 @@ struct ens_ctx {
     bool has_hist = false;
     ens_hist_desc hist{};
     HistGeom hg{};
+    double *ledge = nullptr;          // log-histogram edges 10^(lo + b (hi - lo) / bins), b = 0..bins
     hipStream_t cap = nullptr;   // private stream used for graph capture
     std::vector<std::unique_ptr<Member>> members;
     std::map<std::vector<int>, std::unique_ptr<Plan>> plans;
@@ -323,9 +324,23 @@ ENS_API ens_status ens_create(ens_ctx **out, int device, const ens_hist_desc *h)
         ctx->has_hist = true;
         ctx->hist = *h;
         ctx->hg = make_hist_geom(*h);
+        std::vector<double> edges((size_t)h->log_bins + 1);
+        const double w = (h->log10_hi - h->log10_lo) / (double)h->log_bins;
+        for (size_t b = 0; b < edges.size(); b++) edges[b] = std::pow(10.0, h->log10_lo + (double)b * w);
+        e = hipMalloc(&ctx->ledge, edges.size() * sizeof(double));
+        if (e != hipSuccess) return fail(ENS_E_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        ctx->dev_allocs.push_back(ctx->ledge);
+        e = hipMemcpy(ctx->ledge, edges.data(), edges.size() * sizeof(double), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            hipFree(ctx->ledge);
+            return fail(ENS_E_HIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
+        }
     }
     e = hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking);
-    if (e != hipSuccess) return fail(ENS_E_HIP, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+    if (e != hipSuccess) {
+        if (ctx->ledge) hipFree(ctx->ledge);
+        return fail(ENS_E_HIP, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+    }
     *out = ctx.release();
     return ENS_OK;
 }
@@ -523,7 +538,7 @@ ENS_API ens_status ens_accumulate_stats(ens_ctx *ctx, const int32_t *members, in
         const int cnt = (int)g.ids.size();
         HIPCK(ctx, launch_grad_zinv(g.n, g.prec, g.dev, cnt, g.tw, s));
         HIPCK(ctx, launch_grad_yinv(g.n, g.prec, g.dev, cnt, g.tw, s));
-        HIPCK(ctx, launch_grad_xstats(g.n, g.prec, g.dev, cnt, ctx->hist, g.tw, s));
+        HIPCK(ctx, launch_grad_xstats(g.n, g.prec, g.dev, cnt, ctx->hist, ctx->ledge, g.tw, s));
         HIPCK(ctx, launch_stats_reduce(g.n, g.prec, g.dev, cnt, s));
     }
     for (int id : ids) ctx->members[id]->last = s;
@@ -721,7 +736,7 @@ ENS_API ens_status ens_autotune(ens_ctx *ctx, const int32_t *members, int32_t co
     drop_graphs(ctx);
     if (cache_path) {
         std::ofstream f(cache_path);
-        f << "# libensdns kernel variants (pass:n:precision variant); 0 = 8, 1 = 16 values per thread\n";
+        f << "# libensdns kernel variants (pass:n:precision variant); 0 = 8, 1 = 16 values per thread, 2 = streamed x pass\n";
         for (auto &kv : cache) f << kv.first << " " << kv.second << "\n";
     }
     return ENS_OK;

@@ -84,7 +84,9 @@ enum Pass { P_BAND = 0, P_ZINV = 1, P_YINV = 2, P_XPASS = 3, P_YFWD = 4, P_ZFWD 
 // Launchers (defined in the .hip files).  `mem` points to a device array of
 // `count` MemberDev of one size n and precision; grids cover all of them.
 // `variant` selects a compiled kernel variant (0: 8 values per thread,
-// 1: 16 values per thread) for passes with pass_variants(pass) > 1.
+// 1: 16 values per thread; x pass 2: persistent pipelined workgroups with
+// direct-to-LDS staging, 8 values per thread) for passes with
+// pass_variants(pass) > 1.
 hipError_t launch_pass(int pass, int variant, int n, int prec, const MemberDev *mem, int count, int stage,
                        const void *tw, hipStream_t s);
 int pass_variants(int pass);
@@ -97,7 +99,7 @@ hipError_t launch_get_state(int n, int prec, const MemberDev *mem, double *dst, 
 hipError_t launch_grad_zinv(int n, int prec, const MemberDev *mem, int count, const void *tw, hipStream_t s);
 hipError_t launch_grad_yinv(int n, int prec, const MemberDev *mem, int count, const void *tw, hipStream_t s);
 hipError_t launch_grad_xstats(int n, int prec, const MemberDev *mem, int count, const ens_hist_desc &h,
-                              const void *tw, hipStream_t s);
+                              const double *ledge, const void *tw, hipStream_t s);
 hipError_t launch_stats_reduce(int n, int prec, const MemberDev *mem, int count, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, long long n, unsigned long long v, hipStream_t s);
 hipError_t launch_fill_f64(double *p, long long n, double v, hipStream_t s);
@@ -115,7 +117,7 @@ int mix_max_members();
 // Number of workgroups that write FP64 partials, per member.
 long long zfwd_blocks(int n, int prec);
 long long xstats_blocks(int n);
-bool stats_hist_fits(const ens_hist_desc &h);   // 1-D histograms fit the statistics kernel's LDS
+bool stats_hist_fits(const ens_hist_desc &h);   // 1-D histograms and log edges fit the statistics kernel's LDS
 long long init_blocks(int n);
 
 }  // namespace ens

@@ -133,6 +133,18 @@ __host__ __device__ constexpr int stage_span(int N, int E, int s) {
     return p;
 }
 
+// Entries of the twiddle table a transform reads: 1 + the largest index
+// m k N / (Ns r) over its stages (m < r, k < Ns).
+__host__ __device__ constexpr int twiddle_span(int N, int E) {
+    int mx = 0;
+    for (int s = 1; s < num_stages(N, E); s++) {
+        const int r = stage_radix(N, E, s), ns = stage_span(N, E, s);
+        const int v = (r - 1) * (ns - 1) * (N / (ns * r));
+        mx = v > mx ? v : mx;
+    }
+    return mx + 1;
+}
+
 template <int N, int E> struct Plan {
     static constexpr int M = N / E;                              // threads per line
     static constexpr int S = num_stages(N, E);
@@ -153,6 +165,18 @@ template <int DIR, typename P> __device__ __forceinline__ Cx<P> twiddle(const Cx
 }
 
 template <typename P> using LdsT = typename V2<P>::T;
+
+// Workgroup barrier for LDS exchanges: waits for this wave's LDS operations
+// only.  A __syncthreads() fence would also wait for outstanding loads that
+// write LDS directly (global_load_lds), which the pipelined passes keep in
+// flight across the transforms.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+// Barrier between transform stages: __syncthreads() (SB = false) or
+// lds_barrier() (SB = true, for passes that keep direct-to-LDS loads in flight).
+template <bool SB> __device__ __forceinline__ void stage_barrier() {
+    if constexpr (SB) lds_barrier();
+    else __syncthreads();
+}
 
 template <typename P> __device__ __forceinline__ void lds_put(LdsT<P> *lds, int i, Cx<P> v) {
     LdsT<P> x; x.x = v.re; x.y = v.im; lds[i] = x;
@@ -190,24 +214,24 @@ __device__ __forceinline__ void stage_scatter(const Cx<P> *v, LdsT<P> *lds, int 
     }
 }
 
-template <typename P, int N, int E, int T, int DIR, int s>
+template <typename P, int N, int E, int T, int DIR, int s, bool SB>
 __device__ __forceinline__ void run_stages(Cx<P> *v, LdsT<P> *lds, int l, int t, const Cx<P> *tw) {
     if constexpr (s < num_stages(N, E)) {
-        __syncthreads();
+        stage_barrier<SB>();
         stage_scatter<P, N, E, T, s - 1>(v, lds, l, t);
-        __syncthreads();
+        stage_barrier<SB>();
         stage_gather<P, N, E, T, DIR, s>(v, lds, l, t, tw);
-        run_stages<P, N, E, T, DIR, s + 1>(v, lds, l, t, tw);
+        run_stages<P, N, E, T, DIR, s + 1, SB>(v, lds, l, t, tw);
     }
 }
 
 // Forward-flow transform.  All threads of the workgroup must call it (it
 // contains barriers).  LDS: N*T elements of V2<P>.
-template <typename P, int N, int E, int T, int DIR>
+template <typename P, int N, int E, int T, int DIR, bool SB = false>
 __device__ __forceinline__ void line_fft(Cx<P> *v, LdsT<P> *lds, int l, int t, const Cx<P> *tw) {
     static_assert(N % E == 0 && N >= E, "line length must be a multiple of E");
     dft<E, DIR>(v);                       // stage 0: span 1, no twiddles
-    run_stages<P, N, E, T, DIR, 1>(v, lds, l, t, tw);
+    run_stages<P, N, E, T, DIR, 1, SB>(v, lds, l, t, tw);
 }
 
 // ---- transposed flow (stages in reverse order, twiddles after the butterflies)
@@ -247,21 +271,21 @@ __device__ __forceinline__ void stageT_gather(Cx<P> *v, const LdsT<P> *lds, int 
     }
 }
 
-template <typename P, int N, int E, int T, int DIR, int s>
+template <typename P, int N, int E, int T, int DIR, int s, bool SB>
 __device__ __forceinline__ void run_stagesT(Cx<P> *v, LdsT<P> *lds, int l, int t, const Cx<P> *tw) {
     stageT_compute<P, N, E, T, DIR, s>(v, t, tw);
     if constexpr (s > 0) {
-        __syncthreads();
+        stage_barrier<SB>();
         stageT_scatter<P, N, E, T, s>(v, lds, l, t);
-        __syncthreads();
+        stage_barrier<SB>();
         stageT_gather<P, N, E, T, s - 1>(v, lds, l, t);
-        run_stagesT<P, N, E, T, DIR, s - 1>(v, lds, l, t, tw);
+        run_stagesT<P, N, E, T, DIR, s - 1, SB>(v, lds, l, t, tw);
     }
 }
 
-template <typename P, int N, int E, int T, int DIR>
+template <typename P, int N, int E, int T, int DIR, bool SB = false>
 __device__ __forceinline__ void line_fft_T(Cx<P> *v, LdsT<P> *lds, int l, int t, const Cx<P> *tw) {
-    run_stagesT<P, N, E, T, DIR, num_stages(N, E) - 1>(v, lds, l, t, tw);
+    run_stagesT<P, N, E, T, DIR, num_stages(N, E) - 1, SB>(v, lds, l, t, tw);
 }
 
 }  // namespace ens

@@ -53,4 +53,43 @@ __device__ __forceinline__ void xcd_tile(unsigned &tile, unsigned &member) {
     tile = gp - member * gx;
 }
 
+// s_waitcnt bounding only the vector-memory counter: wait until at most n
+// vector-memory operations (loads, stores, direct-to-LDS loads) of this wave
+// are outstanding; they complete in issue order.
+template <int n> __device__ __forceinline__ void wait_vm() {
+    static_assert(n >= 0 && n < 64, "vmcnt is a 6-bit counter");
+    __builtin_amdgcn_s_waitcnt((n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+// Direct-to-LDS copy of one tile of three fields into `dst` laid out
+// [3][RV] in 16-byte vectors.  Field f's tile starts at byte b0 + f fstride
+// (16-byte aligned).  Each field is cut into ceil(RV/64) wave-sized chunks,
+// the last one moved back to end at the field's last vector (re-copying a few
+// vectors with identical data), so that every global_load_lds moves 64
+// consecutive vectors of one field: its global and LDS bases are wave-uniform
+// (scalar registers) and the lane offset is lane * 16.  Every wave issues
+// exactly ceil(3 ceil(RV/64) / waves) copies (surplus waves repeat the last
+// chunk), so the vector-memory counter of every wave advances by the same
+// known amount.
+template <int RV, int NTH>
+__device__ __forceinline__ void dma_tile3(void *dst, const char *b0, long long fstride) {
+    constexpr int NCF = (RV + 63) / 64, NCH = 3 * NCF, NW = NTH / 64;
+    static_assert(RV >= 64 && NTH % 64 == 0, "tile too small for wave-wide copies");
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const unsigned lane16 = (threadIdx.x & 63u) * 16u;
+#pragma unroll
+    for (int j = 0; j < (NCH + NW - 1) / NW; j++) {
+        int c = j * NW + wave;
+        c = c < NCH ? c : NCH - 1;
+        const int f = c / NCF, q = c - f * NCF;
+        const int st = q * 64 < RV - 64 ? q * 64 : RV - 64;
+        const ENS_GLOBAL char *src = (const ENS_GLOBAL char *)b0 + f * fstride + st * 16;
+        __builtin_amdgcn_global_load_lds((const ENS_GLOBAL void *)(src + lane16),
+                                         (__attribute__((address_space(3))) void *)((char *)dst + (f * RV + st) * 16), 16, 0, 0);
+    }
+}
+template <int RV, int NTH> constexpr int dma_tile3_ops() {
+    return (3 * ((RV + 63) / 64) + NTH / 64 - 1) / (NTH / 64);
+}
+
 }  // namespace ens

@@ -143,6 +143,8 @@ struct HistArgs {
     double tau, inv_trs, inv_trs15, inv_eps_ref, om_scale;
     int win0, win;             // QR bins [win0, win0 + win)^2 are counted in LDS, the rest globally
     int tiles_per_block;
+    const double *ledge;       // lb + 1 edges 10^(l_lo + b / l_scale) of the log histograms (FP64)
+    float l2s, loff;           // log10(2) l_scale and l_lo l_scale: bin estimate from log2
 };
 
 // -1 under, -2 over, -3 nan, else bin
@@ -153,18 +155,39 @@ __device__ __forceinline__ int bin_of(double x, double lo, double scale, int nb)
     if (b >= (double)nb) return -2;
     return (int)b;
 }
+// Bin of log10(x) for x > 0 with the decision taken in FP64 against the edge
+// table: an FP32 estimate from the exponent and the hardware log2 of the
+// mantissa is within a small fraction of a bin, so one comparison with each
+// neighbouring edge gives floor((log10 x - lo) scale) except for x within
+// rounding of an edge.  Replaces the FP64 log10 (about 80 instructions).
+__device__ __forceinline__ int log_bin(double x, const double *edge, int nb, float l2s, float loff) {
+    if (x < edge[0]) return -1;
+    if (x >= edge[nb]) return -2;
+    int e;
+    const double m = frexp(x, &e);                       // x = m 2^e, m in [0.5, 1)
+    const float l2 = (float)e + __log2f((float)m);
+    int c = (int)floorf(l2 * l2s - loff);
+    c = c < 0 ? 0 : (c > nb - 1 ? nb - 1 : c);
+    if (x < edge[c]) c--;
+    else if (x >= edge[c + 1]) c++;
+    return c;
+}
 __device__ __forceinline__ int slot_1d(int b, int nb) { return b >= 0 ? b : (b == -1 ? nb : (b == -2 ? nb + 1 : nb + 2)); }
 
 // Persistent x pass of the gradient fields: each workgroup takes row tiles
 // blockIdx.x, blockIdx.x + gridDim.x, ...; per-point values are formed in FP64;
 // 1-D histograms and a central window of the QR histogram are accumulated in
 // LDS (32-bit) and flushed once; moments stay in registers and are reduced
-// in a fixed order to one partial per workgroup.
+// in a fixed order to one partial per workgroup.  The register budget is
+// capped at 256 so that two workgroups share a compute unit (one leaves each
+// SIMD a single wave, which stalls on every dependent FP64 operation).
 template <typename P, int N>
-__global__ void __launch_bounds__(256) k_gxstats(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw, HistArgs h) {
+__global__ void __launch_bounds__(256, 2) k_gxstats(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw, HistArgs h) {
     constexpr int E = 4, M = N / E, T = 256 / M, K = N / 3;
     constexpr long long FS = (long long)N * N * (K + 1);
-    extern __shared__ unsigned int hs[];                    // 1-D histograms, then the QR window
+    extern __shared__ double dyn[];                         // log edges, 1-D histograms, QR window
+    double *ledge = dyn;
+    unsigned int *hs = (unsigned int *)(dyn + h.lb + 1);
     __shared__ LdsT<P> lds[N * T];
     __shared__ double red[4][32];
     // Hot bins are replicated: the central CW bins of each 1-D histogram and
@@ -181,6 +204,7 @@ __global__ void __launch_bounds__(256) k_gxstats(const MemberDev *__restrict__ m
     const int n1d = 2 * (h.lb + 3) + 2 * (h.ab + 3);
     const int nwin = h.win * h.win;
     for (int i = threadIdx.x; i < n1d + nwin; i += 256) hs[i] = 0u;
+    for (int i = threadIdx.x; i <= h.lb; i += 256) ledge[i] = h.ledge[i];
     for (int i = threadIdx.x; i < 4 * NC * CW; i += 256) (&cen1[0][0][0])[i] = 0u;
     for (int i = threadIdx.x; i < NC * CQ * CQ; i += 256) (&cenq[0][0])[i] = 0u;
     unsigned int *h_le = hs, *h_lw = hs + (h.lb + 3), *h_al = hs + 2 * (h.lb + 3), *h_at = h_al + (h.ab + 3);
@@ -244,18 +268,21 @@ __global__ void __launch_bounds__(256) k_gxstats(const MemberDev *__restrict__ m
 #pragma unroll
                 for (int j = 0; j < 3; j++) a[i][j] = (double)g[3 * i + j][s];
             const double tr = a[0][0] + a[1][1] + a[2][2];
-            double q = 0.0, r = 0.0, ss = 0.0;
+            // Q = -tr(A^2)/2 and R = -tr(A^3)/3 from the rows of A^2
+            double q = 0.0, r = 0.0;
 #pragma unroll
             for (int i = 0; i < 3; i++)
 #pragma unroll
-                for (int j = 0; j < 3; j++) {
-                    q += a[i][j] * a[j][i];
-                    const double sij = 0.5 * (a[i][j] + a[j][i]);
-                    ss += sij * sij;
-#pragma unroll
-                    for (int k = 0; k < 3; k++) r += a[i][j] * a[j][k] * a[k][i];
+                for (int k = 0; k < 3; k++) {
+                    const double b = a[i][0] * a[0][k] + a[i][1] * a[1][k] + a[i][2] * a[2][k];
+                    if (i == k) q += b;
+                    r += b * a[k][i];
                 }
             q *= -0.5; r *= -1.0 / 3.0;
+            // S_ij S_ij: diagonal squares plus twice each off-diagonal pair
+            const double s01 = a[0][1] + a[1][0], s02 = a[0][2] + a[2][0], s12 = a[1][2] + a[2][1];
+            const double ss = a[0][0] * a[0][0] + a[1][1] * a[1][1] + a[2][2] * a[2][2] +
+                              0.5 * (s01 * s01 + s02 * s02 + s12 * s12);
             const double w0 = a[2][1] - a[1][2], w1 = a[0][2] - a[2][0], w2 = a[1][0] - a[0][1];
             const double ens = w0 * w0 + w1 * w1 + w2 * w2;
             const double qs = q * h.inv_trs, rs = r * h.inv_trs15;
@@ -276,8 +303,8 @@ __global__ void __launch_bounds__(256) k_gxstats(const MemberDev *__restrict__ m
                 else if (widx >= 0) atomicAdd(&h_qr[widx], 1u);
                 else atomicAdd(&G[gidx], 1ull);
             }
-            add1(0, slot_1d(es > 0.0 ? bin_of(log10(es), h.l_lo, h.l_scale, h.lb) : (es != es ? -3 : -1), h.lb));
-            add1(1, slot_1d(ws > 0.0 ? bin_of(log10(ws), h.l_lo, h.l_scale, h.lb) : (ws != ws ? -3 : -1), h.lb));
+            add1(0, slot_1d(es > 0.0 ? log_bin(es, ledge, h.lb, h.l2s, h.loff) : (es != es ? -3 : -1), h.lb));
+            add1(1, slot_1d(ws > 0.0 ? log_bin(ws, ledge, h.lb, h.l2s, h.loff) : (ws != ws ? -3 : -1), h.lb));
 #pragma unroll
             for (int i = 0; i < 3; i++)
 #pragma unroll
@@ -376,7 +403,8 @@ static int xstats_grid(int n, int count) {
 
 // ---------------------------------------------------------------- launchers
 template <typename P, int N>
-static hipError_t stats_pass(int pass, const MemberDev *mem, int count, const ens_hist_desc *hd, const void *tw, hipStream_t s) {
+static hipError_t stats_pass(int pass, const MemberDev *mem, int count, const ens_hist_desc *hd, const double *ledge,
+                             const void *tw, hipStream_t s) {
     using C = SCfg<P, N, grad_e<P>()>;
     const Cx<P> *twp = reinterpret_cast<const Cx<P> *>(tw);
     if (pass == 0) {
@@ -399,17 +427,21 @@ static hipError_t stats_pass(int pass, const MemberDev *mem, int count, const en
         h.inv_trs15 = 1.0 / pow(trs, 1.5);
         h.inv_eps_ref = 1.0 / d.eps_ref;
         h.om_scale = d.nu_ref / d.eps_ref;
-        // LDS: transform tile + reduction (static) + 1-D histograms + QR window (dynamic) <= 64 KiB
+        h.ledge = ledge;
+        h.l2s = (float)(0.30102999566398119521 * h.l_scale);
+        h.loff = (float)(h.l_lo * h.l_scale);
+        // LDS: transform tile + reduction (static) + log edges, 1-D histograms, QR window (dynamic) <= 64 KiB
         constexpr int T = 256 / (N / 4);
         const size_t stat = (size_t)N * T * sizeof(LdsT<P>) + 4 * 32 * sizeof(double) + (4 * 8 * 64 + 8 * 16 * 16) * 4;
         const size_t n1d = 2 * (size_t)(h.lb + 3) + 2 * (size_t)(h.ab + 3);
         const size_t budget = 65536 - stat - 512;
-        if (n1d * 4 > budget) return hipErrorInvalidValue;      // rejected on the host beforehand
-        int win = (int)std::sqrt((double)((budget - n1d * 4) / 4));
+        const size_t fixed = n1d * 4 + (size_t)(h.lb + 1) * 8;
+        if (fixed > budget || !ledge) return hipErrorInvalidValue;   // rejected on the host beforehand
+        int win = (int)std::sqrt((double)((budget - fixed) / 4));
         if (win > h.qb) win = h.qb;
         h.win = win;
         h.win0 = (h.qb - win) / 2;
-        const size_t dyn = (n1d + (size_t)win * win) * 4;
+        const size_t dyn = (size_t)(h.lb + 1) * 8 + (n1d + (size_t)win * win) * 4;
         const int per = xstats_grid(N, count);
         k_gxstats<P, N><<<dim3(per, count), 256, dyn, s>>>(mem, twp, h);
     } else {
@@ -419,42 +451,44 @@ static hipError_t stats_pass(int pass, const MemberDev *mem, int count, const en
 }
 
 template <typename P>
-static hipError_t stats_n(int n, int pass, const MemberDev *mem, int count, const ens_hist_desc *hd, const void *tw, hipStream_t s) {
+static hipError_t stats_n(int n, int pass, const MemberDev *mem, int count, const ens_hist_desc *hd, const double *le,
+                          const void *tw, hipStream_t s) {
     switch (n) {
-    case 16: return stats_pass<P, 16>(pass, mem, count, hd, tw, s);
-    case 32: return stats_pass<P, 32>(pass, mem, count, hd, tw, s);
-    case 64: return stats_pass<P, 64>(pass, mem, count, hd, tw, s);
-    case 128: return stats_pass<P, 128>(pass, mem, count, hd, tw, s);
-    case 256: return stats_pass<P, 256>(pass, mem, count, hd, tw, s);
-    case 512: return stats_pass<P, 512>(pass, mem, count, hd, tw, s);
+    case 16: return stats_pass<P, 16>(pass, mem, count, hd, le, tw, s);
+    case 32: return stats_pass<P, 32>(pass, mem, count, hd, le, tw, s);
+    case 64: return stats_pass<P, 64>(pass, mem, count, hd, le, tw, s);
+    case 128: return stats_pass<P, 128>(pass, mem, count, hd, le, tw, s);
+    case 256: return stats_pass<P, 256>(pass, mem, count, hd, le, tw, s);
+    case 512: return stats_pass<P, 512>(pass, mem, count, hd, le, tw, s);
     case 1024:
-        if constexpr (sizeof(P) == 4) return stats_pass<P, 1024>(pass, mem, count, hd, tw, s);
+        if constexpr (sizeof(P) == 4) return stats_pass<P, 1024>(pass, mem, count, hd, le, tw, s);
         else return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
 }
-static hipError_t stats_dispatch(int n, int prec, int pass, const MemberDev *mem, int count, const ens_hist_desc *hd,
+static hipError_t stats_dispatch(int n, int prec, int pass, const MemberDev *mem, int count, const ens_hist_desc *hd, const double *le,
                                  const void *tw, hipStream_t s) {
-    return prec == ENS_FP32 ? stats_n<float>(n, pass, mem, count, hd, tw, s) : stats_n<double>(n, pass, mem, count, hd, tw, s);
+    return prec == ENS_FP32 ? stats_n<float>(n, pass, mem, count, hd, le, tw, s) : stats_n<double>(n, pass, mem, count, hd, le, tw, s);
 }
 
 hipError_t launch_grad_zinv(int n, int prec, const MemberDev *mem, int count, const void *tw, hipStream_t s) {
-    return stats_dispatch(n, prec, 0, mem, count, nullptr, tw, s);
+    return stats_dispatch(n, prec, 0, mem, count, nullptr, nullptr, tw, s);
 }
 hipError_t launch_grad_yinv(int n, int prec, const MemberDev *mem, int count, const void *tw, hipStream_t s) {
-    return stats_dispatch(n, prec, 1, mem, count, nullptr, tw, s);
+    return stats_dispatch(n, prec, 1, mem, count, nullptr, nullptr, tw, s);
 }
-hipError_t launch_grad_xstats(int n, int prec, const MemberDev *mem, int count, const ens_hist_desc &h, const void *tw, hipStream_t s) {
-    return stats_dispatch(n, prec, 2, mem, count, &h, tw, s);
+hipError_t launch_grad_xstats(int n, int prec, const MemberDev *mem, int count, const ens_hist_desc &h, const double *ledge,
+                              const void *tw, hipStream_t s) {
+    return stats_dispatch(n, prec, 2, mem, count, &h, ledge, tw, s);
 }
 hipError_t launch_stats_reduce(int n, int prec, const MemberDev *mem, int count, hipStream_t s) {
-    return stats_dispatch(n, prec, 3, mem, count, nullptr, nullptr, s);
+    return stats_dispatch(n, prec, 3, mem, count, nullptr, nullptr, nullptr, s);
 }
 // upper bound of workgroup partials per member (the grid depends on the batch)
 long long xstats_blocks(int n) { return 512; }
 bool stats_hist_fits(const ens_hist_desc &h) {
     const size_t n1d = 2 * (size_t)(h.log_bins + 3) + 2 * (size_t)(h.a_bins + 3);
-    return n1d * 4 <= 65536 - 16384 - 4 * 32 * 8 - 16384 - 512 - 4096;
+    return n1d * 4 + (size_t)(h.log_bins + 1) * 8 <= 65536 - 16384 - 4 * 32 * 8 - 16384 - 512 - 4096;
 }
 
 // =================================================================== mixture

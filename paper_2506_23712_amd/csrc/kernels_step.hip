@@ -379,6 +379,213 @@ __global__ void __launch_bounds__(256) k_xpass(const MemberDev *__restrict__ mem
     }
 }
 
+// ------------------------------------------------------ pipelined x pass
+// The same computation as k_xpass, organised for streaming: a persistent
+// workgroup walks a contiguous range of row tiles of one member.  Its six input
+// fields arrive by direct-to-LDS loads into two staging buffers (fields 0-2 and
+// 3-5 of a tile), and the next tile's fields are requested as soon as a buffer
+// has been read, so HBM reads stay in flight through the transforms, the
+// product and the stores without holding registers.  Twiddles are read from
+// LDS, since a global load consumed inside the loop would wait for every
+// earlier copy (vector-memory operations complete in order).  Outputs are
+// staged in LDS and written with linear 16-byte stores.
+template <typename P, int N, int E_> struct XCfg {
+    static constexpr int K = N / 3, E = E_ > N ? N : E_, M = N / E;
+    static constexpr int CS = (int)sizeof(Cx<P>), CPV = 16 / CS;
+    static constexpr int NTW = twiddle_span(N, E);
+    static constexpr long long lds_bytes(int t) {
+        const long long rw = (long long)t * (K + 1);
+        const long long xl = (long long)N * t > 3 * rw ? (long long)N * t : 3 * rw;
+        return (6 * rw + xl + NTW) * CS + 64;
+    }
+    // rows per tile: the most (at most 256 threads) whose LDS lets three
+    // workgroups share a compute unit, else the fewest with one full wave
+    static constexpr int pick_t() {
+        int t = 256 / M;
+        while (t > 1 && (t * M > 64) && lds_bytes(t) > 53248) t /= 2;
+        return t < 1 ? 1 : t;
+    }
+    static constexpr int T = pick_t(), NTH = M * T;
+    static constexpr int RW = T * (K + 1);                 // elements of a tile per field
+    static constexpr int RV = RW / CPV;                    // 16-byte vectors per field tile
+    static constexpr int D3 = dma_tile3_ops<RV, NTH>();     // copies per wave per staging buffer
+    static constexpr int S = D3;                           // 16-byte stores per wave per tile (same chunks)
+    static constexpr int XL = N * T > 3 * RW ? N * T : 3 * RW;
+    static constexpr int TILES = N * N / T;
+    // workgroups per compute unit the register budget is cut for: what the LDS
+    // allows, up to 3 waves per SIMD (FP32) or 2 (FP64)
+    static constexpr int MINB_LDS = (int)(163840 / ((lds_bytes(T) + 511) / 512 * 512));
+    static constexpr int MINB_VGPR = (sizeof(P) == 4 ? 12 : 8) / (NTH / 64);
+    static constexpr int MINB = MINB_LDS < MINB_VGPR ? MINB_LDS : MINB_VGPR;
+    static_assert(RW % CPV == 0 && NTH % 64 == 0 && RV >= 64 && D3 + S < 64, "x-pass tile shape");
+};
+
+template <typename P, int N, int EV>
+__global__ void __launch_bounds__((XCfg<P, N, EV>::NTH), (XCfg<P, N, EV>::MINB)) k_xpass_dma(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw, int stage) {
+    using C = XCfg<P, N, EV>;
+    constexpr int E = C::E, M = C::M, T = C::T, K = C::K, NTH = C::NTH, RW = C::RW, RV = C::RV;
+    constexpr long long FSB = (long long)N * N * (K + 1) * C::CS;    // bytes per field
+    __shared__ __attribute__((aligned(16))) LdsT<P> slot0[3 * RW];
+    __shared__ __attribute__((aligned(16))) LdsT<P> slot1[3 * RW];
+    __shared__ __attribute__((aligned(16))) LdsT<P> lds[C::XL];
+    __shared__ Cx<P> twl[C::NTW];
+    unsigned chunk, mem_i;
+    xcd_tile(chunk, mem_i);
+    const MemberDev &md = mems[mem_i];
+    const int t0 = (int)((long long)chunk * C::TILES / gridDim.x);
+    const int t1 = (int)((long long)(chunk + 1) * C::TILES / gridDim.x);
+    if (t0 >= t1) return;                                     // uniform over the workgroup
+    const int l = (int)threadIdx.x % T, t = (int)threadIdx.x / T;
+    for (int i = (int)threadIdx.x; i < C::NTW; i += NTH) twl[i] = tw[i];
+    const char *inb = (const char *)md.bufB;
+    char *outb = (char *)md.bufA;
+    auto request = [&](LdsT<P> *dst, int tile, int f0) {      // fields f0..f0+2 of `tile`
+        dma_tile3<RV, NTH>(dst, inb + (long long)f0 * FSB + (long long)tile * RW * C::CS, FSB);
+    };
+    // packed two-for-one spectrum of fields (fa, fb): C = A + i B, Hermitian
+    // fill.  Position n = t + M m; whole segments [M m, M m + M) below K, above
+    // N - K or in between are sorted out at compile time.
+    auto gather = [&](Cx<P> *v, const LdsT<P> *fa, const LdsT<P> *fb) {
+#pragma unroll
+        for (int m = 0; m < E; m++) {
+            const int n = t + M * m;
+            const int r = l * (K + 1);
+            if (M * m > K && M * m + M - 1 < N - K) {
+                v[m] = czero<P>();
+            } else if (m > 0 && M * m + M - 1 <= K) {
+                const Cx<P> A = lds_get<P>(fa, r + n), B = lds_get<P>(fb, r + n);
+                v[m] = {A.re - B.im, A.im + B.re};
+            } else if (M * m >= N - K) {
+                const Cx<P> A = lds_get<P>(fa, r + N - n), B = lds_get<P>(fb, r + N - n);
+                v[m] = {A.re + B.im, B.re - A.im};
+            } else {
+                const bool lo = n <= K, hi = n >= N - K;
+                const int kx = lo ? n : N - n;
+                Cx<P> A = czero<P>(), B = czero<P>();
+                if (lo || hi) { A = lds_get<P>(fa, r + kx); B = lds_get<P>(fb, r + kx); }
+                if (n == 0) v[m] = {A.re, B.re};
+                else if (lo) v[m] = {A.re - B.im, A.im + B.re};
+                else v[m] = {A.re + B.im, B.re - A.im};
+            }
+        }
+    };
+    P umx = P(0);
+    Cx<P> v[E];
+    // Write the tile staged in lds ([3][RV] vectors) with 16-byte stores, in
+    // the wave-sized chunks of dma_tile3 (the same count per wave).
+    typedef float F4 __attribute__((ext_vector_type(4)));
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const unsigned lane16 = (threadIdx.x & 63u) * 16u;
+    auto store_tile = [&](int tile, bool zero) {
+        constexpr int NCF = (RV + 63) / 64, NCH = 3 * NCF, NW = NTH / 64;
+#pragma unroll
+        for (int j = 0; j < C::S; j++) {
+            int c = j * NW + wave;
+            c = c < NCH ? c : NCH - 1;
+            const int f = c / NCF, q = c - f * NCF;
+            const int st = q * 64 < RV - 64 ? q * 64 : RV - 64;
+            const F4 x = zero ? F4{0.f, 0.f, 0.f, 0.f} : *(const F4 *)((const char *)lds + (f * RV + st) * 16 + lane16);
+            ENS_GLOBAL char *dst = (ENS_GLOBAL char *)outb + f * FSB + (long long)tile * RW * C::CS + st * 16;
+            *(ENS_GLOBAL F4 *)(dst + lane16) = x;
+        }
+    };
+    // Wait accounting (vector-memory operations complete in issue order): in
+    // the loop, fields 0-2 of a tile are followed by its fields 3-5 (D3 copies)
+    // and the previous tile's S stores, fields 3-5 by those stores.  The
+    // prologue reproduces that order by writing zeros to the first tile's
+    // output (overwritten by the same threads later).  Requests are issued
+    // unconditionally (the last tile re-requests itself) and the first pair of
+    // the next tile is read at the end of the loop body, so that every read of
+    // a staging buffer sees one fixed history of copies.
+    request(slot0, t0, 0);
+    request(slot1, t0, 3);
+    store_tile(t0, true);
+    wait_vm<C::D3 + C::S>();                                   // fields 0-2 of the first tile
+    lds_barrier();
+    gather(v, slot0, slot0 + RW);
+    for (int tile = t0; tile < t1; tile++) {
+        const bool more = tile + 1 < t1;
+        P ph[6][E];
+        line_fft<P, N, E, T, +1, true>(v, lds, l, t, twl);
+#pragma unroll
+        for (int s = 0; s < E; s++) { ph[0][s] = v[s].re; ph[1][s] = v[s].im; }
+        wait_vm<C::S>();                                       // fields 3-5
+        lds_barrier();
+        gather(v, slot0 + 2 * RW, slot1);
+        lds_barrier();                                         // slot0 read by every wave
+        request(slot0, more ? tile + 1 : tile, 0);
+        line_fft<P, N, E, T, +1, true>(v, lds, l, t, twl);
+#pragma unroll
+        for (int s = 0; s < E; s++) { ph[2][s] = v[s].re; ph[3][s] = v[s].im; }
+        gather(v, slot1 + RW, slot1 + 2 * RW);
+        lds_barrier();                                         // slot1 read by every wave
+        request(slot1, more ? tile + 1 : tile, 3);
+        line_fft<P, N, E, T, +1, true>(v, lds, l, t, twl);
+#pragma unroll
+        for (int s = 0; s < E; s++) { ph[4][s] = v[s].re; ph[5][s] = v[s].im; }
+        // ph: 0 u_x, 1 u_y, 2 u_z, 3 omega_x, 4 omega_y, 5 omega_z
+        if (stage == 0) {
+#pragma unroll
+            for (int s = 0; s < E; s++) {
+                const P a = fabs(ph[0][s]) + fabs(ph[1][s]) + fabs(ph[2][s]);
+                umx = a > umx ? a : umx;
+            }
+        }
+        Cx<P> d1[E], d2[E];
+#pragma unroll
+        for (int s = 0; s < E; s++) {
+            d1[s] = {ph[1][s] * ph[5][s] - ph[2][s] * ph[4][s], ph[2][s] * ph[3][s] - ph[0][s] * ph[5][s]};
+            d2[s] = {ph[0][s] * ph[4][s] - ph[1][s] * ph[3][s], P(0)};
+        }
+        line_fft_T<P, N, E, T, -1, true>(d1, lds, l, t, twl);        // d1[m] = D1[t + M m]
+        line_fft_T<P, N, E, T, -1, true>(d2, lds, l, t, twl);
+        lds_barrier();
+#pragma unroll
+        for (int m = 0; m < E; m++) lds_put<P>(lds, (t + M * m) * T + l, d1[m]);
+        lds_barrier();
+        // split D1 into the x-spectra of n_x and n_y
+        Cx<P> ox[E], oy[E];
+#pragma unroll
+        for (int m = 0; m < E; m++) {
+            const int k = t + M * m;
+            if (M * m <= K && (M * m + M - 1 <= K || k <= K)) {
+                const Cx<P> a = d1[m];
+                const Cx<P> b = lds_get<P>(lds, ((N - k) % N) * T + l);
+                const P h = P(0.5);
+                ox[m] = {h * (a.re + b.re), h * (a.im - b.im)};
+                oy[m] = {h * (a.im + b.im), h * (b.re - a.re)};
+            }
+        }
+        lds_barrier();                                         // partner reads done
+#pragma unroll
+        for (int m = 0; m < E; m++) {
+            const int k = t + M * m;
+            if (M * m <= K && (M * m + M - 1 <= K || k <= K)) {
+                lds_put<P>(lds, l * (K + 1) + k, ox[m]);
+                lds_put<P>(lds, RW + l * (K + 1) + k, oy[m]);
+                lds_put<P>(lds, 2 * RW + l * (K + 1) + k, d2[m]);
+            }
+        }
+        lds_barrier();
+        store_tile(tile, false);
+        if (more) {                                            // first pair of the next tile
+            wait_vm<C::D3 + C::S>();                           // its fields 0-2 precede 3-5 and the stores
+            lds_barrier();
+            gather(v, slot0, slot0 + RW);
+        }
+    }
+    wait_vm<0>();                                              // no copy into LDS outlives the workgroup
+    if (stage == 0) {
+        double dm = (double)umx;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double o = __shfl_xor(dm, off, 64);
+            dm = o > dm ? o : dm;
+        }
+        if ((threadIdx.x & 63) == 0) atomicMax(&md.st->umax_bits, (unsigned long long)__double_as_longlong(dm));
+    }
+}
+
 // ================================================================== yfwd
 // y-lines L = z (K+1) + kx.  in bufA [3][N][N][K+1]; out bufB [3][N (z)][2K+1][K+1]
 template <typename P, int N, int EV>
@@ -586,12 +793,36 @@ static hipError_t run_pencil(int pass, const MemberDev *mem, int count, int stag
     return hipGetLastError();
 }
 
+// Persistent pipelined x pass: as many workgroups as stay resident on the
+// device (occupancy times compute units), split evenly over the members.
+template <typename P, int N, int EV>
+static hipError_t run_xpass_dma(const MemberDev *mem, int count, int stage, const Cx<P> *tw, hipStream_t s) {
+    using C = XCfg<P, N, EV>;
+    static int resident = 0;                                   // workgroups per device (first call)
+    if (resident == 0) {
+        int dev = 0, cus = 0, occ = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_xpass_dma<P, N, EV>, C::NTH, 0);
+        if (e != hipSuccess) return e;
+        resident = (cus > 0 ? cus : 1) * (occ > 0 ? occ : 1);
+    }
+    int per = resident / (count > 0 ? count : 1);
+    per = per < 1 ? 1 : (per > C::TILES ? C::TILES : per);
+    k_xpass_dma<P, N, EV><<<dim3((unsigned)per, count), C::NTH, 0, s>>>(mem, tw, stage);
+    return hipGetLastError();
+}
+
 template <typename P, int N>
 static hipError_t run_pass(int pass, int variant, const MemberDev *mem, int count, int stage, const void *tw, hipStream_t s) {
     using C = Cfg<P, N, 8>;
     const Cx<P> *twp = reinterpret_cast<const Cx<P> *>(tw);
     switch (pass) {
     case P_ZINV: case P_YINV: case P_XPASS: case P_YFWD:
+        if (pass == P_XPASS && variant == 2) {
+            if constexpr (N >= 64) return run_xpass_dma<P, N, 8>(mem, count, stage, twp, s);
+            else return run_pencil<P, N, 8>(pass, mem, count, stage, twp, s);   // lines too short to stream
+        }
         return variant == 1 ? run_pencil<P, N, 16>(pass, mem, count, stage, twp, s)
                             : run_pencil<P, N, 8>(pass, mem, count, stage, twp, s);
     case P_ZFWD:
@@ -632,11 +863,13 @@ hipError_t launch_pass(int pass, int variant, int n, int prec, const MemberDev *
                             : dispatch_n<double>(n, pass, variant, mem, count, stage, tw, s);
 }
 
-int pass_variants(int pass) { return (pass == P_ZINV || pass == P_YINV || pass == P_XPASS || pass == P_YFWD) ? 2 : 1; }
+int pass_variants(int pass) {
+    if (pass == P_XPASS) return 3;
+    return (pass == P_ZINV || pass == P_YINV || pass == P_YFWD) ? 2 : 1;
+}
 
 int default_variant(int pass, int n, int prec) {
-    (void)n;
-    if (pass == P_XPASS) return 0;                              // 8 values per thread
+    if (pass == P_XPASS) return n >= 64 ? 2 : 0;               // streamed, 8 values per thread
     if (pass == P_ZINV || pass == P_YINV || pass == P_YFWD) return prec == ENS_FP32 ? 1 : 0;
     return 0;
 }
