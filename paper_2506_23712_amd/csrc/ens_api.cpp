@@ -97,7 +97,7 @@ struct Layout {
 };
 
 Layout member_layout(const ens_member_desc &d, const HistGeom *hg) {
-    const Geom g = make_geom(d.n);
+    const Geom g = make_geom(d.n, d.precision);
     const size_t cs = d.precision == ENS_FP32 ? 8 : 16;
     const long long n = d.n;
     Layout L;
@@ -107,7 +107,7 @@ Layout member_layout(const ens_member_desc &d, const HistGeom *hg) {
     L.off_q = o; o += align256(3 * (size_t)g.S * cs);
     const size_t a_elems = std::max((size_t)6 * n * g.nzl, (size_t)3 * n * n * (g.K + 1));
     L.off_a = o; o += align256(a_elems * cs);
-    L.off_b = o; o += align256((size_t)9 * n * n * (g.K + 1) * cs);
+    L.off_b = o; o += align256((size_t)9 * n * n * g.px * cs);
     const size_t nparts = std::max({(size_t)(2 * zfwd_blocks(d.n, d.precision)), (size_t)init_blocks(d.n),
                                     (size_t)(ENS_NMOM * xstats_blocks(d.n))});
     L.off_part = o; o += align256(nparts * sizeof(double));
@@ -391,7 +391,7 @@ ENS_API ens_status ens_member_init(ens_ctx *ctx, const ens_member_desc *d, void 
     hipStream_t s = (hipStream_t)stream;
     auto m = std::make_unique<Member>();
     m->d = *d;
-    m->g = make_geom(d->n);
+    m->g = make_geom(d->n, d->precision);
     m->lay = lay;
     m->ws = dev_workspace;
     char *base = (char *)dev_workspace;
@@ -413,6 +413,7 @@ ENS_API ens_status ens_member_init(ens_ctx *ctx, const ens_member_desc *d, void 
     md.box = d->box;
     md.dk = 2.0 * M_PI / d->box;
     md.n = d->n; md.K = d->n / 3; md.prec = d->precision; md.visc_mode = d->visc_mode;
+    md.px = m->g.px; md.pad_ = 0;
     void *p = nullptr;
     HIPCK(ctx, hipMalloc(&p, sizeof(MemberDev)));
     m->dev = (MemberDev *)p;

@@ -27,35 +27,52 @@ struct DevState {
     double pad[4];
 };
 
+// Pitch of the x-mode (fastest) index of the pencil buffers that a pass
+// writes in runs of one 128-byte line per position (the z- and y-inverse
+// outputs and the y-forward output): K + 1 rounded up to whole lines (16 FP32
+// / 8 FP64 complex values), the pad entries written as zeros, so that every
+// store covers whole lines.  A line shared by two workgroups, each writing
+// part of it, is written back twice at far lower bandwidth.  `cbytes` is the
+// size of one complex value.  Where the padding would exceed 1/8 of a row
+// (short rows: n <= 64 FP32, n <= 32 FP64) the rows are left unpadded.
+__host__ __device__ constexpr int kx_pitch(int K, int cbytes) {
+    const int per = 128 / cbytes, px = (K + 1 + per - 1) / per * per;
+    return 8 * (px - (K + 1)) <= K + 1 ? px : K + 1;
+}
+
 // Everything a kernel needs to know about one member (lives in a device
 // table owned by the library; pointers refer to the caller's workspace).
+// PX = kx_pitch(K, complex size).  Layouts (x-mode index fastest):
 struct MemberDev {
     void *uh;          // velocity  [3][2K+1 (kz)][2K+1 (ky)][K+1 (kx)] complex
     void *q;           // RK register, same layout
-    void *bufA;        // [F][n (z)][2K+1][K+1] (z-inverse out) / [3][n][n][K+1] (x-pass out)
-    void *bufB;        // [F][n (z)][n (y)][K+1] (y-inverse out) / [3][n][2K+1][K+1] (y-forward out)
+    void *bufA;        // [F][n (z)][2K+1][PX] (z-inverse out) / [3][n][n][K+1] (x-pass out, linear stores)
+    void *bufB;        // [F][n (z)][n (y)][PX] (y-inverse out) / [3][n][2K+1][PX] (y-forward out)
     DevState *st;
     double *partials;  // per-workgroup FP64 partial sums
     unsigned long long *counts;   // statistics counters
     double *moments;              // ENS_NMOM sums
     double nu, eps_m, kf_lo2, kf_hi2, dt_fixed, cfl, box, dk;
     int n, K, prec, visc_mode;
+    int px;            // x-mode pitch PX
+    int pad_;
 };
 
 // Host-visible geometry of one member.
 struct Geom {
-    int n, K;
-    long long nzl;     // z-lines = (2K+1)(K+1)
-    long long S;       // retained modes per component = (2K+1) nzl
-    long long nyl;     // y-lines = n (K+1)
+    int n, K, px;
+    long long nzl;     // z-lines of the pencil buffers = (2K+1) PX (pad lines included)
+    long long S;       // retained modes per component = (2K+1)^2 (K+1)
+    long long nyl;     // y-lines of the pencil buffers = n PX
 };
 
-inline Geom make_geom(int n) {
+inline Geom make_geom(int n, int prec) {
     Geom g;
     g.n = n; g.K = n / 3;
-    g.nzl = (long long)(2 * g.K + 1) * (g.K + 1);
-    g.S = (long long)(2 * g.K + 1) * g.nzl;
-    g.nyl = (long long)n * (g.K + 1);
+    g.px = kx_pitch(g.K, prec == ENS_FP32 ? 8 : 16);
+    g.nzl = (long long)(2 * g.K + 1) * g.px;
+    g.S = (long long)(2 * g.K + 1) * (2 * g.K + 1) * (g.K + 1);
+    g.nyl = (long long)n * g.px;
     return g;
 }
 

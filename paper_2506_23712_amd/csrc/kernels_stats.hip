@@ -21,13 +21,15 @@ __device__ __forceinline__ int mode_of(int n, int N) { return n <= N / 2 ? n : n
 
 template <typename P, int N, int EV> struct SCfg {
     static constexpr int K = N / 3;
-    static constexpr int NZL = (2 * K + 1) * (K + 1);
-    static constexpr int S = (2 * K + 1) * NZL;
-    static constexpr int NYL = N * (K + 1);
+    static constexpr int PX = kx_pitch(K, (int)sizeof(Cx<P>));   // x-mode pitch (whole 128-byte lines)
+    static constexpr int NZL = (2 * K + 1) * PX;                  // z-lines of a pencil buffer
+    static constexpr int NZLS = (2 * K + 1) * (K + 1);            // z-lines of the state
+    static constexpr int S = (2 * K + 1) * NZLS;
+    static constexpr int NYL = N * PX;
     static constexpr int E = EV > N ? N : EV, M = N / E;
     static constexpr int TL = 128 / (int)sizeof(Cx<P>);       // lines for 128-byte runs
     static constexpr int MAXT = E >= 16 ? 512 : 1024;
-    static constexpr int T = N <= 256 ? 256 / M : (TL * M <= MAXT ? TL : MAXT / M);
+    static constexpr int T = N <= 256 ? (256 / M > TL ? 256 / M : TL) : (TL * M <= MAXT ? TL : MAXT / M);
     static constexpr int NT = T * M;
 };
 
@@ -46,7 +48,8 @@ __device__ __forceinline__ void gload_trunc(Cx<P> *v, const Fld<P> &f, uint32_t 
 }
 
 // ------------------------------------------------------------------ gzinv
-// out bufA [6][N][NZL]: U_c = Z^-1[u_c] (fields 0..2), W_c = Z^-1[i k_z u_c] (3..5)
+// in u_hat [3][2K+1][2K+1][K+1]; out bufA [6][N][NZL]: U_c = Z^-1[u_c] (fields
+// 0..2), W_c = Z^-1[i k_z u_c] (3..5); pad lines (kx > K) carry zeros
 template <typename P, int N>
 __global__ void __launch_bounds__((SCfg<P, N, grad_e<P>()>::NT)) k_gzinv(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw) {
     using C = SCfg<P, N, grad_e<P>()>;
@@ -57,20 +60,23 @@ __global__ void __launch_bounds__((SCfg<P, N, grad_e<P>()>::NT)) k_gzinv(const M
     const MemberDev &md = mems[mem_i];
     const int l = threadIdx.x % T, t = threadIdx.x / T;
     const int L = tile * T + l;
-    const bool valid = L < NZL;
+    const bool inb = L < NZL;
+    const int kx = L % C::PX, iy = L / C::PX;
+    const bool valid = inb && kx <= C::K;
+    const uint32_t Ls = valid ? (uint32_t)(iy * (C::K + 1) + kx) : 0u;   // the line in the state
     const P dk = (P)md.dk;
     auto store = [&](const Cx<P> *v, int f) {
-        if (valid) {
+        if (inb) {
             const Fld<P> o(md.bufA, (long long)f * N * NZL);
 #pragma unroll
             for (int s = 0; s < E; s++) o.st((uint32_t)Plan<N, E>::out_pos(t, s) * NZL + L, v[s]);
         }
     };
     Cx<P> a[E], b[E], p[E];
-    gload_trunc<P, N, E>(a, Fld<P>(md.uh, 0), L, NZL, t, valid);
+    gload_trunc<P, N, E>(a, Fld<P>(md.uh, 0), Ls, C::NZLS, t, valid);
 #pragma unroll
     for (int c = 0; c < 3; c++) {
-        if (c < 2) gload_trunc<P, N, E>(p, Fld<P>(md.uh, (long long)(c + 1) * C::S), L, NZL, t, valid);
+        if (c < 2) gload_trunc<P, N, E>(p, Fld<P>(md.uh, (long long)(c + 1) * C::S), Ls, C::NZLS, t, valid);
 #pragma unroll
         for (int m = 0; m < E; m++) b[m] = mul_i(cscale(a[m], dk * (P)mode_of(t + M * m, N)));
         line_fft<P, N, E, T, +1>(b, lds, l, t, tw);
@@ -85,7 +91,7 @@ __global__ void __launch_bounds__((SCfg<P, N, grad_e<P>()>::NT)) k_gzinv(const M
 }
 
 // ------------------------------------------------------------------ gyinv
-// out bufB [9][N][N][K+1]: U_c (0..2), V_c = d_y u_c (3..5), W_c = d_z u_c (6..8)
+// out bufB [9][N][N][PX]: U_c (0..2), V_c = d_y u_c (3..5), W_c = d_z u_c (6..8)
 template <typename P, int N>
 __global__ void __launch_bounds__((SCfg<P, N, grad_e<P>()>::NT)) k_gyinv(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw) {
     using C = SCfg<P, N, grad_e<P>()>;
@@ -95,21 +101,23 @@ __global__ void __launch_bounds__((SCfg<P, N, grad_e<P>()>::NT)) k_gyinv(const M
     xcd_tile(tile, mem_i);
     const MemberDev &md = mems[mem_i];
     const int l = threadIdx.x % T, t = threadIdx.x / T;
+    constexpr int PX = C::PX;
     const int L = tile * T + l;
-    const bool valid = L < C::NYL;
-    const int z = valid ? L / (K + 1) : 0;
-    const int kx = valid ? L % (K + 1) : 0;
+    const bool inb = L < C::NYL;
+    const int z = inb ? L / PX : 0;
+    const int kx = inb ? L % PX : 0;
+    const bool valid = inb && kx <= K;
     const P dk = (P)md.dk;
     const uint32_t in_base = (uint32_t)z * NZL + kx;
-    const uint32_t out_base = (uint32_t)z * N * (K + 1) + kx;
+    const uint32_t out_base = (uint32_t)z * N * PX + kx;
     auto load = [&](Cx<P> *v, int f) {
-        gload_trunc<P, N, E>(v, Fld<P>(md.bufA, (long long)f * N * NZL), in_base, K + 1, t, valid);
+        gload_trunc<P, N, E>(v, Fld<P>(md.bufA, (long long)f * N * NZL), in_base, PX, t, valid);
     };
     auto store = [&](const Cx<P> *v, int f) {
-        if (valid) {
-            const Fld<P> o(md.bufB, (long long)f * N * N * (K + 1));
+        if (inb) {
+            const Fld<P> o(md.bufB, (long long)f * N * N * PX);
 #pragma unroll
-            for (int s = 0; s < E; s++) o.st(out_base + (uint32_t)Plan<N, E>::out_pos(t, s) * (K + 1), v[s]);
+            for (int s = 0; s < E; s++) o.st(out_base + (uint32_t)Plan<N, E>::out_pos(t, s) * PX, v[s]);
         }
     };
     Cx<P> a[E], b[E], p[E];
@@ -184,7 +192,8 @@ __device__ __forceinline__ int slot_1d(int b, int nb) { return b >= 0 ? b : (b =
 template <typename P, int N>
 __global__ void __launch_bounds__(256, 2) k_gxstats(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw, HistArgs h) {
     constexpr int E = 4, M = N / E, T = 256 / M, K = N / 3;
-    constexpr long long FS = (long long)N * N * (K + 1);
+    constexpr int PX = kx_pitch(K, (int)sizeof(Cx<P>));
+    constexpr long long FS = (long long)N * N * PX;
     extern __shared__ double dyn[];                         // log edges, 1-D histograms, QR window
     double *ledge = dyn;
     unsigned int *hs = (unsigned int *)(dyn + h.lb + 1);
@@ -236,7 +245,7 @@ __global__ void __launch_bounds__(256, 2) k_gxstats(const MemberDev *__restrict_
     const int ntiles = N * N / T;
     __syncthreads();
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const uint32_t rb = (uint32_t)(tile * T + l) * (K + 1);
+        const uint32_t rb = (uint32_t)(tile * T + l) * PX;
         auto spec = [&](int f, uint32_t kx) -> Cx<P> {
             const int c = f / 3, j = f % 3;
             if (j == 0) return mul_i(cscale(Fld<P>(md.bufB, c * FS).ld(rb + kx), dk * (P)kx));

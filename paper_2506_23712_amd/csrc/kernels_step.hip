@@ -44,18 +44,21 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
 // (pass, N, precision) from its tuning table.
 template <typename P, int N, int E_> struct Cfg {
     static constexpr int K = N / 3;
-    static constexpr int NZL = (2 * K + 1) * (K + 1);           // z-lines
-    static constexpr int S = (2 * K + 1) * NZL;                 // modes per component
-    static constexpr int NYL = N * (K + 1);                     // y-lines
+    static constexpr int PX = kx_pitch(K, (int)sizeof(Cx<P>));  // x-mode pitch of the pencil buffers
+    static constexpr int NZL = (2 * K + 1) * PX;                // z-lines of a pencil buffer (pad lines included)
+    static constexpr int NZLS = (2 * K + 1) * (K + 1);          // z-lines of the state
+    static constexpr int S = (2 * K + 1) * NZLS;                // retained modes per component
+    static constexpr int NYL = N * PX;                          // y-lines
     static constexpr int E = E_ > N ? N : E_;
     static constexpr int M = N / E;
-    // Lines per workgroup of the y/z pencil passes: 256 threads up to N = 256;
-    // for longer lines, enough lines for 128-byte runs per position (16 FP32 /
-    // 8 FP64), at most 1024 threads (512 with 16 values per thread, so that a
-    // wave may use 256 VGPRs); gfx950 gives a workgroup up to 160 KiB of LDS.
+    // Lines per workgroup of the y/z pencil passes: at least 256 threads and
+    // at least one 128-byte line per position (16 FP32 / 8 FP64 consecutive
+    // lines), so that every store covers whole lines; at most 1024 threads (512
+    // with 16 values per thread, so that a wave may use 256 VGPRs); gfx950
+    // gives a workgroup up to 160 KiB of LDS.
     static constexpr int TL = 128 / (int)sizeof(Cx<P>);
     static constexpr int MAXT = E >= 16 ? 512 : 1024;             // 16 values/thread: keep 256 VGPRs available
-    static constexpr int T = N <= 256 ? 256 / M : (TL * M <= MAXT ? TL : MAXT / M);
+    static constexpr int T = N <= 256 ? (256 / M > TL ? 256 / M : TL) : (TL * M <= MAXT ? TL : MAXT / M);
     static constexpr int NT = T * M;
     static constexpr int TX = 256 / M;                          // x pass: 256 threads
     // z forward + update: 8 values per thread, 512 threads up to N = 256;
@@ -122,8 +125,9 @@ __device__ __forceinline__ void load_trunc(Cx<P> *v, const Fld<P> &f, uint32_t b
 }
 
 // ================================================================== zinv
-// z-lines L = iy (K+1) + kx of the retained (m_y, m_x) pairs.
-// out (bufA) [5][N (z)][NZL]: U_x, U_y, U_z, W_x = Z^-1[i k_z u_x], W_y = Z^-1[i k_z u_y]
+// z-lines L = iy PX + kx of the output (m_y, m_x) pairs; pad lines (kx > K)
+// carry zeros.  in u_hat [3][2K+1][2K+1][K+1]; out (bufA) [5][N (z)][NZL]:
+// U_x, U_y, U_z, W_x = Z^-1[i k_z u_x], W_y = Z^-1[i k_z u_y]
 template <typename P, int N, int EV>
 __global__ void __launch_bounds__((Cfg<P, N, EV>::NT)) k_zinv(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw) {
     using C = Cfg<P, N, EV>;
@@ -134,19 +138,22 @@ __global__ void __launch_bounds__((Cfg<P, N, EV>::NT)) k_zinv(const MemberDev *_
     const MemberDev &md = mems[mem_i];
     const int l = threadIdx.x % T, t = threadIdx.x / T;
     const int L = tile * T + l;
-    const bool valid = L < NZL;
+    const bool inb = L < NZL;                                   // output line (written)
+    const int kx = L % C::PX, iy = L / C::PX;
+    const bool valid = inb && kx <= C::K;                       // retained line (read)
+    const uint32_t Ls = valid ? (uint32_t)(iy * (C::K + 1) + kx) : 0u;   // the line in the state
     const P dk = (P)md.dk;
     auto kz = [&](int m) { return dk * (P)mode_of(t + M * m, N); };
     auto store = [&](const Cx<P> *v, int f) {
-        if (valid) {
+        if (inb) {
             const Fld<P> o(md.bufA, (long long)f * N * NZL);
 #pragma unroll
             for (int s = 0; s < E; s++) o.st((uint32_t)Plan<N, E>::out_pos(t, s) * NZL + L, v[s]);
         }
     };
     Cx<P> a[E], b[E], p[E];
-    load_trunc<P, N, E>(a, Fld<P>(md.uh, 0), L, NZL, t, valid);
-    load_trunc<P, N, E>(p, Fld<P>(md.uh, C::S), L, NZL, t, valid);
+    load_trunc<P, N, E>(a, Fld<P>(md.uh, 0), Ls, C::NZLS, t, valid);
+    load_trunc<P, N, E>(p, Fld<P>(md.uh, C::S), Ls, C::NZLS, t, valid);
 #pragma unroll
     for (int m = 0; m < E; m++) b[m] = mul_i(cscale(a[m], kz(m)));
     line_fft<P, N, E, T, +1>(b, lds, l, t, tw);
@@ -155,7 +162,7 @@ __global__ void __launch_bounds__((Cfg<P, N, EV>::NT)) k_zinv(const MemberDev *_
     store(a, 0);
 #pragma unroll
     for (int m = 0; m < E; m++) a[m] = p[m];
-    load_trunc<P, N, E>(p, Fld<P>(md.uh, 2 * C::S), L, NZL, t, valid);
+    load_trunc<P, N, E>(p, Fld<P>(md.uh, 2 * C::S), Ls, C::NZLS, t, valid);
 #pragma unroll
     for (int m = 0; m < E; m++) b[m] = mul_i(cscale(a[m], kz(m)));
     line_fft<P, N, E, T, +1>(b, lds, l, t, tw);
@@ -167,8 +174,8 @@ __global__ void __launch_bounds__((Cfg<P, N, EV>::NT)) k_zinv(const MemberDev *_
 }
 
 // ================================================================== yinv
-// y-lines L = z (K+1) + kx.  in bufA [5][N][NZL]; out bufB [6][N (z)][N (y)][K+1]:
-// u_x, u_y, u_z, omega_x, omega_y, omega_z
+// y-lines L = z PX + kx.  in bufA [5][N][NZL]; out bufB [6][N (z)][N (y)][PX]:
+// u_x, u_y, u_z, omega_x, omega_y, omega_z (pad lines kx > K carry zeros)
 template <typename P, int N, int EV>
 __global__ void __launch_bounds__((Cfg<P, N, EV>::NT)) k_yinv(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw) {
     using C = Cfg<P, N, EV>;
@@ -179,22 +186,24 @@ __global__ void __launch_bounds__((Cfg<P, N, EV>::NT)) k_yinv(const MemberDev *_
     const MemberDev &md = mems[mem_i];
     const int l = threadIdx.x % T, t = threadIdx.x / T;
     const int L = tile * T + l;
-    const bool valid = L < C::NYL;
-    const int z = valid ? L / (K + 1) : 0;
-    const int kx = valid ? L % (K + 1) : 0;
+    constexpr int PX = C::PX;
+    const bool inb = L < C::NYL;
+    const int z = inb ? L / PX : 0;
+    const int kx = inb ? L % PX : 0;
+    const bool valid = inb && kx <= K;
     const P dk = (P)md.dk;
     const P kxv = dk * (P)kx;
-    const uint32_t in_base = (uint32_t)z * NZL + kx;             // + iy (K+1)
-    const uint32_t out_base = (uint32_t)z * N * (K + 1) + kx;    // + y (K+1)
+    const uint32_t in_base = (uint32_t)z * NZL + kx;             // + iy PX
+    const uint32_t out_base = (uint32_t)z * N * PX + kx;         // + y PX
     auto ky = [&](int m) { return dk * (P)mode_of(t + M * m, N); };
     auto load = [&](Cx<P> *v, int f) {
-        load_trunc<P, N, E>(v, Fld<P>(md.bufA, (long long)f * N * NZL), in_base, K + 1, t, valid);
+        load_trunc<P, N, E>(v, Fld<P>(md.bufA, (long long)f * N * NZL), in_base, PX, t, valid);
     };
     auto store = [&](const Cx<P> *v, int f) {
-        if (valid) {
-            const Fld<P> o(md.bufB, (long long)f * N * N * (K + 1));
+        if (inb) {
+            const Fld<P> o(md.bufB, (long long)f * N * N * PX);
 #pragma unroll
-            for (int s = 0; s < E; s++) o.st(out_base + (uint32_t)Plan<N, E>::out_pos(t, s) * (K + 1), v[s]);
+            for (int s = 0; s < E; s++) o.st(out_base + (uint32_t)Plan<N, E>::out_pos(t, s) * PX, v[s]);
         }
     };
     Cx<P> a[E], b[E], p[E];
@@ -233,7 +242,7 @@ __global__ void __launch_bounds__((Cfg<P, N, EV>::NT)) k_yinv(const MemberDev *_
 }
 
 // ================================================================== xpass
-// Rows R = z N + y.  in bufB [6][N][N][K+1]; out bufA [3][N][N][K+1] = x-transform
+// Rows R = z N + y.  in bufB [6][N][N][PX]; out bufA [3][N][N][K+1] = x-transform
 // (unnormalised) of n = u x omega, truncated to m_x <= K.
 // The T rows of a workgroup are contiguous in every field, so inputs are
 // copied into LDS (and outputs out of it) with linear, fully coalesced
@@ -242,9 +251,11 @@ __global__ void __launch_bounds__((Cfg<P, N, EV>::NT)) k_yinv(const MemberDev *_
 template <typename P, int N, int EV>
 __global__ void __launch_bounds__(256) k_xpass(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw, int stage) {
     using C = Cfg<P, N, EV>;
-    constexpr int E = C::E, M = C::M, T = C::TX, K = C::K;
-    constexpr long long FS = (long long)N * N * (K + 1);      // elements per field
-    constexpr int RW = T * (K + 1);                            // elements of the tile per field
+    constexpr int E = C::E, M = C::M, T = C::TX, K = C::K, PX = C::PX;
+    constexpr long long FS = (long long)N * N * PX;           // elements per input field
+    constexpr long long FSO = (long long)N * N * (K + 1);     // elements per output field
+    constexpr int RW = T * PX;                                 // elements of the tile per input field
+    constexpr int RWO = T * (K + 1);                           // elements of the tile per output field
     constexpr int PER = (RW + 255) / 256;                      // staged elements per thread per field
     __shared__ LdsT<P> lds[N * T];
     __shared__ LdsT<P> sb[2 * RW];                             // staged pair / two output fields
@@ -283,7 +294,7 @@ __global__ void __launch_bounds__(256) k_xpass(const MemberDev *__restrict__ mem
             const bool lo = n <= K, hi = n >= N - K;
             const int kx = lo ? n : N - n;
             Cx<P> A = czero<P>(), B = czero<P>();
-            if (lo || hi) { A = lds_get<P>(sb, l * (K + 1) + kx); B = lds_get<P>(sb, RW + l * (K + 1) + kx); }
+            if (lo || hi) { A = lds_get<P>(sb, l * PX + kx); B = lds_get<P>(sb, RW + l * PX + kx); }
             if (n == 0) v[m] = {A.re, B.re};
             else if (lo) v[m] = {A.re - B.im, A.im + B.re};
             else v[m] = {A.re + B.im, B.re - A.im};            // zero pairs stay zero
@@ -362,19 +373,20 @@ __global__ void __launch_bounds__(256) k_xpass(const MemberDev *__restrict__ mem
         const int k = t + M * m;
         if (k <= K) {
             lds_put<P>(sb, l * (K + 1) + k, ox[m]);
-            lds_put<P>(sb, RW + l * (K + 1) + k, oy[m]);
+            lds_put<P>(sb, RWO + l * (K + 1) + k, oy[m]);
             lds_put<P>(lds, l * (K + 1) + k, d2[m]);
         }
     }
     __syncthreads();
-    const Fld<P> o0(md.bufA, 0), o1(md.bufA, FS), o2(md.bufA, 2 * FS);
+    const Fld<P> o0(md.bufA, 0), o1(md.bufA, FSO), o2(md.bufA, 2 * FSO);
+    const uint32_t tbo = tile * RWO;
 #pragma unroll
-    for (int i = 0; i < PER; i++) {
+    for (int i = 0; i < (RWO + 255) / 256; i++) {
         const int e = threadIdx.x + 256 * i;
-        if (e < RW) {
-            o0.st(tb + e, lds_get<P>(sb, e));
-            o1.st(tb + e, lds_get<P>(sb, RW + e));
-            o2.st(tb + e, lds_get<P>(lds, e));
+        if (e < RWO) {
+            o0.st(tbo + e, lds_get<P>(sb, e));
+            o1.st(tbo + e, lds_get<P>(sb, RWO + e));
+            o2.st(tbo + e, lds_get<P>(lds, e));
         }
     }
 }
@@ -392,11 +404,13 @@ __global__ void __launch_bounds__(256) k_xpass(const MemberDev *__restrict__ mem
 template <typename P, int N, int E_> struct XCfg {
     static constexpr int K = N / 3, E = E_ > N ? N : E_, M = N / E;
     static constexpr int CS = (int)sizeof(Cx<P>), CPV = 16 / CS;
+    static constexpr int PX = kx_pitch(K, CS);                 // row pitch in HBM
+    static constexpr int RQ = (K + 1 + CPV - 1) / CPV * CPV;   // row length staged in LDS (whole vectors)
     static constexpr int NTW = twiddle_span(N, E);
     static constexpr long long lds_bytes(int t) {
-        const long long rw = (long long)t * (K + 1);
-        const long long xl = (long long)N * t > 3 * rw ? (long long)N * t : 3 * rw;
-        return (6 * rw + xl + NTW) * CS + 64;
+        const long long rs = (long long)t * RQ, ro = (long long)t * (K + 1);
+        const long long xl = (long long)N * t > 3 * ro ? (long long)N * t : 3 * ro;
+        return (6 * rs + xl + NTW) * CS + 64;
     }
     // rows per tile: the most (at most 256 threads) whose LDS lets three
     // workgroups share a compute unit, else the fewest with one full wave
@@ -406,25 +420,31 @@ template <typename P, int N, int E_> struct XCfg {
         return t < 1 ? 1 : t;
     }
     static constexpr int T = pick_t(), NTH = M * T;
-    static constexpr int RW = T * (K + 1);                 // elements of a tile per field
-    static constexpr int RV = RW / CPV;                    // 16-byte vectors per field tile
+    static constexpr int RW = T * RQ;                      // staged elements of a tile per field
+    static constexpr int RVR = RQ / CPV;                   // 16-byte vectors read per row
+    static constexpr int RV = T * RVR;                     // vectors read per field tile
+    static constexpr int RWO = T * (K + 1);                // elements written per field tile (rows of K + 1)
+    static constexpr int RVO = RWO / CPV;
     static constexpr int D3 = dma_tile3_ops<RV, NTH>();     // copies per wave per staging buffer
-    static constexpr int S = D3;                           // 16-byte stores per wave per tile (same chunks)
-    static constexpr int XL = N * T > 3 * RW ? N * T : 3 * RW;
+    static constexpr int S = dma_tile3_ops<RVO, NTH>();     // 16-byte stores per wave per tile
+    static constexpr int XL = N * T > 3 * RWO ? N * T : 3 * RWO;
     static constexpr int TILES = N * N / T;
     // workgroups per compute unit the register budget is cut for: what the LDS
     // allows, up to 3 waves per SIMD (FP32) or 2 (FP64)
     static constexpr int MINB_LDS = (int)(163840 / ((lds_bytes(T) + 511) / 512 * 512));
     static constexpr int MINB_VGPR = (sizeof(P) == 4 ? 12 : 8) / (NTH / 64);
     static constexpr int MINB = MINB_LDS < MINB_VGPR ? MINB_LDS : MINB_VGPR;
-    static_assert(RW % CPV == 0 && NTH % 64 == 0 && RV >= 64 && D3 + S < 64, "x-pass tile shape");
+    static_assert(PX % CPV == 0 && RWO % CPV == 0 && NTH % 64 == 0 && RV >= 64 && RVO >= 64 && D3 + S < 64,
+                  "x-pass tile shape");
 };
 
 template <typename P, int N, int EV>
 __global__ void __launch_bounds__((XCfg<P, N, EV>::NTH), (XCfg<P, N, EV>::MINB)) k_xpass_dma(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw, int stage) {
     using C = XCfg<P, N, EV>;
-    constexpr int E = C::E, M = C::M, T = C::T, K = C::K, NTH = C::NTH, RW = C::RW, RV = C::RV;
-    constexpr long long FSB = (long long)N * N * (K + 1) * C::CS;    // bytes per field
+    constexpr int E = C::E, M = C::M, T = C::T, K = C::K, NTH = C::NTH, RW = C::RW, RQ = C::RQ;
+    constexpr int PX = C::PX, RWO = C::RWO, RVO = C::RVO;
+    constexpr long long FSB = (long long)N * N * PX * C::CS;         // bytes per input field
+    constexpr long long FSBO = (long long)N * N * (K + 1) * C::CS;   // bytes per output field
     __shared__ __attribute__((aligned(16))) LdsT<P> slot0[3 * RW];
     __shared__ __attribute__((aligned(16))) LdsT<P> slot1[3 * RW];
     __shared__ __attribute__((aligned(16))) LdsT<P> lds[C::XL];
@@ -439,8 +459,8 @@ __global__ void __launch_bounds__((XCfg<P, N, EV>::NTH), (XCfg<P, N, EV>::MINB))
     for (int i = (int)threadIdx.x; i < C::NTW; i += NTH) twl[i] = tw[i];
     const char *inb = (const char *)md.bufB;
     char *outb = (char *)md.bufA;
-    auto request = [&](LdsT<P> *dst, int tile, int f0) {      // fields f0..f0+2 of `tile`
-        dma_tile3<RV, NTH>(dst, inb + (long long)f0 * FSB + (long long)tile * RW * C::CS, FSB);
+    auto request = [&](LdsT<P> *dst, int tile, int f0) {      // fields f0..f0+2 of `tile`, rows without the pad
+        dma_rows3<C::RVR, PX * C::CS, T, NTH>(dst, inb + (long long)f0 * FSB + (long long)tile * T * PX * C::CS, FSB);
     };
     // packed two-for-one spectrum of fields (fa, fb): C = A + i B, Hermitian
     // fill.  Position n = t + M m; whole segments [M m, M m + M) below K, above
@@ -449,7 +469,7 @@ __global__ void __launch_bounds__((XCfg<P, N, EV>::NTH), (XCfg<P, N, EV>::MINB))
 #pragma unroll
         for (int m = 0; m < E; m++) {
             const int n = t + M * m;
-            const int r = l * (K + 1);
+            const int r = l * RQ;
             if (M * m > K && M * m + M - 1 < N - K) {
                 v[m] = czero<P>();
             } else if (m > 0 && M * m + M - 1 <= K) {
@@ -471,21 +491,22 @@ __global__ void __launch_bounds__((XCfg<P, N, EV>::NTH), (XCfg<P, N, EV>::MINB))
     };
     P umx = P(0);
     Cx<P> v[E];
-    // Write the tile staged in lds ([3][RV] vectors) with 16-byte stores, in
-    // the wave-sized chunks of dma_tile3 (the same count per wave).
+    // Write the tile staged in lds ([3][T][K+1], contiguous in the output) with
+    // 16-byte stores in wave-sized chunks of 64 vectors (the same count per
+    // wave; the last chunk of a field is moved back onto its end).
     typedef float F4 __attribute__((ext_vector_type(4)));
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const unsigned lane16 = (threadIdx.x & 63u) * 16u;
     auto store_tile = [&](int tile, bool zero) {
-        constexpr int NCF = (RV + 63) / 64, NCH = 3 * NCF, NW = NTH / 64;
+        constexpr int NCF = (RVO + 63) / 64, NCH = 3 * NCF, NW = NTH / 64;
 #pragma unroll
         for (int j = 0; j < C::S; j++) {
             int c = j * NW + wave;
             c = c < NCH ? c : NCH - 1;
             const int f = c / NCF, q = c - f * NCF;
-            const int st = q * 64 < RV - 64 ? q * 64 : RV - 64;
-            const F4 x = zero ? F4{0.f, 0.f, 0.f, 0.f} : *(const F4 *)((const char *)lds + (f * RV + st) * 16 + lane16);
-            ENS_GLOBAL char *dst = (ENS_GLOBAL char *)outb + f * FSB + (long long)tile * RW * C::CS + st * 16;
+            const int st = q * 64 < RVO - 64 ? q * 64 : RVO - 64;
+            const F4 x = zero ? F4{0.f, 0.f, 0.f, 0.f} : *(const F4 *)((const char *)lds + (f * RVO + st) * 16 + lane16);
+            ENS_GLOBAL char *dst = (ENS_GLOBAL char *)outb + f * FSBO + (long long)tile * RWO * C::CS + st * 16;
             *(ENS_GLOBAL F4 *)(dst + lane16) = x;
         }
     };
@@ -562,8 +583,8 @@ __global__ void __launch_bounds__((XCfg<P, N, EV>::NTH), (XCfg<P, N, EV>::MINB))
             const int k = t + M * m;
             if (M * m <= K && (M * m + M - 1 <= K || k <= K)) {
                 lds_put<P>(lds, l * (K + 1) + k, ox[m]);
-                lds_put<P>(lds, RW + l * (K + 1) + k, oy[m]);
-                lds_put<P>(lds, 2 * RW + l * (K + 1) + k, d2[m]);
+                lds_put<P>(lds, RWO + l * (K + 1) + k, oy[m]);
+                lds_put<P>(lds, 2 * RWO + l * (K + 1) + k, d2[m]);
             }
         }
         lds_barrier();
@@ -587,11 +608,12 @@ __global__ void __launch_bounds__((XCfg<P, N, EV>::NTH), (XCfg<P, N, EV>::MINB))
 }
 
 // ================================================================== yfwd
-// y-lines L = z (K+1) + kx.  in bufA [3][N][N][K+1]; out bufB [3][N (z)][2K+1][K+1]
+// y-lines L = z PX + kx.  in bufA [3][N][N][K+1]; out bufB [3][N (z)][2K+1][PX]
+// (pad lines kx > K carry zeros)
 template <typename P, int N, int EV>
 __global__ void __launch_bounds__((Cfg<P, N, EV>::NT)) k_yfwd(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw) {
     using C = Cfg<P, N, EV>;
-    constexpr int E = C::E, M = C::M, T = C::T, K = C::K, NZL = C::NZL;
+    constexpr int E = C::E, M = C::M, T = C::T, K = C::K, NZL = C::NZL, PX = C::PX;
     constexpr long long FS = (long long)N * N * (K + 1);
     __shared__ LdsT<P> lds[N * T];
     unsigned tile, mem_i;
@@ -599,9 +621,10 @@ __global__ void __launch_bounds__((Cfg<P, N, EV>::NT)) k_yfwd(const MemberDev *_
     const MemberDev &md = mems[mem_i];
     const int l = threadIdx.x % T, t = threadIdx.x / T;
     const int L = tile * T + l;
-    const bool valid = L < C::NYL;
-    const int z = valid ? L / (K + 1) : 0;
-    const int kx = valid ? L % (K + 1) : 0;
+    const bool inb = L < C::NYL;
+    const int z = inb ? L / PX : 0;
+    const int kx = inb ? L % PX : 0;
+    const bool valid = inb && kx <= K;
     const uint32_t in_base = (uint32_t)z * N * (K + 1) + kx;
     const uint32_t out_base = (uint32_t)z * NZL + kx;
     auto load = [&](Cx<P> *v, int f) {
@@ -615,12 +638,12 @@ __global__ void __launch_bounds__((Cfg<P, N, EV>::NT)) k_yfwd(const MemberDev *_
     for (int f = 0; f < 3; f++) {
         if (f < 2) load(p, f + 1);
         line_fft<P, N, E, T, -1>(a, lds, l, t, tw);
-        if (valid) {
+        if (inb) {
             const Fld<P> o(md.bufB, (long long)f * N * NZL);
 #pragma unroll
             for (int s = 0; s < E; s++) {
                 const int my = mode_of(Plan<N, E>::out_pos(t, s), N);
-                if (my >= -K && my <= K) o.st(out_base + (uint32_t)(my >= 0 ? my : my + 2 * K + 1) * (K + 1), a[s]);
+                if (my >= -K && my <= K) o.st(out_base + (uint32_t)(my >= 0 ? my : my + 2 * K + 1) * PX, a[s]);
             }
         }
         if (f < 2) {
@@ -631,12 +654,13 @@ __global__ void __launch_bounds__((Cfg<P, N, EV>::NT)) k_yfwd(const MemberDev *_
 }
 
 // ================================================================== zfwd + update
-// z-lines L = iy (K+1) + kx.  in bufB [3][N][NZL].  Forward along z, keep
-// |m_z| <= K, normalise by N^-3, project, add band forcing, RK stage update.
+// z-lines L = iy (K+1) + kx of the state (line iy PX + kx of bufB [3][N][NZL]).
+// Forward along z, keep |m_z| <= K, normalise by N^-3, project, add band
+// forcing, RK stage update.
 template <typename P, int N>
 __global__ void __launch_bounds__((Cfg<P, N, 8>::NTZ)) k_zfwd_update(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw, int stage) {
     using C = Cfg<P, N, 8>;
-    constexpr int E = C::EZ, M = C::MZ, T = C::TZ, K = C::K, NZL = C::NZL, S = C::S;
+    constexpr int E = C::EZ, M = C::MZ, T = C::TZ, K = C::K, NZL = C::NZL, S = C::S;   // NZL: bufB lines
     constexpr int NT = C::NTZ;
     static_assert(NT * sizeof(double) <= N * T * sizeof(LdsT<P>), "reduction scratch reuses the FFT LDS");
     __shared__ LdsT<P> lds[N * T];
@@ -646,16 +670,17 @@ __global__ void __launch_bounds__((Cfg<P, N, 8>::NTZ)) k_zfwd_update(const Membe
     const MemberDev &md = mems[mem_i];
     const int l = threadIdx.x % T, t = threadIdx.x / T;
     const int L = tile * T + l;
-    const bool valid = L < NZL;
+    const bool valid = L < C::NZLS;
     const int iy = valid ? L / (K + 1) : 0;
     const int kx = valid ? L % (K + 1) : 0;
+    const uint32_t Lz = (uint32_t)(iy * C::PX + kx);           // the line in bufB
     const int my = iy <= K ? iy : iy - (2 * K + 1);
     Cx<P> a[3][E];
 #pragma unroll
     for (int f = 0; f < 3; f++) {
         const Fld<P> in(md.bufB, (long long)f * N * NZL);
 #pragma unroll
-        for (int m = 0; m < E; m++) a[f][m] = valid ? in.ld((uint32_t)(t + M * m) * NZL + L) : czero<P>();
+        for (int m = 0; m < E; m++) a[f][m] = valid ? in.ld((uint32_t)(t + M * m) * NZL + Lz) : czero<P>();
     }
 #pragma unroll
     for (int f = 0; f < 3; f++) line_fft<P, N, E, T, -1>(a[f], lds, l, t, tw);
@@ -688,7 +713,7 @@ __global__ void __launch_bounds__((Cfg<P, N, 8>::NTZ)) k_zfwd_update(const Membe
             const int mz = mode_of(Plan<N, E>::out_pos(t, s), N);
             if (mz < -K || mz > K) continue;
             const int iz = mz >= 0 ? mz : mz + 2 * K + 1;
-            const uint32_t idx = (uint32_t)iz * NZL + L;
+            const uint32_t idx = (uint32_t)iz * C::NZLS + L;
             const int m2 = kx * kx + my * my + mz * mz;
             const P kxv = dk * (P)kx, kyv = dk * (P)my, kzv = dk * (P)mz;
             const P k2 = kxv * kxv + kyv * kyv + kzv * kzv;
@@ -826,10 +851,10 @@ static hipError_t run_pass(int pass, int variant, const MemberDev *mem, int coun
         return variant == 1 ? run_pencil<P, N, 16>(pass, mem, count, stage, twp, s)
                             : run_pencil<P, N, 8>(pass, mem, count, stage, twp, s);
     case P_ZFWD:
-        k_zfwd_update<P, N><<<dim3((C::NZL + C::TZ - 1) / C::TZ, count), C::NTZ, 0, s>>>(mem, twp, stage);
+        k_zfwd_update<P, N><<<dim3((C::NZLS + C::TZ - 1) / C::TZ, count), C::NTZ, 0, s>>>(mem, twp, stage);
         break;
     case P_END:
-        k_end_step<N><<<count, 256, 0, s>>>(mem, (C::NZL + C::TZ - 1) / C::TZ);
+        k_end_step<N><<<count, 256, 0, s>>>(mem, (C::NZLS + C::TZ - 1) / C::TZ);
         break;
     default: return hipErrorInvalidValue;
     }
@@ -875,7 +900,7 @@ int default_variant(int pass, int n, int prec) {
 }
 
 long long zfwd_blocks(int n, int prec) {
-    auto blocks = [](auto cfg) { using C = decltype(cfg); return (long long)((C::NZL + C::TZ - 1) / C::TZ); };
+    auto blocks = [](auto cfg) { using C = decltype(cfg); return (long long)((C::NZLS + C::TZ - 1) / C::TZ); };
     const bool f = prec == ENS_FP32;
     switch (n) {
     case 16: return f ? blocks(Cfg<float, 16, 8>{}) : blocks(Cfg<double, 16, 8>{});
