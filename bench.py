@@ -57,28 +57,15 @@ def hist_for(ens, nu):
 
 
 def pass_bytes(n: int, prec: str) -> dict:
-    """Algorithmic HBM bytes of one launch of each pass for one member: the
-    pass's inputs read once and outputs written once (truncated storage)."""
-    K = n // 3
-    cs = 16 if prec == "fp64" else 8
-    S = (2 * K + 1) ** 2 * (K + 1)
-    zl = n * (2 * K + 1) * (K + 1)          # one field of z-pencils
-    yl = n * n * (K + 1)                    # one field of y-pencils
-    return {
-        "zinv": (3 * S + 5 * zl) * cs,
-        "yinv": (5 * zl + 6 * yl) * cs,
-        "xpass": (6 * yl + 3 * yl) * cs,
-        "yfwd": (3 * yl + 3 * zl) * cs,
-        # stages 2 and 3 read the RK register too; average over the 3 stages
-        "zfwd_update": (3 * zl + 3 * S + 2 * 3 * S / 3 + 6 * S) * cs,
-    }
+    from paper_2506_23712_amd import profiling
+    return profiling.pass_bytes(n, prec)
 
 
 def run_workload(ens, torch, name, specs, steps, warmup, stats_every, hist_nu, autotune=True):
     E = ens.Ensemble(hist=hist_for(ens, hist_nu), graphs=True)
     members = [E.add_member(s) for s in specs]
     torch.cuda.synchronize()
-    variants = E.autotune() if autotune else {}
+    variants = E.autotune() if autotune else E.variants()
     for i in range(warmup):
         E.step(1)
         if stats_every and (i + 1) % stats_every == 0:
@@ -149,8 +136,9 @@ def roofline(res):
     avg_ms = ms_step / launches
     bytes_launch = pass_bytes(n, prec)[k] * count
     gbs = bytes_launch / (avg_ms * 1e-3) / 1e9
+    from paper_2506_23712_amd import profiling
     v = res["variants"].get(f"{k}:{n}:{prec}")
-    pname = f"ens::k_{k}<{'float' if prec == 'fp32' else 'double'}, {n}" + (f", {8 if v == 0 else 16}>" if v is not None else "")
+    pname = profiling.kernel_name(k, n, prec, v)
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(res["name"], pname),
             "kernel": pname.replace("ens::", ""), "avg_launch_ms": round(avg_ms, 4),

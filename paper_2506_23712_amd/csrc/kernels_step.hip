@@ -256,9 +256,12 @@ __global__ void __launch_bounds__(256) k_xpass(const MemberDev *__restrict__ mem
     constexpr long long FSO = (long long)N * N * (K + 1);     // elements per output field
     constexpr int RW = T * PX;                                 // elements of the tile per input field
     constexpr int RWO = T * (K + 1);                           // elements of the tile per output field
+    // staged rows are PX + 1 apart in LDS when PX is a multiple of 16, so that
+    // the rows of a wave fall in different banks
+    constexpr int LP = PX % 16 == 0 ? PX + 1 : PX, RWL = T * LP;
     constexpr int PER = (RW + 255) / 256;                      // staged elements per thread per field
     __shared__ LdsT<P> lds[N * T];
-    __shared__ LdsT<P> sb[2 * RW];                             // staged pair / two output fields
+    __shared__ LdsT<P> sb[2 * RWL];                            // staged pair / two output fields
     __shared__ double redmax[256 / 64];
     unsigned tile, mem_i;
     xcd_tile(tile, mem_i);
@@ -283,7 +286,7 @@ __global__ void __launch_bounds__(256) k_xpass(const MemberDev *__restrict__ mem
 #pragma unroll
             for (int i = 0; i < PER; i++) {
                 const int e = threadIdx.x + 256 * i;
-                if (e < RW) lds_put<P>(sb, h * RW + e, st[h][i]);
+                if (e < RW) lds_put<P>(sb, h * RWL + e + (LP - PX) * (e / PX), st[h][i]);
             }
     };
     // packed two-for-one spectrum of the staged pair: C = A + i B, Hermitian fill
@@ -294,7 +297,7 @@ __global__ void __launch_bounds__(256) k_xpass(const MemberDev *__restrict__ mem
             const bool lo = n <= K, hi = n >= N - K;
             const int kx = lo ? n : N - n;
             Cx<P> A = czero<P>(), B = czero<P>();
-            if (lo || hi) { A = lds_get<P>(sb, l * PX + kx); B = lds_get<P>(sb, RW + l * PX + kx); }
+            if (lo || hi) { A = lds_get<P>(sb, l * LP + kx); B = lds_get<P>(sb, RWL + l * LP + kx); }
             if (n == 0) v[m] = {A.re, B.re};
             else if (lo) v[m] = {A.re - B.im, A.im + B.re};
             else v[m] = {A.re + B.im, B.re - A.im};            // zero pairs stay zero

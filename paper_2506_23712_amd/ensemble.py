@@ -182,6 +182,11 @@ class Ensemble:
         ms = members if members is not None else self.members
         cp = cache_path.encode() if cache_path else None
         check(lib().ens_autotune(self.ctx, _ids(ms), len(ms), _stream_ptr(), cp))
+        return self.variants(ms)
+
+    def variants(self, members=None) -> dict:
+        """Kernel variant in use per (pass, n, precision) of the members' sizes."""
+        ms = members if members is not None else self.members
         out = {}
         for n, prec in sorted({(m.spec.n, m.spec.precision) for m in ms}):
             p = _lib.ENS_FP32 if prec == "fp32" else _lib.ENS_FP64

@@ -42,6 +42,35 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def pass_bytes(n: int, prec: str) -> dict:
+    """Algorithmic HBM bytes of one launch of each pass for one member: the
+    pass's inputs read once and outputs written once, truncated storage
+    without the line padding of the pencil buffers."""
+    K = n // 3
+    cs = 16 if prec == "fp64" else 8
+    S = (2 * K + 1) ** 2 * (K + 1)
+    zl = n * (2 * K + 1) * (K + 1)          # one field of z-pencils
+    yl = n * n * (K + 1)                    # one field of y-pencils
+    return {
+        "zinv": (3 * S + 5 * zl) * cs,
+        "yinv": (5 * zl + 6 * yl) * cs,
+        "xpass": (6 * yl + 3 * yl) * cs,
+        "yfwd": (3 * yl + 3 * zl) * cs,
+        # stages 2 and 3 read the RK register too; average over the 3 stages
+        "zfwd_update": (3 * zl + 3 * S + 2 * 3 * S / 3 + 6 * S) * cs,
+    }
+
+
+def kernel_name(pass_name: str, n: int, prec: str, variant) -> str:
+    """Symbol (as rocprofv3 prints it, without arguments) of a pass's kernel."""
+    p = "float" if prec == "fp32" else "double"
+    if pass_name == "zfwd_update":
+        return f"ens::k_zfwd_update<{p}, {n}>"
+    if pass_name == "xpass" and variant == 2 and n >= 64:
+        return f"ens::k_xpass_dma<{p}, {n}, 8>"
+    return f"ens::k_{pass_name}<{p}, {n}, {16 if variant == 1 else 8}>"
+
+
 def _db(path: str) -> sqlite3.Connection:
     if os.path.isdir(path):
         found = glob.glob(os.path.join(path, "**", "*.db"), recursive=True)
@@ -95,6 +124,46 @@ def traffic(copy_fetch: str, copy_write: str, copy_bytes: int, fetch: str, write
             "kernels": kernels}
 
 
+def write_summary(n: int, counts, out: str) -> None:
+    """Markdown table: measured HBM bytes per launch (profiles/traffic_*.json)
+    against the algorithmic bytes of each pass, for the n^3 kernels."""
+    rows = []
+    prof = os.path.join(os.path.dirname(HERE), "profiles")
+    for (wl, prec), cnt in zip((("single256_fp64", "fp64"), ("ens96_mixed_fp32", "fp32")), counts):
+        path = os.path.join(prof, f"traffic_{wl}.json")
+        t = json.load(open(path))
+        pb = pass_bytes(n, prec)
+        K = n // 3
+        cs = 16 if prec == "fp64" else 8
+        S, zl, yl = (2 * K + 1) ** 2 * (K + 1), n * (2 * K + 1) * (K + 1), n * n * (K + 1)
+        rw = {"zinv": (3 * S, 5 * zl), "yinv": (5 * zl, 6 * yl), "xpass": (6 * yl, 3 * yl), "yfwd": (3 * yl, 3 * zl),
+              "zfwd_update": (3 * zl + 3 * S + 2 * S, 6 * S)}
+        for k in ("zinv", "yinv", "xpass", "yfwd", "zfwd_update"):
+            for name, v in sorted(t["kernels"].items()):
+                short = name.replace("ens::", "")
+                if not (short.startswith(f"k_{k}<") or (k == "xpass" and short.startswith("k_xpass_dma<"))):
+                    continue
+                if f", {n}" not in short or ("float" in short) != (prec == "fp32"):
+                    continue
+                ar, aw = rw[k][0] * cs * cnt, rw[k][1] * cs * cnt
+                rows.append((wl, short, ar / 1e9, aw / 1e9, v["fetch_bytes"] / 1e9, v["write_bytes"] / 1e9,
+                             (v["fetch_bytes"] + v["write_bytes"]) / (ar + aw), t["source_hash"]))
+    with open(out, "w") as f:
+        f.write(f"# HBM traffic per launch vs algorithmic bytes ({n}^3 members)\n\n")
+        f.write("Made by `python -m paper_2506_23712_amd.profiling summary --out " + os.path.relpath(out, os.path.dirname(HERE))
+                + "` from `profiles/traffic_single256_fp64.json` and `profiles/traffic_ens96_mixed_fp32.json` "
+                  "(their commands are recorded inside).  Counters: FETCH_SIZE and WRITE_SIZE (rocprofv3 `--pmc`, one "
+                  "counter per run), KiB per dispatch, scaled by what the same counter reads for a plain 1 GiB device "
+                  "copy.  Algorithmic bytes: each pass's inputs read once and outputs written once, truncated storage "
+                  "without line padding (the `zfwd_update` read averages the three RK stages).  The measured bytes "
+                  "include the zero pad entries that the z/y passes write so that every store covers whole 128-byte "
+                  "lines (FP32 rows of 86 complex values padded to 96, FP64 to 88).\n\n")
+        f.write("| workload | kernel | algorithmic read / write GB | measured read / write GB | measured / algorithmic | kernel source hash |\n")
+        f.write("|---|---|---|---|---|---|\n")
+        for r in rows:
+            f.write(f"| {r[0]} | `{r[1]}` | {r[2]:.3f} / {r[3]:.3f} | {r[4]:.3f} / {r[5]:.3f} | {r[6]:.2f} | `{r[7]}` |\n")
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(prog="python -m paper_2506_23712_amd.profiling")
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -109,7 +178,15 @@ def main(argv=None):
         t.add_argument(a, required=True)
     t.add_argument("--copy-bytes", type=int, required=True)
     t.add_argument("--command", default="")
+    m = sub.add_parser("summary")
+    m.add_argument("--n", type=int, default=256)
+    m.add_argument("--counts", type=int, nargs=2, default=(1, 25), metavar=("FP64", "FP32"),
+                   help="members of that size per launch in the two workloads")
+    m.add_argument("--out", required=True)
     a = ap.parse_args(argv)
+    if a.cmd == "summary":
+        write_summary(a.n, a.counts, a.out)
+        return
     if a.cmd == "stats":
         rows = kernel_stats(a.db)[: a.top]
         with open(a.out, "w") as f:
