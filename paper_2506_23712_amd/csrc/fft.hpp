@@ -164,6 +164,42 @@ template <int DIR, typename P> __device__ __forceinline__ Cx<P> twiddle(const Cx
     return w;
 }
 
+// Twiddles held in registers: for thread t, the factors of every stage s >= 1
+// (butterflies b < E/r, m = 1..r-1), loaded once from the table; each
+// transform of the thread then reads no twiddle from memory.
+template <typename P, int N, int E> struct TwRegs {
+    static constexpr int off(int s) {
+        int o = 0;
+        for (int i = 1; i < s; i++) { const int r = stage_radix(N, E, i); o += (E / r) * (r - 1); }
+        return o;
+    }
+    static constexpr int CNT = off(num_stages(N, E));
+    Cx<P> w[CNT > 0 ? CNT : 1];
+    template <int s = 1> __device__ __forceinline__ void load(const Cx<P> *tw, int t) {
+        if constexpr (s < num_stages(N, E)) {
+            constexpr int R = stage_radix(N, E, s), NS = stage_span(N, E, s), M = N / E;
+#pragma unroll
+            for (int b = 0; b < E / R; b++) {
+                const int k = (t + M * b) % NS;
+#pragma unroll
+                for (int m = 1; m < R; m++) w[off(s) + b * (R - 1) + m - 1] = tw[m * k * (N / (NS * R))];
+            }
+            load<s + 1>(tw, t);
+        }
+    }
+    template <int DIR, int s> __device__ __forceinline__ Cx<P> get(int b, int m) const {
+        constexpr int R = stage_radix(N, E, s);
+        Cx<P> x = w[off(s) + b * (R - 1) + m - 1];
+        if constexpr (DIR > 0) x.im = -x.im;
+        return x;
+    }
+};
+// twiddle m k N/(Ns r) of butterfly b, stage s, from a table or from registers
+template <int DIR, int s, typename P>
+__device__ __forceinline__ Cx<P> tw_at(const Cx<P> *tw, int b, int m, int idx) { return twiddle<DIR>(tw, idx); }
+template <int DIR, int s, typename P, int N, int E>
+__device__ __forceinline__ Cx<P> tw_at(const TwRegs<P, N, E> &tw, int b, int m, int idx) { return tw.template get<DIR, s>(b, m); }
+
 template <typename P> using LdsT = typename V2<P>::T;
 
 // Workgroup barrier for LDS exchanges: waits for this wave's LDS operations
@@ -186,8 +222,8 @@ template <typename P> __device__ __forceinline__ Cx<P> lds_get(const LdsT<P> *ld
 }
 
 // One forward-flow stage s >= 1: gather from LDS, twiddle, butterfly.
-template <typename P, int N, int E, int T, int DIR, int s>
-__device__ __forceinline__ void stage_gather(Cx<P> *v, const LdsT<P> *lds, int l, int t, const Cx<P> *tw) {
+template <typename P, int N, int E, int T, int DIR, int s, class TW>
+__device__ __forceinline__ void stage_gather(Cx<P> *v, const LdsT<P> *lds, int l, int t, const TW &tw) {
     constexpr int R = stage_radix(N, E, s), NS = stage_span(N, E, s), M = N / E;
 #pragma unroll
     for (int b = 0; b < E / R; b++) {
@@ -195,7 +231,7 @@ __device__ __forceinline__ void stage_gather(Cx<P> *v, const LdsT<P> *lds, int l
 #pragma unroll
         for (int m = 0; m < R; m++) {
             Cx<P> x = lds_get<P>(lds, (j + m * (N / R)) * T + l);
-            if (m > 0) x = cmul(x, twiddle<DIR>(tw, m * k * (N / (NS * R))));
+            if (m > 0) x = cmul(x, tw_at<DIR, s>(tw, b, m, m * k * (N / (NS * R))));
             v[b * R + m] = x;
         }
         dft<R, DIR>(v + b * R);
@@ -214,8 +250,8 @@ __device__ __forceinline__ void stage_scatter(const Cx<P> *v, LdsT<P> *lds, int 
     }
 }
 
-template <typename P, int N, int E, int T, int DIR, int s, bool SB>
-__device__ __forceinline__ void run_stages(Cx<P> *v, LdsT<P> *lds, int l, int t, const Cx<P> *tw) {
+template <typename P, int N, int E, int T, int DIR, int s, bool SB, class TW>
+__device__ __forceinline__ void run_stages(Cx<P> *v, LdsT<P> *lds, int l, int t, const TW &tw) {
     if constexpr (s < num_stages(N, E)) {
         stage_barrier<SB>();
         stage_scatter<P, N, E, T, s - 1>(v, lds, l, t);
@@ -227,16 +263,16 @@ __device__ __forceinline__ void run_stages(Cx<P> *v, LdsT<P> *lds, int l, int t,
 
 // Forward-flow transform.  All threads of the workgroup must call it (it
 // contains barriers).  LDS: N*T elements of V2<P>.
-template <typename P, int N, int E, int T, int DIR, bool SB = false>
-__device__ __forceinline__ void line_fft(Cx<P> *v, LdsT<P> *lds, int l, int t, const Cx<P> *tw) {
+template <typename P, int N, int E, int T, int DIR, bool SB = false, class TW>
+__device__ __forceinline__ void line_fft(Cx<P> *v, LdsT<P> *lds, int l, int t, const TW &tw) {
     static_assert(N % E == 0 && N >= E, "line length must be a multiple of E");
     dft<E, DIR>(v);                       // stage 0: span 1, no twiddles
     run_stages<P, N, E, T, DIR, 1, SB>(v, lds, l, t, tw);
 }
 
 // ---- transposed flow (stages in reverse order, twiddles after the butterflies)
-template <typename P, int N, int E, int T, int DIR, int s>
-__device__ __forceinline__ void stageT_compute(Cx<P> *v, int t, const Cx<P> *tw) {
+template <typename P, int N, int E, int T, int DIR, int s, class TW>
+__device__ __forceinline__ void stageT_compute(Cx<P> *v, int t, const TW &tw) {
     constexpr int R = stage_radix(N, E, s), NS = stage_span(N, E, s), M = N / E;
 #pragma unroll
     for (int b = 0; b < E / R; b++) {
@@ -244,7 +280,7 @@ __device__ __forceinline__ void stageT_compute(Cx<P> *v, int t, const Cx<P> *tw)
         dft<R, DIR>(v + b * R);
         if constexpr (NS > 1) {
 #pragma unroll
-            for (int m = 1; m < R; m++) v[b * R + m] = cmul(v[b * R + m], twiddle<DIR>(tw, m * k * (N / (NS * R))));
+            for (int m = 1; m < R; m++) v[b * R + m] = cmul(v[b * R + m], tw_at<DIR, s>(tw, b, m, m * k * (N / (NS * R))));
         }
     }
 }
@@ -271,8 +307,8 @@ __device__ __forceinline__ void stageT_gather(Cx<P> *v, const LdsT<P> *lds, int 
     }
 }
 
-template <typename P, int N, int E, int T, int DIR, int s, bool SB>
-__device__ __forceinline__ void run_stagesT(Cx<P> *v, LdsT<P> *lds, int l, int t, const Cx<P> *tw) {
+template <typename P, int N, int E, int T, int DIR, int s, bool SB, class TW>
+__device__ __forceinline__ void run_stagesT(Cx<P> *v, LdsT<P> *lds, int l, int t, const TW &tw) {
     stageT_compute<P, N, E, T, DIR, s>(v, t, tw);
     if constexpr (s > 0) {
         stage_barrier<SB>();
@@ -283,8 +319,8 @@ __device__ __forceinline__ void run_stagesT(Cx<P> *v, LdsT<P> *lds, int l, int t
     }
 }
 
-template <typename P, int N, int E, int T, int DIR, bool SB = false>
-__device__ __forceinline__ void line_fft_T(Cx<P> *v, LdsT<P> *lds, int l, int t, const Cx<P> *tw) {
+template <typename P, int N, int E, int T, int DIR, bool SB = false, class TW>
+__device__ __forceinline__ void line_fft_T(Cx<P> *v, LdsT<P> *lds, int l, int t, const TW &tw) {
     run_stagesT<P, N, E, T, DIR, num_stages(N, E) - 1, SB>(v, lds, l, t, tw);
 }
 

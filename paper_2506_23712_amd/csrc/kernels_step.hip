@@ -409,7 +409,10 @@ template <typename P, int N, int E_> struct XCfg {
     static constexpr int CS = (int)sizeof(Cx<P>), CPV = 16 / CS;
     static constexpr int PX = kx_pitch(K, CS);                 // row pitch in HBM
     static constexpr int RQ = (K + 1 + CPV - 1) / CPV * CPV;   // row length staged in LDS (whole vectors)
-    static constexpr int NTW = twiddle_span(N, E);
+    // FP32: each thread keeps its twiddles in registers; FP64: a table in LDS
+    // (registers would cost the second wave per SIMD)
+    static constexpr bool REGTW = sizeof(P) == 4;
+    static constexpr int NTW = REGTW ? 1 : twiddle_span(N, E);
     static constexpr long long lds_bytes(int t) {
         const long long rs = (long long)t * RQ, ro = (long long)t * (K + 1);
         const long long xl = (long long)N * t > 3 * ro ? (long long)N * t : 3 * ro;
@@ -459,7 +462,13 @@ __global__ void __launch_bounds__((XCfg<P, N, EV>::NTH), (XCfg<P, N, EV>::MINB))
     const int t1 = (int)((long long)(chunk + 1) * C::TILES / gridDim.x);
     if (t0 >= t1) return;                                     // uniform over the workgroup
     const int l = (int)threadIdx.x % T, t = (int)threadIdx.x / T;
-    for (int i = (int)threadIdx.x; i < C::NTW; i += NTH) twl[i] = tw[i];
+    TwRegs<P, N, E> twr;
+    if constexpr (C::REGTW) twr.load(tw, t);
+    else for (int i = (int)threadIdx.x; i < C::NTW; i += NTH) twl[i] = tw[i];
+    const auto &twx = [&]() -> const auto & {
+        if constexpr (C::REGTW) return twr;
+        else return twl;
+    }();
     const char *inb = (const char *)md.bufB;
     char *outb = (char *)md.bufA;
     auto request = [&](LdsT<P> *dst, int tile, int f0) {      // fields f0..f0+2 of `tile`, rows without the pad
@@ -530,7 +539,7 @@ __global__ void __launch_bounds__((XCfg<P, N, EV>::NTH), (XCfg<P, N, EV>::MINB))
     for (int tile = t0; tile < t1; tile++) {
         const bool more = tile + 1 < t1;
         P ph[6][E];
-        line_fft<P, N, E, T, +1, true>(v, lds, l, t, twl);
+        line_fft<P, N, E, T, +1, true>(v, lds, l, t, twx);
 #pragma unroll
         for (int s = 0; s < E; s++) { ph[0][s] = v[s].re; ph[1][s] = v[s].im; }
         wait_vm<C::S>();                                       // fields 3-5
@@ -538,13 +547,13 @@ __global__ void __launch_bounds__((XCfg<P, N, EV>::NTH), (XCfg<P, N, EV>::MINB))
         gather(v, slot0 + 2 * RW, slot1);
         lds_barrier();                                         // slot0 read by every wave
         request(slot0, more ? tile + 1 : tile, 0);
-        line_fft<P, N, E, T, +1, true>(v, lds, l, t, twl);
+        line_fft<P, N, E, T, +1, true>(v, lds, l, t, twx);
 #pragma unroll
         for (int s = 0; s < E; s++) { ph[2][s] = v[s].re; ph[3][s] = v[s].im; }
         gather(v, slot1 + RW, slot1 + 2 * RW);
         lds_barrier();                                         // slot1 read by every wave
         request(slot1, more ? tile + 1 : tile, 3);
-        line_fft<P, N, E, T, +1, true>(v, lds, l, t, twl);
+        line_fft<P, N, E, T, +1, true>(v, lds, l, t, twx);
 #pragma unroll
         for (int s = 0; s < E; s++) { ph[4][s] = v[s].re; ph[5][s] = v[s].im; }
         // ph: 0 u_x, 1 u_y, 2 u_z, 3 omega_x, 4 omega_y, 5 omega_z
@@ -561,8 +570,8 @@ __global__ void __launch_bounds__((XCfg<P, N, EV>::NTH), (XCfg<P, N, EV>::MINB))
             d1[s] = {ph[1][s] * ph[5][s] - ph[2][s] * ph[4][s], ph[2][s] * ph[3][s] - ph[0][s] * ph[5][s]};
             d2[s] = {ph[0][s] * ph[4][s] - ph[1][s] * ph[3][s], P(0)};
         }
-        line_fft_T<P, N, E, T, -1, true>(d1, lds, l, t, twl);        // d1[m] = D1[t + M m]
-        line_fft_T<P, N, E, T, -1, true>(d2, lds, l, t, twl);
+        line_fft_T<P, N, E, T, -1, true>(d1, lds, l, t, twx);        // d1[m] = D1[t + M m]
+        line_fft_T<P, N, E, T, -1, true>(d2, lds, l, t, twx);
         lds_barrier();
 #pragma unroll
         for (int m = 0; m < E; m++) lds_put<P>(lds, (t + M * m) * T + l, d1[m]);
