@@ -129,10 +129,12 @@ __device__ __forceinline__ void load_trunc(Cx<P> *v, const Fld<P> &f, uint32_t b
 // carry zeros.  in u_hat [3][2K+1][2K+1][K+1]; out (bufA) [5][N (z)][NZL]:
 // U_x, U_y, U_z, W_x = Z^-1[i k_z u_x], W_y = Z^-1[i k_z u_y]
 template <typename P, int N, int EV>
-__global__ void __launch_bounds__((Cfg<P, N, EV>::NT)) k_zinv(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw) {
+__global__ void __launch_bounds__((Cfg<P, N, EV>::NT)) k_zinv(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ twg) {
     using C = Cfg<P, N, EV>;
     constexpr int E = C::E, M = C::M, T = C::T, NZL = C::NZL;
     __shared__ LdsT<P> lds[N * T];
+    __shared__ Cx<P> tw[twiddle_span(N, E)];               // twiddles in LDS: no global load inside the transforms
+    for (int i = (int)threadIdx.x; i < twiddle_span(N, E); i += (int)blockDim.x) tw[i] = twg[i];
     unsigned tile, mem_i;
     xcd_tile(tile, mem_i);
     const MemberDev &md = mems[mem_i];
@@ -177,10 +179,12 @@ __global__ void __launch_bounds__((Cfg<P, N, EV>::NT)) k_zinv(const MemberDev *_
 // y-lines L = z PX + kx.  in bufA [5][N][NZL]; out bufB [6][N (z)][N (y)][PX]:
 // u_x, u_y, u_z, omega_x, omega_y, omega_z (pad lines kx > K carry zeros)
 template <typename P, int N, int EV>
-__global__ void __launch_bounds__((Cfg<P, N, EV>::NT)) k_yinv(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw) {
+__global__ void __launch_bounds__((Cfg<P, N, EV>::NT)) k_yinv(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ twg) {
     using C = Cfg<P, N, EV>;
     constexpr int E = C::E, M = C::M, T = C::T, K = C::K, NZL = C::NZL;
     __shared__ LdsT<P> lds[N * T];
+    __shared__ Cx<P> tw[twiddle_span(N, E)];               // twiddles in LDS: no global load inside the transforms
+    for (int i = (int)threadIdx.x; i < twiddle_span(N, E); i += (int)blockDim.x) tw[i] = twg[i];
     unsigned tile, mem_i;
     xcd_tile(tile, mem_i);
     const MemberDev &md = mems[mem_i];
@@ -249,7 +253,7 @@ __global__ void __launch_bounds__((Cfg<P, N, EV>::NT)) k_yinv(const MemberDev *_
 // accesses; the next field pair is fetched into registers while the current
 // pair is transformed.  Stage 0 also folds max(|u|+|v|+|w|) into st->umax_bits.
 template <typename P, int N, int EV>
-__global__ void __launch_bounds__(256) k_xpass(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw, int stage) {
+__global__ void __launch_bounds__(256) k_xpass(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ twg, int stage) {
     using C = Cfg<P, N, EV>;
     constexpr int E = C::E, M = C::M, T = C::TX, K = C::K, PX = C::PX;
     constexpr long long FS = (long long)N * N * PX;           // elements per input field
@@ -261,6 +265,8 @@ __global__ void __launch_bounds__(256) k_xpass(const MemberDev *__restrict__ mem
     constexpr int LP = PX % 16 == 0 ? PX + 1 : PX, RWL = T * LP;
     constexpr int PER = (RW + 255) / 256;                      // staged elements per thread per field
     __shared__ LdsT<P> lds[N * T];
+    __shared__ Cx<P> tw[twiddle_span(N, E)];               // twiddles in LDS: no global load inside the transforms
+    for (int i = (int)threadIdx.x; i < twiddle_span(N, E); i += (int)blockDim.x) tw[i] = twg[i];
     __shared__ LdsT<P> sb[2 * RWL];                            // staged pair / two output fields
     __shared__ double redmax[256 / 64];
     unsigned tile, mem_i;
@@ -623,11 +629,13 @@ __global__ void __launch_bounds__((XCfg<P, N, EV>::NTH), (XCfg<P, N, EV>::MINB))
 // y-lines L = z PX + kx.  in bufA [3][N][N][K+1]; out bufB [3][N (z)][2K+1][PX]
 // (pad lines kx > K carry zeros)
 template <typename P, int N, int EV>
-__global__ void __launch_bounds__((Cfg<P, N, EV>::NT)) k_yfwd(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw) {
+__global__ void __launch_bounds__((Cfg<P, N, EV>::NT)) k_yfwd(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ twg) {
     using C = Cfg<P, N, EV>;
     constexpr int E = C::E, M = C::M, T = C::T, K = C::K, NZL = C::NZL, PX = C::PX;
     constexpr long long FS = (long long)N * N * (K + 1);
     __shared__ LdsT<P> lds[N * T];
+    __shared__ Cx<P> tw[twiddle_span(N, E)];               // twiddles in LDS: no global load inside the transforms
+    for (int i = (int)threadIdx.x; i < twiddle_span(N, E); i += (int)blockDim.x) tw[i] = twg[i];
     unsigned tile, mem_i;
     xcd_tile(tile, mem_i);
     const MemberDev &md = mems[mem_i];
@@ -670,12 +678,14 @@ __global__ void __launch_bounds__((Cfg<P, N, EV>::NT)) k_yfwd(const MemberDev *_
 // Forward along z, keep |m_z| <= K, normalise by N^-3, project, add band
 // forcing, RK stage update.
 template <typename P, int N>
-__global__ void __launch_bounds__((Cfg<P, N, 8>::NTZ)) k_zfwd_update(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw, int stage) {
+__global__ void __launch_bounds__((Cfg<P, N, 8>::NTZ)) k_zfwd_update(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ twg, int stage) {
     using C = Cfg<P, N, 8>;
     constexpr int E = C::EZ, M = C::MZ, T = C::TZ, K = C::K, NZL = C::NZL, S = C::S;   // NZL: bufB lines
     constexpr int NT = C::NTZ;
     static_assert(NT * sizeof(double) <= N * T * sizeof(LdsT<P>), "reduction scratch reuses the FFT LDS");
     __shared__ LdsT<P> lds[N * T];
+    __shared__ Cx<P> tw[twiddle_span(N, E)];               // twiddles in LDS: no global load inside the transforms
+    for (int i = (int)threadIdx.x; i < twiddle_span(N, E); i += (int)blockDim.x) tw[i] = twg[i];
     double *red = reinterpret_cast<double *>(lds);
     unsigned tile, mem_i;
     xcd_tile(tile, mem_i);
