@@ -51,10 +51,12 @@ __device__ __forceinline__ void gload_trunc(Cx<P> *v, const Fld<P> &f, uint32_t 
 // in u_hat [3][2K+1][2K+1][K+1]; out bufA [6][N][NZL]: U_c = Z^-1[u_c] (fields
 // 0..2), W_c = Z^-1[i k_z u_c] (3..5); pad lines (kx > K) carry zeros
 template <typename P, int N>
-__global__ void __launch_bounds__((SCfg<P, N, grad_e<P>()>::NT)) k_gzinv(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw) {
+__global__ void __launch_bounds__((SCfg<P, N, grad_e<P>()>::NT)) k_gzinv(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ twg) {
     using C = SCfg<P, N, grad_e<P>()>;
     constexpr int E = C::E, M = C::M, T = C::T, NZL = C::NZL;
     __shared__ LdsT<P> lds[N * T];
+    __shared__ Cx<P> tw[twiddle_span(N, E)];               // twiddles in LDS: no global load inside the transforms
+    for (int i = (int)threadIdx.x; i < twiddle_span(N, E); i += (int)blockDim.x) tw[i] = twg[i];
     unsigned tile, mem_i;
     xcd_tile(tile, mem_i);
     const MemberDev &md = mems[mem_i];
@@ -93,10 +95,12 @@ __global__ void __launch_bounds__((SCfg<P, N, grad_e<P>()>::NT)) k_gzinv(const M
 // ------------------------------------------------------------------ gyinv
 // out bufB [9][N][N][PX]: U_c (0..2), V_c = d_y u_c (3..5), W_c = d_z u_c (6..8)
 template <typename P, int N>
-__global__ void __launch_bounds__((SCfg<P, N, grad_e<P>()>::NT)) k_gyinv(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw) {
+__global__ void __launch_bounds__((SCfg<P, N, grad_e<P>()>::NT)) k_gyinv(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ twg) {
     using C = SCfg<P, N, grad_e<P>()>;
     constexpr int E = C::E, M = C::M, T = C::T, K = C::K, NZL = C::NZL;
     __shared__ LdsT<P> lds[N * T];
+    __shared__ Cx<P> tw[twiddle_span(N, E)];               // twiddles in LDS: no global load inside the transforms
+    for (int i = (int)threadIdx.x; i < twiddle_span(N, E); i += (int)blockDim.x) tw[i] = twg[i];
     unsigned tile, mem_i;
     xcd_tile(tile, mem_i);
     const MemberDev &md = mems[mem_i];
@@ -190,7 +194,7 @@ __device__ __forceinline__ int slot_1d(int b, int nb) { return b >= 0 ? b : (b =
 // capped at 256 so that two workgroups share a compute unit (one leaves each
 // SIMD a single wave, which stalls on every dependent FP64 operation).
 template <typename P, int N>
-__global__ void __launch_bounds__(256, 2) k_gxstats(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw, HistArgs h) {
+__global__ void __launch_bounds__(256, 2) k_gxstats(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ twg, HistArgs h) {
     constexpr int E = 4, M = N / E, T = 256 / M, K = N / 3;
     constexpr int PX = kx_pitch(K, (int)sizeof(Cx<P>));
     constexpr long long FS = (long long)N * N * PX;
@@ -198,6 +202,8 @@ __global__ void __launch_bounds__(256, 2) k_gxstats(const MemberDev *__restrict_
     double *ledge = dyn;
     unsigned int *hs = (unsigned int *)(dyn + h.lb + 1);
     __shared__ LdsT<P> lds[N * T];
+    __shared__ Cx<P> tw[twiddle_span(N, E)];               // twiddles in LDS: no global load inside the transforms
+    for (int i = (int)threadIdx.x; i < twiddle_span(N, E); i += (int)blockDim.x) tw[i] = twg[i];
     __shared__ double red[4][32];
     // Hot bins are replicated: the central CW bins of each 1-D histogram and
     // the central CQ x CQ bins of the QR histogram get NC copies, one per
@@ -441,7 +447,8 @@ static hipError_t stats_pass(int pass, const MemberDev *mem, int count, const en
         h.loff = (float)(h.l_lo * h.l_scale);
         // LDS: transform tile + reduction (static) + log edges, 1-D histograms, QR window (dynamic) <= 64 KiB
         constexpr int T = 256 / (N / 4);
-        const size_t stat = (size_t)N * T * sizeof(LdsT<P>) + 4 * 32 * sizeof(double) + (4 * 8 * 64 + 8 * 16 * 16) * 4;
+        const size_t stat = (size_t)N * T * sizeof(LdsT<P>) + 4 * 32 * sizeof(double) + (4 * 8 * 64 + 8 * 16 * 16) * 4 +
+                            (size_t)twiddle_span(N, 4) * sizeof(Cx<P>);
         const size_t n1d = 2 * (size_t)(h.lb + 3) + 2 * (size_t)(h.ab + 3);
         const size_t budget = 65536 - stat - 512;
         const size_t fixed = n1d * 4 + (size_t)(h.lb + 1) * 8;
