@@ -66,6 +66,10 @@ template <typename P, int N, int E_> struct Cfg {
     static constexpr int EZ = N <= 256 ? 8 : 16, MZ = N / EZ;
     static constexpr int TZ = N <= 256 ? ((512 / MZ) < 1 ? 1 : 512 / MZ) : (TL * MZ <= 512 ? TL : 512 / MZ);
     static constexpr int NTZ = TZ * MZ;
+    // z forward + update, waves per SIMD the register budget is cut for: two
+    // 512-thread workgroups per compute unit (4 waves per SIMD) in FP32; the
+    // FP64 update keeps its registers
+    static constexpr int ZMINB = (sizeof(P) == 4 && NTZ == 512 && EZ == 8) ? 4 : 1;
 };
 
 // ================================================================== band
@@ -441,11 +445,13 @@ template <typename P, int N, int E_> struct XCfg {
     static constexpr int S = dma_tile3_ops<RVO, NTH>();     // 16-byte stores per wave per tile
     static constexpr int XL = N * T > 3 * RWO ? N * T : 3 * RWO;
     static constexpr int TILES = N * N / T;
-    // workgroups per compute unit the register budget is cut for: what the LDS
-    // allows, up to 3 waves per SIMD (FP32) or 2 (FP64)
-    static constexpr int MINB_LDS = (int)(163840 / ((lds_bytes(T) + 511) / 512 * 512));
-    static constexpr int MINB_VGPR = (sizeof(P) == 4 ? 12 : 8) / (NTH / 64);
-    static constexpr int MINB = MINB_LDS < MINB_VGPR ? MINB_LDS : MINB_VGPR;
+    // waves per SIMD the register budget is cut for: what the LDS allows
+    // (workgroups per compute unit times waves per workgroup, over 4 SIMDs),
+    // at most 3 (FP32) or 2 (FP64)
+    static constexpr int WG_LDS = (int)(163840 / ((lds_bytes(T) + 511) / 512 * 512));
+    static constexpr int W_LDS = WG_LDS * (NTH / 64) / 4;
+    static constexpr int W_MAX = sizeof(P) == 4 ? 3 : 2;
+    static constexpr int MINB = W_LDS < 1 ? 1 : (W_LDS < W_MAX ? W_LDS : W_MAX);
     static_assert(PX % CPV == 0 && RWO % CPV == 0 && NTH % 64 == 0 && RV >= 64 && RVO >= 64 && D3 + S < 64,
                   "x-pass tile shape");
 };
@@ -678,7 +684,7 @@ __global__ void __launch_bounds__((Cfg<P, N, EV>::NT)) k_yfwd(const MemberDev *_
 // Forward along z, keep |m_z| <= K, normalise by N^-3, project, add band
 // forcing, RK stage update.
 template <typename P, int N>
-__global__ void __launch_bounds__((Cfg<P, N, 8>::NTZ)) k_zfwd_update(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ twg, int stage) {
+__global__ void __launch_bounds__((Cfg<P, N, 8>::NTZ), (Cfg<P, N, 8>::ZMINB)) k_zfwd_update(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ twg, int stage) {
     using C = Cfg<P, N, 8>;
     constexpr int E = C::EZ, M = C::MZ, T = C::TZ, K = C::K, NZL = C::NZL, S = C::S;   // NZL: bufB lines
     constexpr int NT = C::NTZ;
