@@ -60,6 +60,8 @@ template <typename P, int N, int E_> struct Cfg {
     static constexpr int MAXT = E >= 16 ? 512 : 1024;             // 16 values/thread: keep 256 VGPRs available
     static constexpr int T = N <= 256 ? (256 / M > TL ? 256 / M : TL) : (TL * M <= MAXT ? TL : MAXT / M);
     static constexpr int NT = T * M;
+    // z/y inverse passes: waves per SIMD the register budget is cut for
+    static constexpr int PMINW = (sizeof(P) == 4 && E == 16 && NT == 256) ? 3 : 1;
     static constexpr int TX = 256 / M;                          // x pass: 256 threads
     // z forward + update: 8 values per thread, 512 threads up to N = 256;
     // 16 values per thread and the pencil rule above for longer lines
@@ -133,7 +135,7 @@ __device__ __forceinline__ void load_trunc(Cx<P> *v, const Fld<P> &f, uint32_t b
 // carry zeros.  in u_hat [3][2K+1][2K+1][K+1]; out (bufA) [5][N (z)][NZL]:
 // U_x, U_y, U_z, W_x = Z^-1[i k_z u_x], W_y = Z^-1[i k_z u_y]
 template <typename P, int N, int EV>
-__global__ void __launch_bounds__((Cfg<P, N, EV>::NT)) k_zinv(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ twg) {
+__global__ void __launch_bounds__((Cfg<P, N, EV>::NT), (Cfg<P, N, EV>::PMINW)) k_zinv(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ twg) {
     using C = Cfg<P, N, EV>;
     constexpr int E = C::E, M = C::M, T = C::T, NZL = C::NZL;
     __shared__ LdsT<P> lds[N * T];
