@@ -151,6 +151,47 @@ def divergence_ratio(uhat: np.ndarray, box: float = 2 * np.pi) -> float:
     return float(np.max(np.abs(kd)) / den) if den > 0 else 0.0
 
 
+# ---------------------------------------------------------- spectral diagnostics
+def shell_index(m2):
+    """Shell s of integer |m|^2 = m2: s - 1/2 <= |m| < s + 1/2 (no ties: |m|^2 is
+    an integer and (s + 1/2)^2 never is)."""
+    return np.floor(np.sqrt(np.asarray(m2, dtype=np.float64)) + 0.5).astype(np.int64)
+
+
+def spectrum(uhat: np.ndarray, nshell: int) -> np.ndarray:
+    """Shell energy spectrum of a field in the canonical layout, the quantity of
+    the paper's energy-spectra figure (section describing the ensemble
+    simulations): E[s] = (1/2) sum of |u_hat_m|^2 over the full spectrum for
+    the modes of shell s (|m| in units of the wavenumber spacing; weight 2 for
+    m_x > 0 in the half-spectrum layout).  Shells s >= nshell are dropped."""
+    n = uhat.shape[1]
+    mz, my, mx = modes(n)
+    s = np.broadcast_to(shell_index(mz * mz + my * my + mx * mx), uhat.shape[1:])
+    w = np.ones(uhat.shape[-1]); w[1:] = 2.0
+    e = 0.5 * np.sum(uhat.real ** 2 + uhat.imag ** 2, axis=0) * w
+    keep = s < nshell
+    return np.bincount(s[keep].ravel(), weights=e[keep].ravel(), minlength=nshell)[:nshell]
+
+
+def refine(uhat: np.ndarray, n_big: int) -> np.ndarray:
+    """Spectral refinement onto a finer grid (the paper replaces its most
+    intense ensemble members by identical simulations at twice the resolution,
+    section on extrapolating to the frontier): every retained mode |m_i| <= n/3
+    of the n^3 field keeps its value on the n_big^3 grid, every other mode is
+    zero.  Canonical layout in and out."""
+    n = uhat.shape[1]
+    K = n // 3
+    if n_big < n:
+        raise ValueError("refinement needs n_big >= n")
+    out = np.zeros(canonical_shape(n_big), dtype=np.complex128)
+    m = np.arange(-K, K + 1)
+    src = m % n
+    dst = m % n_big
+    out[:, dst[:, None, None], dst[None, :, None], np.arange(K + 1)[None, None, :]] = \
+        uhat[:, src[:, None, None], src[None, :, None], np.arange(K + 1)[None, None, :]]
+    return out
+
+
 # ----------------------------------------------------------------------- solver
 @dataclass
 class Member:
