@@ -173,6 +173,26 @@ def spectrum(uhat: np.ndarray, nshell: int) -> np.ndarray:
     return np.bincount(s[keep].ravel(), weights=e[keep].ravel(), minlength=nshell)[:nshell]
 
 
+def integral_scales(uhat: np.ndarray, box: float = 2 * np.pi):
+    """(E, u', L, T) of a field in the canonical layout: the energy, the rms
+    velocity u' = sqrt(2E/3), the integral length L = pi / (2 u'^2) times the
+    sum over modes of e_m / |k_m| (the discrete form of the integral of E(k)/k),
+    and the integral time T = L / u' that the paper measures run lengths and
+    bootstrap windows in.  Sums over the full spectrum, e_m = |u_hat_m|^2 / 2."""
+    n = uhat.shape[1]
+    mz, my, mx = modes(n)
+    m2 = np.broadcast_to(mz * mz + my * my + mx * mx, uhat.shape[1:]).astype(np.float64)
+    w = np.ones(uhat.shape[-1]); w[1:] = 2.0
+    e = 0.5 * np.sum(uhat.real ** 2 + uhat.imag ** 2, axis=0) * w
+    E = float(e.sum())
+    up2 = 2.0 * E / 3.0
+    dk = 2 * np.pi / box
+    nz = m2 > 0
+    L = float(np.pi / (2 * up2) * np.sum(e[nz] / (dk * np.sqrt(m2[nz])))) if up2 > 0 else 0.0
+    up = float(np.sqrt(up2))
+    return E, up, L, (L / up if up > 0 else 0.0)
+
+
 def refine(uhat: np.ndarray, n_big: int) -> np.ndarray:
     """Spectral refinement onto a finer grid (the paper replaces its most
     intense ensemble members by identical simulations at twice the resolution,

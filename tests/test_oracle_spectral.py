@@ -98,3 +98,45 @@ def test_refine_keeps_energy_spectrum_and_divergence(orc):
     assert np.array_equal(orc.refine(u, n), u)
     with pytest.raises(ValueError):
         orc.refine(u, 8)
+
+
+def test_integral_scales_of_single_modes(orc):
+    """One mode of wavenumber k: E = e, u'^2 = 2e/3 and L = 3 pi / (4 k) whatever the
+    amplitude; two modes add their e/k; a box twice as large halves k."""
+    n = 16
+    u = np.zeros((3, n, n, n // 2 + 1), dtype=np.complex128)
+    u[0, 0, 3, 4] = 1.5 + 0.5j                                # m = (m_z, m_y, m_x) = (0, 3, 4), |m| = 5
+    E, up, L, T = orc.integral_scales(u)
+    e = 2.5                                                   # (1/2)|u|^2 = 1.25, twice for the mirror mode
+    assert abs(E - e) <= 1e-15 and abs(up - math.sqrt(2 * e / 3)) <= 1e-15
+    assert abs(L - 3 * math.pi / 20) <= 1e-15 and abs(T - L / up) <= 1e-15
+    _, _, L4, _ = orc.integral_scales(u, box=4 * math.pi)
+    assert abs(L4 - 2 * L) <= 1e-15
+    u[2, 1, 0, 0] = 2.0                                       # m = (1, 0, 0) on the m_x = 0 plane ...
+    u[2, n - 1, 0, 0] = 2.0                                   # ... and its mirror (-1, 0, 0): e = (4 + 4) / 2
+    E2, _, L2, _ = orc.integral_scales(u)
+    assert abs(E2 - (e + 4.0)) <= 1e-15
+    assert abs(L2 - 3 * math.pi / (4 * E2) * (e / 5 + 4.0 / 1)) <= 1e-15
+    assert orc.integral_scales(np.zeros_like(u)) == (0.0, 0.0, 0.0, 0.0)
+
+
+def test_integral_scales_of_the_initial_field_closed_form(orc):
+    """Brute force over the retained cube with the initial field's mode energies."""
+    n, kp = 16, 2.0
+    K = n // 3
+    u = field(orc, n, 21)
+    f, fk = 0.0, 0.0
+    for mz in range(-K, K + 1):
+        for my in range(-K, K + 1):
+            for mx in range(-K, K + 1):
+                m2 = mx * mx + my * my + mz * mz
+                if m2:
+                    k = math.sqrt(m2)
+                    v = k ** 4 * math.exp(-2 * (k / kp) ** 2) / (4 * math.pi * m2)
+                    f += v
+                    fk += v / k
+    E, up, L, T = orc.integral_scales(u)
+    assert abs(E - 0.5) <= 1e-14
+    want_L = math.pi / (2 * (2 * 0.5 / 3)) * 0.5 * fk / f
+    assert abs(L - want_L) <= 1e-14 * want_L
+    assert abs(T - want_L / math.sqrt(1 / 3)) <= 1e-13 * T
