@@ -169,6 +169,39 @@ def cpu_baseline(specs, steps=3):
                       f"{dt:.1f} s"}
 
 
+def diagnostics(ens, torch, reps=20):
+    """HIP-event times of the spectral diagnostics on 256^3 members (FP32 and FP64):
+    shell spectrum, integral scales (each reads the 3 velocity components once),
+    and refinement of a 128^3 member onto 256^3 (reads the 128^3 field, writes
+    the 256^3 field and clears its RK register)."""
+    out = {}
+    stream = torch.cuda.current_stream()
+    for prec, cs in (("fp32", 8), ("fp64", 16)):
+        E = ens.Ensemble()
+        a = E.add_member(ens.MemberSpec(n=128, nu=0.02, eps_ref=1.0, kf_hi=2.5, precision=prec, seed=1))
+        b = E.add_member(ens.MemberSpec(n=256, nu=0.02, eps_ref=1.0, kf_hi=2.5, precision=prec, seed=2))
+        E.step(2)
+        S = lambda n: (2 * (n // 3) + 1) ** 2 * (n // 3 + 1)
+        cases = {"spectrum": (b.spectrum, 3 * S(256) * cs),
+                 "integral_scales": (b.integral_scales, 3 * S(256) * cs),
+                 "refine_128_to_256": (lambda: b.refine_from(a), 3 * S(128) * cs + 6 * S(256) * cs)}
+        for name, (fn, nbytes) in cases.items():
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) / reps * 1e3
+            gbs = nbytes / (us * 1e-6) / 1e9
+            out[f"{name}_{prec}"] = {"us": round(us, 2), "bytes": nbytes, "GB/s": round(gbs, 1),
+                                     "frac": round(gbs / HBM_PEAK_GBS, 4)}
+        E.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,6 +211,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--only", choices=["ens96_mixed_fp32", "single256_fp64"], default=None)
+    ap.add_argument("--diagnostics", action="store_true",
+                    help="only time the spectral diagnostics (spectrum, integral scales, refinement) and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (reference for HBM byte counters) and exit")
     args = ap.parse_args()
@@ -196,6 +231,9 @@ def main():
         print(json.dumps({"calibrate_copy_bytes_read": n * 4, "bytes_written": n * 4, "launches": 3}))
         return
     import paper_2506_23712_amd as ens
+    if args.diagnostics:
+        print(json.dumps({"diagnostics_256": diagnostics(ens, torch), "peak_GB/s": HBM_PEAK_GBS}))
+        return
 
     res = {}
     if args.only in (None, "ens96_mixed_fp32"):

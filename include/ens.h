@@ -245,6 +245,43 @@ ens_status ens_mix_len(const ens_ctx *ctx, int32_t count, size_t *n_out);
 ens_status ens_mix(ens_ctx *ctx, const int32_t *members, int32_t count, double c, double Z,
                    int32_t weight_mode, double q_sigma, double *dev_out, void *stream);
 
+/* ---------------------------------------------------- spectral diagnostics */
+
+/* Shell energy spectrum of member m (the energy spectra of the ensemble
+ * members shown in the paper's figure of energy spectra, section "Description
+ * of the ensemble simulations"): E[s] = sum over the retained modes with
+ * s - 1/2 <= |m| < s + 1/2 of (1/2)|u_hat_m|^2 over the full spectrum, |m| in
+ * units of the wavenumber spacing, s = 0 .. nshell-1 (shells beyond the
+ * retained set are zero).  FP64, written to device memory `dev_out` (nshell
+ * doubles, caller-owned), asynchronous on `stream`.  Deterministic (fixed
+ * summation order).  Errors:
+ * ENS_E_INVALID for a bad member, nshell < 1 or a null pointer. */
+ens_status ens_spectrum(ens_ctx *ctx, int32_t m, int32_t nshell, double *dev_out, void *stream);
+
+/* Energy, rms velocity, integral length and integral time of member m, the
+ * scales that set the run lengths and the bootstrap windows of one integral
+ * time (section "Description of the ensemble simulations", tables of the
+ * ensemble and reference runs).  Sums over the retained modes of the full
+ * spectrum, e_m = (1/2)|u_hat_m|^2, |k_m| = dk |m|:
+ *   dev_out[0] = E = sum e_m,  dev_out[1] = u' = sqrt(2E/3),
+ *   dev_out[2] = L = pi / (2 u'^2) * sum_{m != 0} e_m / |k_m|,  dev_out[3] = T = L / u'
+ * (L = T = 0 for a zero field).  FP64 into device memory (4 doubles,
+ * caller-owned), asynchronous on `stream`; uses the member's own partial-sum
+ * area, so it is ordered with the member's steps only on one stream.
+ * Deterministic.  Errors: ENS_E_INVALID for a bad member or a null pointer. */
+ens_status ens_integral_scales(ens_ctx *ctx, int32_t m, double *dev_out, void *stream);
+
+/* Spectral refinement (section "Extrapolating to the frontier of current
+ * turbulence simulations": the most intense members are replaced by identical
+ * simulations at twice the resolution): member dst, on a grid n_dst >= n_src
+ * with the same box, takes member src's field (every retained mode of src
+ * keeps its value, every other mode is zero; FP32 <-> FP64 conversion as the
+ * precisions require); dst's RK register is cleared and src's time, step count
+ * and diagnostics are carried over.  Both members must exist; the physics
+ * parameters of dst are its own.  Asynchronous on `stream`.  Errors: ENS_E_INVALID for bad ids, src == dst,
+ * n_dst < n_src or a different box. */
+ens_status ens_member_refine(ens_ctx *ctx, int32_t src, int32_t dst, void *stream);
+
 /* ------------------------------------------------------------- primitives */
 
 /* Batched complex FFT of `lines` lines of length n (16..1024, power of two)

@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "ens_internal.h"
+#include "ens_diag.h"
 
 #define ENS_API extern "C" __attribute__((visibility("default")))
 
@@ -109,7 +110,8 @@ Layout member_layout(const ens_member_desc &d, const HistGeom *hg) {
     L.off_a = o; o += align256(a_elems * cs);
     L.off_b = o; o += align256((size_t)9 * n * n * g.px * cs);
     const size_t nparts = std::max({(size_t)(2 * zfwd_blocks(d.n, d.precision)), (size_t)init_blocks(d.n),
-                                    (size_t)(ENS_NMOM * xstats_blocks(d.n))});
+                                    (size_t)(ENS_NMOM * xstats_blocks(d.n)), (size_t)scales_partials(g.K),
+                                    (size_t)spectrum_partials(g.K)});
     L.off_part = o; o += align256(nparts * sizeof(double));
     const size_t ncounts = hg ? (size_t)hg->n_counts : 0;
     L.off_counts = o; o += align256(ncounts * sizeof(unsigned long long));
@@ -617,6 +619,47 @@ ENS_API ens_status ens_mix(ens_ctx *ctx, const int32_t *members, int32_t count, 
     }
     HIPCK(ctx, launch_mix(mds.data(), lam.data(), count, ctx->hist, c, Z, weight_mode, q_sigma, dev_out,
                           ctx->mix_scratch, s));
+    return ENS_OK;
+}
+
+ENS_API ens_status ens_spectrum(ens_ctx *ctx, int32_t mid, int32_t nshell, double *dev_out, void *stream) {
+    if (ens_status st = check_ctx(ctx)) return st;
+    Member *m;
+    if (ens_status st = member_of(ctx, mid, &m)) return st;
+    if (nshell < 1) return fail(ENS_E_INVALID, "nshell must be >= 1");
+    if (!dev_out) return fail(ENS_E_INVALID, "null output pointer");
+    HIPCK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    HIPCK(ctx, launch_spectrum(m->d.precision, m->dev, m->g.K, nshell, dev_out, s));
+    m->last = s;
+    return ENS_OK;
+}
+
+ENS_API ens_status ens_integral_scales(ens_ctx *ctx, int32_t mid, double *dev_out, void *stream) {
+    if (ens_status st = check_ctx(ctx)) return st;
+    Member *m;
+    if (ens_status st = member_of(ctx, mid, &m)) return st;
+    if (!dev_out) return fail(ENS_E_INVALID, "null output pointer");
+    HIPCK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    HIPCK(ctx, launch_scales(m->d.precision, m->dev, m->g.K, dev_out, s));
+    m->last = s;
+    return ENS_OK;
+}
+
+ENS_API ens_status ens_member_refine(ens_ctx *ctx, int32_t src, int32_t dst, void *stream) {
+    if (ens_status st = check_ctx(ctx)) return st;
+    Member *a, *b;
+    if (ens_status st = member_of(ctx, src, &a)) return st;
+    if (ens_status st = member_of(ctx, dst, &b)) return st;
+    if (src == dst) return fail(ENS_E_INVALID, "refinement needs two members");
+    if (b->d.n < a->d.n) return fail(ENS_E_INVALID, "refinement needs n_dst >= n_src");
+    if (std::fabs(a->d.box - b->d.box) > 1e-12 * a->d.box) return fail(ENS_E_INVALID, "refinement needs the same box");
+    HIPCK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    HIPCK(ctx, launch_refine(a->d.precision, b->d.precision, a->dev, b->dev, b->d.n, s));
+    a->last = s;
+    b->last = s;
     return ENS_OK;
 }
 

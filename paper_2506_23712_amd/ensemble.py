@@ -132,6 +132,29 @@ class Member:
     def reset_stats(self) -> None:
         check(lib().ens_reset_stats(self.ens.ctx, self.id, _stream_ptr()))
 
+    def spectrum(self, nshell: int | None = None) -> torch.Tensor:
+        """Shell energy spectrum E[s], s = 0 .. nshell-1 (float64 on the device);
+        by default every shell that holds retained modes."""
+        if nshell is None:
+            nshell = int(math.isqrt(3 * (self.spec.n // 3) ** 2)) + 2
+        out = torch.empty(nshell, dtype=torch.float64, device=self.ens.device)
+        check(lib().ens_spectrum(self.ens.ctx, self.id, nshell, ctypes.c_void_p(out.data_ptr()), _stream_ptr()))
+        return out
+
+    def integral_scales(self) -> torch.Tensor:
+        """(E, u', L, T) as float64 on the device: energy, rms velocity, integral
+        length and integral time from mode sums."""
+        out = torch.empty(4, dtype=torch.float64, device=self.ens.device)
+        check(lib().ens_integral_scales(self.ens.ctx, self.id, ctypes.c_void_p(out.data_ptr()), _stream_ptr()))
+        return out
+
+    def refine_from(self, src: "Member") -> None:
+        """Take src's field on this member's (finer or equal) grid: retained modes
+        of src kept, the rest zero; time and diagnostics carried over."""
+        if src.ens is not self.ens:
+            raise ValueError("both members must belong to the same ensemble")
+        check(lib().ens_member_refine(self.ens.ctx, src.id, self.id, _stream_ptr()))
+
 
 class Ensemble:
     def __init__(self, hist: HistSpec | None = None, device: int = 0, graphs: bool = True):

@@ -48,6 +48,8 @@ def test_argument_validation_without_a_gpu(L):
     assert L.ens_fft_pencils(64, 0, 2, 10, None, None, None) == _lib.ENS_E_INVALID
     assert L.ens_fft_pencils(64, 0, -1, 0, None, None, None) == _lib.ENS_OK
     assert L.ens_step(None, None, 0, 1, None) == _lib.ENS_E_INVALID
+    assert L.ens_spectrum(None, 0, 8, None, None) == _lib.ENS_E_INVALID
+    assert L.ens_member_refine(None, 0, 1, None) == _lib.ENS_E_INVALID
     ctx = ctypes.c_void_p()
     bad = _lib.HistDesc(0, -1, 1, -1, 1, 8, -1, 1, 8, -1, 1, 1.0, 1.0)
     assert L.ens_create(ctypes.byref(ctx), 0, ctypes.byref(bad)) == _lib.ENS_E_INVALID
