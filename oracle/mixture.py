@@ -21,7 +21,20 @@ Readings (the paper is silent): members are sorted by lambda and the bin of a
 member is bounded by the midpoints to its neighbours; the two end bins are open
 to -inf / +inf (mode 0), or closed at half a spacing and renormalised (mode 1);
 mode 2 is self-normalised importance weighting P(lambda_i; Z) / q(lambda_i) for
-members whose lambda were drawn from a normal density q.
+members whose lambda were drawn from a normal density q; mode 3 takes the bin
+masses (open end bins) of the truncated Gaussian of the appendix,
+eq. (truncated_gaussian): variance 9cZ, support lambda <= Z, its mean mu(Z) the
+root of the mean-injection constraint (eq. mean_injection_constraint).
+
+The scale gap from a target Reynolds number (section "Benchmarking the method
+against DNS data", eq. Rlambda_Z_relation): with C_eps constant, eq.
+(Re_definition) at fixed L and nu gives Re ~ e^(lambda/3) across the members, and
+R_lambda ~ Re^(1/2) ~ e^(lambda/6).  Fitting C_eps to the members with
+lambda >= 0 is then a fit of A in R_lambda = A e^(lambda/6) (slope fixed, least
+squares in log R_lambda); the reference at scale gap Z has Re larger by
+e^(4Z/3), so R_lambda,ref = A e^(2Z/3) and Z = (3/2) ln(R_lambda,ref / A).
+A member's R_lambda is formed from its time-averaged energy and dissipation,
+R_lambda = (2<E>/3) sqrt(15 / (nu <D>)).
 """
 from __future__ import annotations
 
@@ -55,6 +68,51 @@ def _mass(a: float, b: float, mu: float, sig: float) -> float:
     if b <= mu:
         return lower(b) - lower(a)
     return 1.0 - lower(a) - upper(b)
+
+
+def _phi(x: float) -> float:
+    """Standard normal distribution function."""
+    return 0.5 * math.erfc(-x / math.sqrt(2.0))
+
+
+def truncated_params(c: float, Z: float) -> tuple[float, float]:
+    """(mu, sigma) of the truncated Gaussian, eq. (truncated_gaussian): sigma^2 = 9cZ
+    and mu(Z) such that the density N exp(-(lambda - mu)^2 / (2 sigma^2)) on
+    lambda <= Z has int P e^lambda = 1.  For a normal truncated at Z,
+    int P e^lambda = exp(mu + sigma^2/2) Phi((Z - mu - sigma^2)/sigma) / Phi((Z - mu)/sigma);
+    its logarithm g(mu) grows with mu, is negative at mu = -sigma^2/2 (the
+    untruncated root) and tends to Z > 0 as mu grows: bisection on it."""
+    if Z <= 0.0:
+        return 0.0, 0.0
+    sig = math.sqrt(9.0 * c * Z)
+    s2 = sig * sig
+
+    def g(mu):
+        return mu + 0.5 * s2 + math.log(_phi((Z - mu - s2) / sig)) - math.log(_phi((Z - mu) / sig))
+
+    lo = -0.5 * s2
+    step = max(sig, 1e-3)
+    hi = lo + step
+    while g(hi) <= 0.0:
+        lo, hi = hi, hi + step
+        step *= 2.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if mid == lo or mid == hi:
+            break
+        if g(mid) > 0.0:
+            hi = mid
+        else:
+            lo = mid
+    return 0.5 * (lo + hi), sig
+
+
+def truncated_pdf(lam: float, c: float, Z: float) -> float:
+    """P(lambda; Z) of eq. (truncated_gaussian), normalised on lambda <= Z."""
+    mu, sig = truncated_params(c, Z)
+    if lam > Z:
+        return 0.0
+    return math.exp(-(lam - mu) ** 2 / (2 * sig * sig)) / (sig * math.sqrt(2 * math.pi) * _phi((Z - mu) / sig))
 
 
 def cell_edges(lams: Sequence[float], mode: int = 0) -> list[tuple[float, float]]:
@@ -91,9 +149,13 @@ def weights(lams: Sequence[float], c: float, Z: float, mode: int = 0,
             raw.append(p / q)
         s = sum(raw)
         return [r / s for r in raw]
-    edges = cell_edges(lams, mode)
+    edges = cell_edges(lams, 0 if mode == 3 else mode)
     if Z <= 0.0:                       # P(lambda; 0) = delta(lambda)
         return [1.0 if (a <= 0.0 < b) else 0.0 for a, b in edges]
+    if mode == 3:                      # truncated Gaussian: mass of [a, b) cut at Z
+        mu, sig = truncated_params(c, Z)
+        tot = _mass(-math.inf, Z, mu, sig)
+        return [(_mass(a, min(b, Z), mu, sig) / tot if a < Z else 0.0) for a, b in edges]
     mu, sig = gaussian_params(c, Z)
     w = [_mass(a, b, mu, sig) for a, b in edges]
     if mode == 1:
@@ -105,6 +167,26 @@ def weights(lams: Sequence[float], c: float, Z: float, mode: int = 0,
 def z_from_rlambda(r_target: float, r_anchor: float, z_anchor: float) -> float:
     """Scale gap for a target R_lambda, from R_lambda ~ exp(2Z/3) through an anchor."""
     return z_anchor + 1.5 * math.log(r_target / r_anchor)
+
+
+def rlambda_from_means(e_mean: float, d_mean: float, nu: float) -> float:
+    """Taylor-scale Reynolds number from time-averaged energy and dissipation:
+    u'^2 = 2<E>/3, lambda_T = sqrt(15 nu u'^2 / <D>), R_lambda = u' lambda_T / nu."""
+    up2 = 2.0 * e_mean / 3.0
+    return up2 * math.sqrt(15.0 / (nu * d_mean))
+
+
+def rlambda_prefactor(lams: Sequence[float], rls: Sequence[float]) -> float:
+    """A of R_lambda = A e^(lambda/6), least squares in log over members with lambda >= 0."""
+    xs = [math.log(r) - l / 6.0 for l, r in zip(lams, rls) if l >= 0.0]
+    if not xs:
+        raise ValueError("no member with lambda >= 0")
+    return math.exp(sum(xs) / len(xs))
+
+
+def scale_gap(r_ref: float, prefactor: float) -> float:
+    """Z with R_lambda,ref = A e^(2Z/3), eq. (Rlambda_Z_relation)."""
+    return 1.5 * math.log(r_ref / prefactor)
 
 
 def mix(ws: Sequence[float], values: Sequence[Sequence[float]]) -> list[float]:

@@ -120,3 +120,114 @@ def test_cost_saving_matches_paper():
     g = GOLD["cost_saving"]
     r = mx.cost_ratio(g["rlambda_ref"], g["rlambda_ens"], g["n"])
     assert float(f"{r:.1e}") == g["value"]
+
+
+# ---------------------------------------------------------------- truncated Gaussian (appendix)
+@pytest.mark.parametrize("Z", [0.05, math.log(2), math.log(8), 3.0, 6.0])
+def test_truncated_gaussian_is_normalised_and_conserves_injection(Z):
+    """eq. (truncated_gaussian): int P = 1 and int P e^lambda = 1 (quadrature of the
+    density itself, independent of the closed-form root condition)."""
+    mu, sig = mx.truncated_params(C, Z)
+    assert abs(sig * sig - 9 * C * Z) <= 1e-15 * max(1.0, 9 * C * Z)
+    lo = mu - 40 * sig
+    norm, _ = integrate.quad(lambda l: mx.truncated_pdf(l, C, Z), lo, Z, limit=400, epsabs=1e-14, epsrel=1e-13)
+    inj, _ = integrate.quad(lambda l: mx.truncated_pdf(l, C, Z) * math.exp(l), lo, Z, limit=400, epsabs=1e-14,
+                            epsrel=1e-13)
+    assert abs(norm - 1) < 1e-11 and abs(inj - 1) < 1e-11
+    assert mx.truncated_pdf(Z + 1e-9, C, Z) == 0.0
+
+
+def test_truncated_gaussian_reduces_to_the_gaussian_when_the_cut_is_far():
+    """c -> 0 at fixed Z puts the cut many sigma above the mean: mu -> -sigma^2/2."""
+    for c in (1e-4, 1e-3):
+        mu, sig = mx.truncated_params(c, 2.0)
+        g_mu, g_sig = mx.gaussian_params(c, 2.0)
+        assert abs(mu - g_mu) <= 1e-12 and sig == g_sig
+    # at the paper's c the cut moves the mean up, and less for larger Z relative to sigma
+    mu2, s2 = mx.truncated_params(C, math.log(2))
+    assert mu2 > mx.gaussian_params(C, math.log(2))[0]
+
+
+def test_truncated_gaussian_cgf_slope_saturates_at_Z():
+    """d/dt K(t; Z) tends to the upper end of the support, lambda_max = Z (appendix).
+    K'(t) is the mean of the tilted density, a normal of mean mu + t sigma^2 cut at
+    Z: scipy's truncated normal gives it; quadrature checks it at moderate t; for
+    large t it approaches Z as Z - s2/D + 2 s2^2/D^3, D = mu + t s2 - Z, s2 = sigma^2
+    (the asymptotic series of the normal's Mills ratio)."""
+    from scipy.stats import truncnorm
+    Z = math.log(4)
+    mu, sig = mx.truncated_params(C, Z)
+    prev = -math.inf
+    for t in (0.5, 1.0, 10.0, 100.0, 1000.0):
+        m = mu + t * sig * sig
+        with np.errstate(invalid="ignore"):
+            k1 = float(truncnorm(-np.inf, (Z - m) / sig, loc=m, scale=sig).stats(moments="m"))
+        if t <= 10:
+            num, _ = integrate.quad(lambda l: l * mx.truncated_pdf(l, C, Z) * math.exp(t * (l - Z)), mu - 40 * sig, Z,
+                                    limit=400, epsabs=0, epsrel=1e-10)
+            den, _ = integrate.quad(lambda l: mx.truncated_pdf(l, C, Z) * math.exp(t * (l - Z)), mu - 40 * sig, Z,
+                                    limit=400, epsabs=0, epsrel=1e-10)
+            assert abs(num / den - k1) < 1e-9
+        assert prev < k1 < Z
+        prev = k1
+        if t >= 100:
+            D, s2 = m - Z, sig * sig
+            tol = 20 * s2 ** 3 / D ** 5 + 1e-12 if t <= 100 else 1e-7   # scipy's far-tail mean: ~1e-8
+            assert abs((Z - k1) - (s2 / D - 2 * s2 * s2 / D ** 3)) < tol
+    assert prev > Z - 1.1e-3
+
+
+def test_truncated_weights_are_bin_masses_of_the_density():
+    """Mode 3 weights = quadrature of the truncated density over each member's bin;
+    members above the cut get nothing; they sum to 1."""
+    lam = paper_lambda_grid()
+    for Z in (math.log(2), math.log(8)):
+        w = mx.weights(lam, C, Z, mode=3)
+        assert abs(sum(w) - 1) < 1e-14
+        edges = mx.cell_edges(lam, 0)
+        mu, sig = mx.truncated_params(C, Z)
+        for (a, b), wi, l in zip(edges, w, lam):
+            if a >= Z:
+                assert wi == 0.0
+                continue
+            lo = max(a, mu - 40 * sig)
+            hi = min(b, Z)
+            ref, _ = integrate.quad(lambda x: mx.truncated_pdf(x, C, Z), lo, hi, epsabs=1e-16, epsrel=1e-12) \
+                if hi > lo else (0.0, 0.0)
+            assert abs(wi - ref) <= 1e-12 * max(ref, 1e-300) + 1e-17, (l, wi, ref)
+    assert mx.weights(lam, C, 0.0, mode=3)[lam.index(0.0)] == 1.0
+
+
+# ---------------------------------------------------------------- scale gap from R_lambda
+def test_rlambda_from_means_closed_form():
+    """u' = 1, eps = 15 nu gives lambda_T = 1 and R_lambda = 1/nu."""
+    nu = 0.01
+    assert abs(mx.rlambda_from_means(1.5, 15 * nu, nu) - 1 / nu) < 1e-12
+
+
+def test_prefactor_fit_recovers_an_exact_power_law_and_ignores_negative_lambda():
+    lam = paper_lambda_grid()
+    A = 63.0
+    rls = [A * math.exp(l / 6) * (1.0 if l >= 0 else 7.0) for l in lam]   # lambda < 0 members must not count
+    assert abs(mx.rlambda_prefactor(lam, rls) - A) < 1e-12 * A
+    # log-least-squares with fixed slope: geometric mean of R e^(-lambda/6) over lambda >= 0
+    rls2 = [A * math.exp(l / 6) * (1.1 if i % 2 else 1 / 1.1) for i, l in enumerate(lam)]
+    sel = [(l, r) for l, r in zip(lam, rls2) if l >= 0]
+    gm = math.exp(sum(math.log(r) - l / 6 for l, r in sel) / len(sel))
+    assert abs(mx.rlambda_prefactor(lam, rls2) - gm) < 1e-12 * gm
+    with pytest.raises(ValueError):
+        mx.rlambda_prefactor([-1.0, -0.5], [10.0, 12.0])
+
+
+def test_scale_gap_reproduces_the_reference_table():
+    """Table II from Table I's central member: the ens256 centre (R = 63, box 4 pi)
+    against references in boxes 8, 16, 32 pi (Z = ln 2, ln 4, ln 8) predicts
+    R_lambda,ref = 63 e^(2Z/3) = 100, 159, 252 against the printed 103, 173, 261
+    (within 10 %: the printed centre is one member, not the fit); an exponent of
+    1/3 or 4/3 instead of 2/3 would miss by a factor 1.3-16."""
+    r_ens = GOLD["ens256_rlambda_central"]["value"]
+    for Z, r_ref in zip((math.log(2), math.log(4), math.log(8)), GOLD["reference_rlambda"]["value"]):
+        z = mx.scale_gap(r_ref, r_ens)
+        assert abs(z - Z) < 0.15
+        assert abs(r_ens * math.exp(2 * Z / 3) - r_ref) / r_ref < 0.10
+    assert mx.scale_gap(r_ens, r_ens) == 0.0
