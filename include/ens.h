@@ -212,7 +212,9 @@ ens_status ens_accumulate_stats(ens_ctx *ctx, const int32_t *members, int32_t co
  * moments (32) = [0..5] sum A*_L^p, [6..11] sum A*_T^p (p = 1..6; 3 and 6
  * samples per point), [12..15] sum eps*^p, [16..19] sum Omega*^p (p = 1..4),
  * [20] sum Q*, [21] sum R*, [22] sum S*_ij S*_ij, [23] sum (Tr A*)^2,
- * [24] sum Q*^2, [25] sum R*^2, [26..31] 0. */
+ * [24] sum Q*^2, [25] sum R*^2, [26] sum over snapshots of the member's
+ * energy E and [27] of its dissipation D (the values of its last step, i.e. of
+ * the field the snapshot sees), [28] number of snapshots, [29..31] 0. */
 #define ENS_NMOM 32
 ens_status ens_stats_len(const ens_ctx *ctx, size_t *n_counts);
 
@@ -232,8 +234,13 @@ ens_status ens_reset_stats(ens_ctx *ctx, int32_t m, void *stream);
  * eq. gaussian_lambda_pdf; each member gets the mass of its lambda bin).
  * Bins: members sorted by lambda, edges at midpoints; mode 0: end bins open to
  * +-inf; mode 1: end bins closed at half a spacing, weights renormalised;
- * mode 2: w_i proportional to P(lambda_i; Z)/q(lambda_i), q = N(0, q_sigma^2).
+ * mode 2: w_i proportional to P(lambda_i; Z)/q(lambda_i), q = N(0, q_sigma^2);
+ * mode 3: the truncated Gaussian of the appendix (eq. truncated_gaussian:
+ * variance 9cZ, support lambda <= Z, its mean set on the host by bisection so
+ * that the mean-injection constraint, eq. mean_injection_constraint, holds),
+ * bins as in mode 0, each member the mass of its bin below Z.
  * Z = 0 puts all weight on the member whose bin holds lambda = 0.
+ * Mixed moments [26..31] are 0 (the snapshot sums of E and D are per member).
  * Writes to device memory `dev_out` (FP64, ens_mix_len elements):
  *   [weights: count][QR pdf: qb*qb][log eps* pdf: lb][log Omega* pdf: lb]
  *   [A_L pdf: ab][A_T pdf: ab][mixed mean moments: ENS_NMOM]
@@ -244,6 +251,22 @@ ens_status ens_reset_stats(ens_ctx *ctx, int32_t m, void *stream);
 ens_status ens_mix_len(const ens_ctx *ctx, int32_t count, size_t *n_out);
 ens_status ens_mix(ens_ctx *ctx, const int32_t *members, int32_t count, double c, double Z,
                    int32_t weight_mode, double q_sigma, double *dev_out, void *stream);
+
+/* Scale gap Z for a target Taylor-scale Reynolds number (section
+ * "Benchmarking the method against DNS data", eq. Rlambda_Z_relation, with
+ * C_eps constant as in eq. Re_definition).  Each member's R_lambda is formed
+ * from its snapshot-averaged energy and dissipation (moments [26..28]):
+ * R_lambda = (2<E>/3) sqrt(15 / (nu <D>)).  C_eps constant makes
+ * Re ~ e^(lambda/3) across members at fixed L and nu, so R_lambda = A e^(lambda/6);
+ * A is fitted (least squares in ln R_lambda, slope fixed) over the members
+ * with lambda >= 0, and Z = (3/2) ln(rlambda_ref / A) (negative if the target
+ * is below the fitted central value).  Host outputs: *Z_out, *prefactor_out
+ * (= A) and, if not NULL, rlambda_out[count] (each member's R_lambda, in the
+ * order given).  Synchronises.  Errors: ENS_E_INVALID for bad ids, a
+ * non-positive target or no member with lambda >= 0; ENS_E_STATE without a
+ * histogram descriptor or for a member with no snapshot. */
+ens_status ens_scale_gap(ens_ctx *ctx, const int32_t *members, int32_t count, double rlambda_ref,
+                         double *Z_out, double *prefactor_out, double *rlambda_out);
 
 /* ---------------------------------------------------- spectral diagnostics */
 

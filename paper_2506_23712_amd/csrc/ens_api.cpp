@@ -599,7 +599,7 @@ ENS_API ens_status ens_mix(ens_ctx *ctx, const int32_t *members, int32_t count, 
     if (!dev_out) return fail(ENS_E_INVALID, "null output pointer");
     if (count > mix_max_members()) return fail(ENS_E_INVALID, "too many members for one mixture call");
     if (!(c > 0) || !(Z >= 0) || !std::isfinite(Z)) return fail(ENS_E_INVALID, "need c > 0 and Z >= 0");
-    if (weight_mode < 0 || weight_mode > 2) return fail(ENS_E_INVALID, "weight_mode must be 0, 1 or 2");
+    if (weight_mode < 0 || weight_mode > 3) return fail(ENS_E_INVALID, "weight_mode must be 0, 1, 2 or 3");
     if (weight_mode == 2 && (!(q_sigma > 0) || !(Z > 0))) return fail(ENS_E_INVALID, "mode 2 needs q_sigma > 0 and Z > 0");
     HIPCK(ctx, hipSetDevice(ctx->device));
     std::vector<const MemberDev *> mds;
@@ -619,6 +619,40 @@ ENS_API ens_status ens_mix(ens_ctx *ctx, const int32_t *members, int32_t count, 
     }
     HIPCK(ctx, launch_mix(mds.data(), lam.data(), count, ctx->hist, c, Z, weight_mode, q_sigma, dev_out,
                           ctx->mix_scratch, s));
+    return ENS_OK;
+}
+
+ENS_API ens_status ens_scale_gap(ens_ctx *ctx, const int32_t *members, int32_t count, double rlambda_ref,
+                                 double *Z_out, double *prefactor_out, double *rlambda_out) {
+    if (ens_status st = check_ctx(ctx)) return st;
+    if (!ctx->has_hist) return fail(ENS_E_STATE, "context has no histogram descriptor");
+    std::vector<int> ids;
+    if (ens_status st = collect_ids(ctx, members, count, ids)) return st;
+    if (!Z_out || !prefactor_out) return fail(ENS_E_INVALID, "null output pointer");
+    if (!(rlambda_ref > 0) || !std::isfinite(rlambda_ref)) return fail(ENS_E_INVALID, "need R_lambda,ref > 0");
+    HIPCK(ctx, hipSetDevice(ctx->device));
+    std::vector<double> rl(ids.size());
+    double acc = 0.0;
+    int used = 0;
+    for (size_t i = 0; i < ids.size(); i++) {
+        Member *m = ctx->members[ids[i]].get();
+        HIPCK(ctx, hipStreamSynchronize(m->last));
+        double mom[3];
+        HIPCK(ctx, hipMemcpy(mom, m->md.moments + 26, sizeof(mom), hipMemcpyDeviceToHost));
+        if (!(mom[2] > 0)) return fail(ENS_E_STATE, "a member has no statistics snapshot");
+        const double E = mom[0] / mom[2], D = mom[1] / mom[2];
+        if (!(E > 0) || !(D > 0)) return fail(ENS_E_STATE, "a member has no positive mean energy and dissipation");
+        rl[i] = (2.0 * E / 3.0) * std::sqrt(15.0 / (m->d.nu * D));
+        if (m->d.lambda >= 0.0) {
+            acc += std::log(rl[i]) - m->d.lambda / 6.0;
+            used++;
+        }
+    }
+    if (!used) return fail(ENS_E_INVALID, "no member with lambda >= 0");
+    const double A = std::exp(acc / used);
+    *prefactor_out = A;
+    *Z_out = 1.5 * std::log(rlambda_ref / A);
+    if (rlambda_out) std::copy(rl.begin(), rl.end(), rlambda_out);
     return ENS_OK;
 }
 

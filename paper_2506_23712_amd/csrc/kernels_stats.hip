@@ -404,6 +404,13 @@ __global__ void __launch_bounds__(256) k_stats_reduce(const MemberDev *__restric
         if (threadIdx.x == 0) md.moments[i] += red[0];
         __syncthreads();
     }
+    // snapshot sums of the member's energy and dissipation (its last step's
+    // values, those of the field this snapshot sees) and the snapshot count
+    if (threadIdx.x == 0) {
+        md.moments[26] += md.st->diag.E;
+        md.moments[27] += md.st->diag.D;
+        md.moments[28] += 1.0;
+    }
 }
 
 // Workgroups per member of the persistent statistics pass: about 2048 in
@@ -544,7 +551,28 @@ __device__ double nmass(double a, double b, double mu, double sig) {
 
 constexpr int kMaxMix = 1023;
 
-__global__ void __launch_bounds__(1024) k_mix_weights(MixIn *mi, int count, double c, double Z, int mode, double qs, double *out) {
+// Mean of the truncated Gaussian in lambda (support lambda <= Z, variance
+// 9cZ, eq. truncated_gaussian) that satisfies the mean-injection constraint.
+// For a normal of mean mu cut at Z, ln int P e^lambda =
+//   mu + s2/2 + ln Phi((Z - mu - s2)/s) - ln Phi((Z - mu)/s),
+// increasing in mu, negative at mu = -s2/2 (the uncut root), tending to Z
+// for large mu: bracketed by doubling steps, then bisected to the last bit.
+static double truncated_mean(double c, double Z) {
+    const double s = std::sqrt(9.0 * c * Z), s2 = s * s;
+    auto lnPhi = [](double x) { return std::log(0.5 * std::erfc(-x / std::sqrt(2.0))); };
+    auto g = [&](double mu) { return mu + 0.5 * s2 + lnPhi((Z - mu - s2) / s) - lnPhi((Z - mu) / s); };
+    double lo = -0.5 * s2, step = std::max(s, 1e-3), hi = lo + step;
+    while (g(hi) <= 0.0) { lo = hi; step *= 2.0; hi = lo + step; }
+    for (int it = 0; it < 400; it++) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        (g(mid) > 0.0 ? hi : lo) = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+__global__ void __launch_bounds__(1024) k_mix_weights(MixIn *mi, int count, double c, double Z, int mode, double qs,
+                                                      double mu3, double *out) {
     __shared__ double raw[kMaxMix + 1];
     const int i = threadIdx.x;
     double w = 0.0;
@@ -573,6 +601,9 @@ __global__ void __launch_bounds__(1024) k_mix_weights(MixIn *mi, int count, doub
             w = p / q;
         } else if (Z <= 0.0) {
             w = (a <= 0.0 && 0.0 < b) ? 1.0 : 0.0;
+        } else if (mode == 3) {
+            const double sig = sqrt(9.0 * c * Z);
+            w = a < Z ? nmass(a, b < Z ? b : Z, mu3, sig) / nmass(-INFINITY, Z, mu3, sig) : 0.0;
         } else {
             w = nmass(a, b, -4.5 * c * Z, sqrt(9.0 * c * Z));
         }
@@ -669,7 +700,8 @@ hipError_t launch_mix(const MemberDev *const *members_host, const double *lambda
     e = hipStreamSynchronize(s);       // tmp is freed on return
     if (e != hipSuccess) return e;
     k_mix_prep<<<count, 256, 0, s>>>(mi, hg.off_le);
-    k_mix_weights<<<1, 1024, 0, s>>>(mi, count, c, Z, mode, q_sigma, out);
+    const double mu3 = (mode == 3 && Z > 0.0) ? truncated_mean(c, Z) : 0.0;
+    k_mix_weights<<<1, 1024, 0, s>>>(mi, count, c, Z, mode, q_sigma, mu3, out);
     MixGeom g;
     g.qb = hg.qb; g.lb = hg.lb; g.ab = hg.ab; g.count = count;
     g.off_le = hg.off_le; g.off_lw = hg.off_lw; g.off_al = hg.off_al; g.off_at = hg.off_at;

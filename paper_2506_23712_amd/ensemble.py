@@ -249,6 +249,15 @@ class Ensemble:
                    H_trans=float(d[4]), mean_eps=float(d[5]), mean_ens=float(d[6]))
         return res
 
+    def scale_gap(self, rlambda_ref: float, members=None) -> dict:
+        """Z for a target R_lambda from the members' snapshot-averaged R_lambda
+        (prefactor A of R_lambda = A e^(lambda/6) fitted over lambda >= 0)."""
+        ms = members if members is not None else self.members
+        Z, A = ctypes.c_double(), ctypes.c_double()
+        rl = (ctypes.c_double * len(ms))()
+        check(lib().ens_scale_gap(self.ctx, _ids(ms), len(ms), rlambda_ref, ctypes.byref(Z), ctypes.byref(A), rl))
+        return {"Z": Z.value, "prefactor": A.value, "rlambda": list(rl)}
+
     def close(self) -> None:
         if self.ctx:
             torch.cuda.synchronize(self.device)

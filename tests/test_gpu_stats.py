@@ -92,7 +92,8 @@ def test_mixture_matches_oracle(orc):
     for l, s in zip(lams, states):
         c, mom, near, _ = orc.stats(orc.Member(n=16, nu=0.02, eps=0.1 * math.exp(l), kf_hi=2.0, dt=0.01), h, s)
         per.append((c, mom))
-    for mode, Z in ((0, math.log(8)), (1, math.log(4)), (0, 0.0), (2, math.log(2))):
+    for mode, Z in ((0, math.log(8)), (1, math.log(4)), (0, 0.0), (2, math.log(2)), (3, math.log(8)),
+                    (3, math.log(2)), (3, 0.0), (3, 6.0)):
         res = E.mix(0.023, Z, mode=mode, q_sigma=math.sqrt(2))
         w = mx.weights(lams, 0.023, Z, mode=mode, q_sigma=math.sqrt(2))
         assert np.allclose(res["weights"].numpy(), w, rtol=1e-13, atol=1e-16)
@@ -108,4 +109,47 @@ def test_mixture_matches_oracle(orc):
         assert np.all(np.abs(res["moments"].numpy()[:26] - mm) <= 1e-11 * scale)
         assert math.isclose(res["S_long"], mx.skewness(mm[1], mm[2]), rel_tol=1e-10)
         assert math.isclose(res["F_trans"], mx.flatness(mm[7], mm[9]), rel_tol=1e-10)
+    E.close()
+
+
+def test_scale_gap_from_snapshot_averaged_rlambda(orc):
+    """Snapshot sums of E and D land in moments [26..28]; the scale gap for a
+    target R_lambda follows the oracle's fit of R_lambda = A e^(lambda/6) over
+    the members with lambda >= 0 and Z = (3/2) ln(R_ref / A)."""
+    import paper_2506_23712_amd as ens
+    from oracle import mixture as mx
+    lams = [-1.0, 0.0, 0.5, 1.0, 2.0]
+    nu = 0.02
+    E = ens.Ensemble(hist=ens.HistSpec(**HK))
+    ms = [E.add_member(ens.MemberSpec(n=16, nu=nu, eps_ref=0.1, lam=l, kf_hi=2.0, dt=0.01, seed=70 + i))
+          for i, l in enumerate(lams)]
+    with pytest.raises(ens.EnsError):
+        E.scale_gap(100.0)                              # no snapshot yet
+    sums = [[0.0, 0.0] for _ in ms]
+    for _ in range(4):
+        E.step(3)
+        E.accumulate_stats()
+        for k, m in enumerate(ms):
+            d = m.diag()
+            sums[k][0] += d["E"]
+            sums[k][1] += d["D"]
+    rls = []
+    for k, m in enumerate(ms):
+        _, mom, _ = m.stats()
+        mom = mom.numpy()
+        assert mom[26] == sums[k][0] and mom[27] == sums[k][1] and mom[28] == 4.0
+        assert np.all(mom[29:] == 0)
+        rls.append(mx.rlambda_from_means(mom[26] / 4, mom[27] / 4, nu))
+    A = mx.rlambda_prefactor(lams, rls)
+    for r_ref in (3.0, 50.0, 400.0):
+        res = E.scale_gap(r_ref)
+        assert np.allclose(res["rlambda"], rls, rtol=1e-14, atol=0)
+        assert math.isclose(res["prefactor"], A, rel_tol=1e-14)
+        assert math.isclose(res["Z"], mx.scale_gap(r_ref, A), rel_tol=1e-13, abs_tol=1e-14)
+    # only the lambda < 0 member: no fit
+    with pytest.raises(ens.EnsError):
+        E.scale_gap(100.0, members=ms[:1])
+    ms[1].reset_stats()
+    with pytest.raises(ens.EnsError):
+        E.scale_gap(100.0)
     E.close()
