@@ -169,6 +169,51 @@ def z_from_rlambda(r_target: float, r_anchor: float, z_anchor: float) -> float:
     return z_anchor + 1.5 * math.log(r_target / r_anchor)
 
 
+def lambda_pdf_from_cf(phi, lam0: float, h: float):
+    """Density P(lambda) on the grid lambda_j = lam0 + j h (j = 0 .. M-1) from
+    samples of its characteristic function phi_k = exp(K(i omega_k; Z)), the
+    cumulant generating function (eq. cumulant_generating_function) at imaginary
+    argument, omega_k = 2 pi f_k with f_k numpy's FFT frequencies of M points at
+    spacing h (section "Modeling choices": the two-sided Laplace transform is
+    inverted by a Fourier transform).  P_j = Re sum_k phi_k e^(-i omega_k lambda_j) / (M h):
+    the rectangle rule of the inverse Fourier integral, one FFT (numpy's)."""
+    import numpy as np
+    phi = np.asarray(phi, dtype=np.complex128)
+    M = phi.shape[0]
+    omega = 2.0 * np.pi * np.fft.fftfreq(M, d=h)
+    return np.real(np.fft.fft(phi * np.exp(-1j * omega * lam0))) / (M * h)
+
+
+def cf_omegas(M: int, h: float):
+    """The frequencies omega_k at which lambda_pdf_from_cf expects its samples."""
+    import numpy as np
+    return 2.0 * np.pi * np.fft.fftfreq(M, d=h)
+
+
+def weights_from_table(lams: Sequence[float], pdf: Sequence[float], lam0: float, h: float) -> list[float]:
+    """Member weights from a tabulated lambda density: negative samples (ringing of
+    the Fourier inversion) set to zero, the density linear between samples and
+    zero outside the table, each member the integral over its bin (mode-0 bins:
+    midpoints, open end bins), normalised by the sum of the bin integrals."""
+    p = [max(0.0, float(v)) for v in pdf]
+    M = len(p)
+
+    def integral(a, b):
+        tot = 0.0
+        for s in range(M - 1):
+            x0, x1 = lam0 + s * h, lam0 + (s + 1) * h
+            lo, hi = max(a, x0), min(b, x1)
+            if hi <= lo:
+                continue
+            f = lambda x: p[s] + (p[s + 1] - p[s]) * (x - x0) / h
+            tot += (hi - lo) * 0.5 * (f(lo) + f(hi))
+        return tot
+
+    raw = [integral(a, b) for a, b in cell_edges(lams, 0)]
+    s = sum(raw)
+    return [r / s for r in raw]
+
+
 def rlambda_from_means(e_mean: float, d_mean: float, nu: float) -> float:
     """Taylor-scale Reynolds number from time-averaged energy and dissipation:
     u'^2 = 2<E>/3, lambda_T = sqrt(15 nu u'^2 / <D>), R_lambda = u' lambda_T / nu."""

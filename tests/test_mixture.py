@@ -231,3 +231,58 @@ def test_scale_gap_reproduces_the_reference_table():
         assert abs(z - Z) < 0.15
         assert abs(r_ens * math.exp(2 * Z / 3) - r_ref) / r_ref < 0.10
     assert mx.scale_gap(r_ens, r_ens) == 0.0
+
+
+# ---------------------------------------------------------------- lambda density from the CGF
+def test_cf_inversion_of_the_quadratic_cgf_is_the_gaussian():
+    """exp(K(i omega; Z)) with K = 9cZ (t^2 - t)/2 (quadratic exponents) inverts to
+    the Gaussian of eq. (gaussian_lambda_pdf)."""
+    Z, M, h, lam0 = math.log(8), 1024, 0.02, -10.24
+    om = mx.cf_omegas(M, h)
+    t = 1j * om
+    phi = np.exp(9 * C * Z * (t * t - t) / 2)
+    pdf = mx.lambda_pdf_from_cf(phi, lam0, h)
+    lam = lam0 + h * np.arange(M)
+    ref = np.array([mx.lambda_pdf(l, C, Z) for l in lam])
+    assert np.max(np.abs(pdf - ref)) < 1e-12 * ref.max()
+
+
+def test_cf_inversion_of_a_shifted_gamma_cgf():
+    """A skewed family with K linear in Z and K(1; Z) = 0: lambda = s - G with G
+    Gamma-distributed (shape aZ, rate b), K(t) = aZ [t ln(1 + 1/b) - ln(1 + t/b)];
+    scipy's gamma density gives the exact P."""
+    from scipy import stats
+    a, b, Z = 3.0, 4.0, 1.5
+    s = a * Z * math.log(1 + 1 / b)
+    M, h, lam0 = 4096, 0.005, -12.0
+    t = 1j * mx.cf_omegas(M, h)
+    phi = np.exp(a * Z * (t * math.log(1 + 1 / b) - np.log(1 + t / b)))
+    pdf = mx.lambda_pdf_from_cf(phi, lam0, h)
+    lam = lam0 + h * np.arange(M)
+    ref = stats.gamma(a * Z, scale=1 / b).pdf(s - lam)
+    assert np.max(np.abs(pdf - ref)) < 2e-6 * ref.max()          # the density's kink-free tail limits the rule
+    # injection constraint of the exact density
+    inj, _ = integrate.quad(lambda x: stats.gamma(a * Z, scale=1 / b).pdf(s - x) * math.exp(x), -40, s, limit=200)
+    assert abs(inj - 1) < 1e-10
+
+
+def test_table_weights_integrate_the_piecewise_linear_density():
+    """A triangle density on [0, 2] tabulated exactly: bins integrate it exactly."""
+    h, lam0 = 0.5, -1.0
+    pdf = [0.0, 0.0, 0.0, 0.5, 1.0, 0.5, 0.0, -0.1]         # lambda = -1 .. 2.5; last sample clamps to 0
+    lams = [0.25, 1.0, 1.75]
+    w = mx.weights_from_table(lams, pdf, lam0, h)
+    # bins (-inf, 0.625), [0.625, 1.375), [1.375, inf); triangle area 1
+    F = lambda x: 0.0 if x <= 0 else (x * x / 2 if x <= 1 else (1 - (2 - x) ** 2 / 2 if x < 2 else 1.0))
+    ref = [F(0.625), F(1.375) - F(0.625), 1 - F(1.375)]
+    assert np.allclose(w, ref, rtol=1e-15, atol=1e-16)
+
+
+def test_table_weights_of_the_gaussian_table_approach_the_gaussian_bin_masses():
+    lam = paper_lambda_grid()
+    Z, h, lam0 = math.log(8), 0.001, -12.0
+    grid = lam0 + h * np.arange(24001)
+    pdf = [mx.lambda_pdf(l, C, Z) for l in grid]
+    w = mx.weights_from_table(lam, pdf, lam0, h)
+    ref = mx.weights(lam, C, Z, mode=0)
+    assert np.max(np.abs(np.array(w) - ref)) < 1e-7
