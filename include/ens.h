@@ -252,6 +252,33 @@ ens_status ens_mix_len(const ens_ctx *ctx, int32_t count, size_t *n_out);
 ens_status ens_mix(ens_ctx *ctx, const int32_t *members, int32_t count, double c, double Z,
                    int32_t weight_mode, double q_sigma, double *dev_out, void *stream);
 
+/* Mixture as ens_mix, with each member's weight the mass of its lambda bin
+ * (bins of mode 0: midpoints, open end bins) under a tabulated lambda density
+ * instead of a parametric one: for any exponent parameterisation whose lambda
+ * distribution follows from its cumulant generating function (eqs.
+ * exponents_KZ_1 and cumulant_generating_function; section "Modeling choices").
+ * dev_pdf: table_len FP64 samples in device memory at lam0 + j dlam; negative
+ * samples count as zero, the density is linear between samples and zero
+ * outside the table; weights are normalised to sum to 1.  Output layout as
+ * ens_mix.  Errors: ENS_E_INVALID for bad ids, table_len < 2, dlam <= 0, null
+ * pointers; ENS_E_STATE without a histogram descriptor. */
+ens_status ens_mix_table(ens_ctx *ctx, const int32_t *members, int32_t count, const double *dev_pdf,
+                         int32_t table_len, double lam0, double dlam, double *dev_out, void *stream);
+
+/* Lambda density from its characteristic function: the two-sided Laplace
+ * transform exp(K(t; Z)) of eq. cumulant_generating_function evaluated at
+ * t = i omega and inverted by a Fourier transform (section "Modeling
+ * choices").  dev_phi: table_len complex FP64 values (re, im interleaved) of
+ * exp(K(i omega_k; Z)) at omega_k = 2 pi f_k / (table_len dlam), f_k = k for
+ * k < table_len/2 and k - table_len otherwise (the FFT frequency order);
+ * dev_pdf (table_len doubles) receives
+ *   P(lam0 + j dlam) = Re sum_k phi_k exp(-i omega_k (lam0 + j dlam)) / (table_len dlam),
+ * the rectangle rule of the inverse Fourier integral, summed directly in a
+ * fixed order (deterministic).  Asynchronous on `stream`.  Errors:
+ * ENS_E_INVALID for table_len outside [2, 65536], dlam <= 0 or null pointers. */
+ens_status ens_lambda_pdf_from_cf(const double *dev_phi, int32_t table_len, double lam0, double dlam,
+                                  double *dev_pdf, void *stream);
+
 /* Scale gap Z for a target Taylor-scale Reynolds number (section
  * "Benchmarking the method against DNS data", eq. Rlambda_Z_relation, with
  * C_eps constant as in eq. Re_definition).  Each member's R_lambda is formed

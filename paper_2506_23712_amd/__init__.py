@@ -8,6 +8,6 @@ histograms) and their Gaussian-in-lambda mixture.  All arithmetic runs in
 libensdns.so (hand-written HIP for gfx950); see include/ens.h for the C ABI.
 """
 from ._lib import EnsError, lib
-from .ensemble import Ensemble, HistSpec, Member, MemberSpec, fft_pencils
+from .ensemble import Ensemble, HistSpec, Member, MemberSpec, fft_pencils, lambda_pdf_from_cf
 
-__all__ = ["Ensemble", "HistSpec", "Member", "MemberSpec", "EnsError", "fft_pencils", "lib"]
+__all__ = ["Ensemble", "HistSpec", "Member", "MemberSpec", "EnsError", "fft_pencils", "lambda_pdf_from_cf", "lib"]

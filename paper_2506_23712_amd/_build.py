@@ -7,8 +7,8 @@ from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = ["csrc/ens_api.cpp", "csrc/kernels_step.hip", "csrc/kernels_misc.hip", "csrc/kernels_stats.hip",
-           "csrc/kernels_diag.hip"]
-HEADERS = ["csrc/ens_internal.h", "csrc/ens_diag.h", "csrc/fft.hpp", "csrc/gmem.hpp", "../include/ens.h"]
+           "csrc/kernels_diag.hip", "csrc/kernels_lambda.hip"]
+HEADERS = ["csrc/ens_internal.h", "csrc/ens_diag.h", "csrc/ens_lambda.h", "csrc/fft.hpp", "csrc/gmem.hpp", "../include/ens.h"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-fvisibility=hidden",
          "-Wno-unused-result", "-Wno-unused-value",
          # no packed-FP32 instructions: hipcc would otherwise form them from scalar float code

@@ -17,6 +17,7 @@
 
 #include "ens_internal.h"
 #include "ens_diag.h"
+#include "ens_lambda.h"
 
 #define ENS_API extern "C" __attribute__((visibility("default")))
 
@@ -619,6 +620,47 @@ ENS_API ens_status ens_mix(ens_ctx *ctx, const int32_t *members, int32_t count, 
     }
     HIPCK(ctx, launch_mix(mds.data(), lam.data(), count, ctx->hist, c, Z, weight_mode, q_sigma, dev_out,
                           ctx->mix_scratch, s));
+    return ENS_OK;
+}
+
+ENS_API ens_status ens_mix_table(ens_ctx *ctx, const int32_t *members, int32_t count, const double *dev_pdf,
+                                 int32_t table_len, double lam0, double dlam, double *dev_out, void *stream) {
+    if (ens_status st = check_ctx(ctx)) return st;
+    if (!ctx->has_hist) return fail(ENS_E_STATE, "context has no histogram descriptor");
+    std::vector<int> ids;
+    if (ens_status st = collect_ids(ctx, members, count, ids)) return st;
+    if (!dev_out || !dev_pdf) return fail(ENS_E_INVALID, "null pointer");
+    if (count > mix_max_members()) return fail(ENS_E_INVALID, "too many members for one mixture call");
+    if (table_len < 2 || !(dlam > 0) || !std::isfinite(lam0) || !std::isfinite(dlam))
+        return fail(ENS_E_INVALID, "need table_len >= 2, dlam > 0 and a finite grid");
+    HIPCK(ctx, hipSetDevice(ctx->device));
+    std::vector<const MemberDev *> mds;
+    std::vector<double> lam;
+    for (int id : ids) {
+        mds.push_back(&ctx->members[id]->md);
+        lam.push_back(ctx->members[id]->d.lambda);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    for (int id : ids) HIPCK(ctx, hipStreamSynchronize(ctx->members[id]->last));
+    const size_t need = mix_scratch_bytes(count);
+    if (need > ctx->mix_scratch_bytes) {
+        if (ctx->mix_scratch) HIPCK(ctx, hipFree(ctx->mix_scratch));
+        ctx->mix_scratch = nullptr;
+        HIPCK(ctx, hipMalloc(&ctx->mix_scratch, need));
+        ctx->mix_scratch_bytes = need;
+    }
+    HIPCK(ctx, launch_mix_table(mds.data(), lam.data(), count, ctx->hist, 1.0, 0.0, 4, 1.0, dev_pdf, table_len, lam0,
+                                dlam, dev_out, ctx->mix_scratch, s));
+    return ENS_OK;
+}
+
+ENS_API ens_status ens_lambda_pdf_from_cf(const double *dev_phi, int32_t table_len, double lam0, double dlam,
+                                          double *dev_pdf, void *stream) {
+    if (!dev_phi || !dev_pdf) return fail(ENS_E_INVALID, "null pointer");
+    if (table_len < 2 || table_len > kMaxCfTable || !(dlam > 0) || !std::isfinite(lam0) || !std::isfinite(dlam))
+        return fail(ENS_E_INVALID, "need 2 <= table_len <= 65536, dlam > 0 and a finite grid");
+    const hipError_t e = launch_cf_invert(dev_phi, table_len, lam0, dlam, dev_pdf, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(ENS_E_HIP, hipGetErrorString(e));
     return ENS_OK;
 }
 

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "ens_internal.h"
+#include "ens_lambda.h"
 #include "fft.hpp"
 #include "gmem.hpp"
 #include <cmath>
@@ -525,6 +526,12 @@ struct MixIn {
     int pad;
 };
 
+struct MixTable {
+    const double *p;  // tabulated lambda density (mode 4), M samples
+    int M;
+    double lam0, h;
+};
+
 __global__ void __launch_bounds__(256) k_mix_prep(MixIn *mi, long long nqr) {
     __shared__ unsigned long long red[256];
     unsigned long long s = 0;
@@ -571,8 +578,30 @@ static double truncated_mean(double c, double Z) {
     return 0.5 * (lo + hi);
 }
 
+// Integral over [a, b) of a tabulated lambda density: samples p_j at
+// lam0 + j h (negative samples read as zero), linear in between, zero outside.
+// Segments are visited in increasing order.
+__device__ double table_mass(const MixTable &t, double a, double b) {
+    const double x_end = t.lam0 + (t.M - 1) * t.h;
+    const double lo = a > t.lam0 ? a : t.lam0, hi = b < x_end ? b : x_end;
+    if (!(hi > lo)) return 0.0;
+    int s0 = (int)floor((lo - t.lam0) / t.h), s1 = (int)floor((hi - t.lam0) / t.h);
+    if (s0 < 0) s0 = 0;
+    if (s1 > t.M - 2) s1 = t.M - 2;
+    double acc = 0.0;
+    for (int s = s0; s <= s1; s++) {
+        const double x0 = t.lam0 + s * t.h, x1 = x0 + t.h;
+        const double u = lo > x0 ? lo : x0, v = hi < x1 ? hi : x1;
+        if (!(v > u)) continue;
+        const double p0 = t.p[s] > 0.0 ? t.p[s] : 0.0, p1 = t.p[s + 1] > 0.0 ? t.p[s + 1] : 0.0;
+        const double fu = p0 + (p1 - p0) * (u - x0) / t.h, fv = p0 + (p1 - p0) * (v - x0) / t.h;
+        acc += (v - u) * 0.5 * (fu + fv);
+    }
+    return acc;
+}
+
 __global__ void __launch_bounds__(1024) k_mix_weights(MixIn *mi, int count, double c, double Z, int mode, double qs,
-                                                      double mu3, double *out) {
+                                                      double mu3, MixTable tab, double *out) {
     __shared__ double raw[kMaxMix + 1];
     const int i = threadIdx.x;
     double w = 0.0;
@@ -594,7 +623,9 @@ __global__ void __launch_bounds__(1024) k_mix_weights(MixIn *mi, int count, doub
             if (!has_prev) a = li - (b - li);
             if (!has_next) b = li + (li - a);
         }
-        if (mode == 2) {
+        if (mode == 4) {
+            w = table_mass(tab, a, b);
+        } else if (mode == 2) {
             const double mu = -4.5 * c * Z, sig = sqrt(9.0 * c * Z);
             const double p = exp(-(li - mu) * (li - mu) / (2.0 * sig * sig)) / sig;
             const double q = exp(-li * li / (2.0 * qs * qs)) / qs;
@@ -610,14 +641,14 @@ __global__ void __launch_bounds__(1024) k_mix_weights(MixIn *mi, int count, doub
     }
     raw[i] = w;
     __syncthreads();
-    if (i == 0 && (mode == 1 || mode == 2)) {
+    if (i == 0 && (mode == 1 || mode == 2 || mode == 4)) {
         double s = 0.0;
         for (int r = 0; r < count; r++) s += raw[mi[r].order];
         raw[kMaxMix] = s;    // count <= kMaxMix keeps this slot free
     }
     __syncthreads();
     if (i < count) {
-        if (mode == 1 || mode == 2) w = w / raw[kMaxMix];
+        if (mode == 1 || mode == 2 || mode == 4) w = w / raw[kMaxMix];
         mi[i].w = w;
         out[i] = w;
     }
@@ -685,7 +716,14 @@ int mix_max_members() { return kMaxMix; }
 
 hipError_t launch_mix(const MemberDev *const *members_host, const double *lambdas, int count, const ens_hist_desc &h,
                       double c, double Z, int mode, double q_sigma, double *out, void *scratch, hipStream_t s) {
+    return launch_mix_table(members_host, lambdas, count, h, c, Z, mode, q_sigma, nullptr, 0, 0.0, 0.0, out, scratch, s);
+}
+
+hipError_t launch_mix_table(const MemberDev *const *members_host, const double *lambdas, int count,
+                            const ens_hist_desc &h, double c, double Z, int mode, double q_sigma, const double *table,
+                            int table_len, double lam0, double dlam, double *out, void *scratch, hipStream_t s) {
     if (count <= 0 || count > kMaxMix || !scratch) return hipErrorInvalidValue;
+    if (mode == 4 && (!table || table_len < 2 || !(dlam > 0))) return hipErrorInvalidValue;
     const HistGeom hg = make_hist_geom(h);
     std::vector<MixIn> tmp(count);
     for (int i = 0; i < count; i++) {
@@ -701,7 +739,9 @@ hipError_t launch_mix(const MemberDev *const *members_host, const double *lambda
     if (e != hipSuccess) return e;
     k_mix_prep<<<count, 256, 0, s>>>(mi, hg.off_le);
     const double mu3 = (mode == 3 && Z > 0.0) ? truncated_mean(c, Z) : 0.0;
-    k_mix_weights<<<1, 1024, 0, s>>>(mi, count, c, Z, mode, q_sigma, mu3, out);
+    MixTable tab;
+    tab.p = table; tab.M = table_len; tab.lam0 = lam0; tab.h = dlam;
+    k_mix_weights<<<1, 1024, 0, s>>>(mi, count, c, Z, mode, q_sigma, mu3, tab, out);
     MixGeom g;
     g.qb = hg.qb; g.lb = hg.lb; g.ab = hg.ab; g.count = count;
     g.off_le = hg.off_le; g.off_lw = hg.off_lw; g.off_al = hg.off_al; g.off_at = hg.off_at;

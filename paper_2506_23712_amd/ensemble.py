@@ -230,14 +230,30 @@ class Ensemble:
 
     def mix(self, c: float, Z: float, mode: int = 0, q_sigma: float = 1.0, members=None) -> dict:
         ms = members if members is not None else self.members
-        n = ctypes.c_size_t()
-        check(lib().ens_mix_len(self.ctx, len(ms), ctypes.byref(n)))
-        out = torch.zeros(n.value, dtype=torch.float64, device=self.device)
+        out = self._mix_out(len(ms))
         check(lib().ens_mix(self.ctx, _ids(ms), len(ms), c, Z, mode, q_sigma, ctypes.c_void_p(out.data_ptr()),
                             _stream_ptr()))
+        return self._split_mix(out, len(ms))
+
+    def mix_table(self, pdf: torch.Tensor, lam0: float, dlam: float, members=None) -> dict:
+        """Mixture with weights from a tabulated lambda density (float64 device
+        tensor sampled at lam0 + j dlam); same result layout as mix()."""
+        ms = members if members is not None else self.members
+        p = pdf.to(device=self.device, dtype=torch.float64).contiguous()
+        out = self._mix_out(len(ms))
+        check(lib().ens_mix_table(self.ctx, _ids(ms), len(ms), ctypes.c_void_p(p.data_ptr()), p.numel(), lam0, dlam,
+                                  ctypes.c_void_p(out.data_ptr()), _stream_ptr()))
+        return self._split_mix(out, len(ms))
+
+    def _mix_out(self, count: int) -> torch.Tensor:
+        n = ctypes.c_size_t()
+        check(lib().ens_mix_len(self.ctx, count, ctypes.byref(n)))
+        return torch.zeros(n.value, dtype=torch.float64, device=self.device)
+
+    def _split_mix(self, out: torch.Tensor, count: int) -> dict:
         o = out.cpu()
         h = self.hist
-        q, l, a, k = h.qr_bins, h.log_bins, h.a_bins, len(ms)
+        q, l, a, k = h.qr_bins, h.log_bins, h.a_bins, count
         res, pos = {}, 0
         for name, size in (("weights", k), ("qr", q * q), ("log_eps", l), ("log_ens", l), ("a_long", a),
                            ("a_trans", a), ("moments", _lib.ENS_NMOM), ("derived", 8)):
@@ -269,6 +285,18 @@ class Ensemble:
             self.close()
         except Exception:
             pass
+
+
+def lambda_pdf_from_cf(phi: torch.Tensor, lam0: float, dlam: float) -> torch.Tensor:
+    """Lambda density on lam0 + j dlam from exp(K(i omega_k; Z)) sampled at the FFT
+    frequencies omega_k = 2 pi f_k / (M dlam) (complex128 device tensor of M values)."""
+    if phi.dim() != 1 or not phi.is_cuda or phi.dtype != torch.complex128:
+        raise ValueError("phi must be a 1-D complex128 device tensor")
+    p = phi.contiguous()
+    out = torch.empty(p.numel(), dtype=torch.float64, device=p.device)
+    check(lib().ens_lambda_pdf_from_cf(ctypes.c_void_p(p.data_ptr()), p.numel(), lam0, dlam,
+                                       ctypes.c_void_p(out.data_ptr()), _stream_ptr()))
+    return out
 
 
 def fft_pencils(x: torch.Tensor, sign: int) -> torch.Tensor:

@@ -153,3 +153,53 @@ def test_scale_gap_from_snapshot_averaged_rlambda(orc):
     with pytest.raises(ens.EnsError):
         E.scale_gap(100.0)
     E.close()
+
+
+@pytest.mark.parametrize("M,family", [(1024, "quadratic"), (4096, "gamma"), (1000, "quadratic")])
+def test_lambda_density_from_characteristic_function_matches_oracle(M, family):
+    import torch
+    import paper_2506_23712_amd as ens
+    from oracle import mixture as mx
+    if family == "quadratic":
+        c, Z, h, lam0 = 0.023, math.log(8), 0.02, -10.0
+        t = 1j * mx.cf_omegas(M, h)
+        phi = np.exp(9 * c * Z * (t * t - t) / 2)
+    else:
+        a, b, Z, h, lam0 = 3.0, 4.0, 1.5, 0.005, -12.0
+        t = 1j * mx.cf_omegas(M, h)
+        phi = np.exp(a * Z * (t * math.log(1 + 1 / b) - np.log(1 + t / b)))
+    got = ens.lambda_pdf_from_cf(torch.from_numpy(phi).cuda(), lam0, h).cpu().numpy()
+    ref = mx.lambda_pdf_from_cf(phi, lam0, h)
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_mixture_with_tabulated_density_matches_oracle(orc):
+    import torch
+    import paper_2506_23712_amd as ens
+    from oracle import mixture as mx
+    lams = [0.6, -0.9, 0.0, 1.5, -2.2]
+    E = ens.Ensemble(hist=ens.HistSpec(**HK))
+    ms = [E.add_member(ens.MemberSpec(n=16, nu=0.02, eps_ref=0.1, lam=l, kf_hi=2.0, dt=0.01, seed=90 + i))
+          for i, l in enumerate(lams)]
+    E.step(3)
+    E.accumulate_stats()
+    M, h, lam0, c, Z = 2048, 0.01, -10.0, 0.023, math.log(8)
+    t = 1j * mx.cf_omegas(M, h)
+    pdf = ens.lambda_pdf_from_cf(torch.from_numpy(np.exp(9 * c * Z * (t * t - t) / 2)).cuda(), lam0, h)
+    res = E.mix_table(pdf, lam0, h)
+    w = mx.weights_from_table(lams, pdf.cpu().numpy().tolist(), lam0, h)
+    assert np.allclose(res["weights"].numpy(), w, rtol=1e-13, atol=1e-17)
+    assert abs(res["weights"].sum().item() - 1) < 1e-14
+    # close to the parametric Gaussian bin masses (the table is the same density)
+    g = E.mix(c, Z, mode=0)
+    assert np.max(np.abs(res["weights"].numpy() - g["weights"].numpy())) < 1e-5
+    # mixed QR pdf = weighted member pdfs, as in ens_mix
+    h_ = orc.Hist(**HK)
+    counts = [m.stats()[0].numpy().astype(np.uint64) for m in ms]
+    area = (60 / 64) * (120 / 64)
+    pdfs = [h_.split(cn)["qr"].ravel() / (16 ** 3 * area) for cn in counts]
+    ref = np.array(mx.mix(w, pdfs))
+    assert np.allclose(res["qr"].numpy().ravel(), ref, rtol=1e-12, atol=1e-300)
+    with pytest.raises(ens.EnsError):
+        E.mix_table(pdf[:1], lam0, h)
+    E.close()
