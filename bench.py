@@ -19,6 +19,9 @@ Workloads
   single256_fp64   : one 256^3 member, nu = 4.594e-3 (k_max eta ~ 1.5),
                      eps = 1, band |m| <= 2.5, CFL 0.5, FP64.
 The JSON line reports the first as `value` and the second beside it.
+  ens48_128_fp64   : (only with --only ens48_128_fp64) the 48-member 128^3 FP64
+                     set of the ensemble driver: lambda = i ln2/3, i = -22..25,
+                     band [1.4, 2.3], CFL 0.2, k_M eta = 3 for lambda = 0.
 """
 from __future__ import annotations
 
@@ -49,6 +52,11 @@ def ens96_specs(ens):
 def single256_specs(ens):
     return [ens.MemberSpec(n=256, nu=4.594e-3, eps_ref=1.0, lam=0.0, kf_lo=0.0, kf_hi=2.5, dt=0.0, cfl=0.5,
                            precision="fp64", seed=23712)]
+
+
+def ens48_128_specs(ens):
+    from paper_2506_23712_amd import run_ensemble
+    return run_ensemble.ens128_specs(ens, n=128, precision="fp64")
 
 
 def hist_for(ens, nu):
@@ -210,7 +218,9 @@ def main():
     ap.add_argument("--stats-every", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--only", choices=["ens96_mixed_fp32", "single256_fp64"], default=None)
+    ap.add_argument("--only", choices=["ens96_mixed_fp32", "single256_fp64", "ens48_128_fp64"], default=None,
+                    help="one workload; ens48_128_fp64 (the 48-member 128^3 FP64 set of the ensemble driver) "
+                         "runs only when named")
     ap.add_argument("--diagnostics", action="store_true",
                     help="only time the spectral diagnostics (spectrum, integral scales, refinement) and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -242,7 +252,11 @@ def main():
     if args.only in (None, "single256_fp64"):
         res["single"] = run_workload(ens, torch, "single256_fp64", single256_specs(ens), args.steps, args.warmup,
                                      args.stats_every, 4.594e-3, not args.no_autotune)
-    head = res.get("ens") or res["single"]
+    if args.only == "ens48_128_fp64":
+        specs = ens48_128_specs(ens)
+        res["ens48"] = run_workload(ens, torch, "ens48_128_fp64", specs, args.steps, args.warmup,
+                                    args.stats_every, specs[0].nu, not args.no_autotune)
+    head = res.get("ens") or res.get("single") or res["ens48"]
     out = {
         "metric": "grid-pt RK steps/s (batched FP32 ensemble; FP64 single member beside it)",
         "value": round(head["rate"], 1),
@@ -257,7 +271,7 @@ def main():
         "dtype": "f32" if head["name"].endswith("fp32") else "f64",
         "data": "synthetic (seeded random solenoidal fields)",
         "config": {"workload": head["name"],
-                   "members": 96 if head["name"].startswith("ens") else 1,
+                   "members": {"ens96_mixed_fp32": 96, "single256_fp64": 1, "ens48_128_fp64": 48}[head["name"]],
                    "grid_points_per_step": head["points"], "stats_every": args.stats_every,
                    "mixture": "c=0.023, Z=ln 8, open end bins"},
         "roofline": roofline(head),
@@ -274,7 +288,8 @@ def main():
     out["stats_snapshot_ms"] = {r["name"]: round(r["stats_snapshot_ms"], 3) for r in res.values()}
     out["kernel_variants"] = {k: v for r in res.values() for k, v in r["variants"].items()}
     if not args.no_cpu_baseline:
-        specs = ens96_specs(ens) if head["name"].startswith("ens") else single256_specs(ens)
+        specs = {"ens96_mixed_fp32": ens96_specs, "single256_fp64": single256_specs,
+                 "ens48_128_fp64": ens48_128_specs}[head["name"]](ens)
         out["cpu_baseline"] = cpu_baseline(specs)
     print(json.dumps(out))
 
