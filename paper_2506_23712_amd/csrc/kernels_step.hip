@@ -878,6 +878,13 @@ static hipError_t run_pass(int pass, int variant, const MemberDev *mem, int coun
             if constexpr (N >= 64) return run_xpass_dma<P, N, 8>(mem, count, stage, twp, s);
             else return run_pencil<P, N, 8>(pass, mem, count, stage, twp, s);   // lines too short to stream
         }
+        if (pass == P_XPASS && variant == 3) {
+            // streamed, 16 values per thread (one LDS exchange per 256-point
+            // transform); FP32 only: FP64 would need more than 256 registers
+            if constexpr (N >= 128 && N <= 512 && sizeof(P) == 4) return run_xpass_dma<P, N, 16>(mem, count, stage, twp, s);
+            else if constexpr (N >= 64) return run_xpass_dma<P, N, 8>(mem, count, stage, twp, s);
+            else return run_pencil<P, N, 8>(pass, mem, count, stage, twp, s);
+        }
         return variant == 1 ? run_pencil<P, N, 16>(pass, mem, count, stage, twp, s)
                             : run_pencil<P, N, 8>(pass, mem, count, stage, twp, s);
     case P_ZFWD:
@@ -919,7 +926,7 @@ hipError_t launch_pass(int pass, int variant, int n, int prec, const MemberDev *
 }
 
 int pass_variants(int pass) {
-    if (pass == P_XPASS) return 3;
+    if (pass == P_XPASS) return 4;
     return (pass == P_ZINV || pass == P_YINV || pass == P_YFWD) ? 2 : 1;
 }
 

@@ -66,7 +66,9 @@ def kernel_name(pass_name: str, n: int, prec: str, variant) -> str:
     p = "float" if prec == "fp32" else "double"
     if pass_name == "zfwd_update":
         return f"ens::k_zfwd_update<{p}, {n}>"
-    if pass_name == "xpass" and variant == 2 and n >= 64:
+    if pass_name == "xpass" and variant == 3 and 128 <= n <= 512 and prec == "fp32":
+        return f"ens::k_xpass_dma<{p}, {n}, 16>"
+    if pass_name == "xpass" and variant in (2, 3) and n >= 64:
         return f"ens::k_xpass_dma<{p}, {n}, 8>"
     return f"ens::k_{pass_name}<{p}, {n}, {16 if variant == 1 else 8}>"
 

@@ -175,7 +175,7 @@ def test_every_kernel_variant_matches_oracle(orc, prec):
     n, nu, eps = 64, 0.01, 1.0
     ref, _ = orc.run(oracle_member(n, nu, eps, 0.0, 2.5, 0.0), orc.init_field(n, 12), 5)
     tol = 1e-12 if prec == "fp64" else 2e-5
-    for variant in (0, 1, 2):
+    for variant in (0, 1, 2, 3):
         E, m = make(n, nu, eps, 0.0, 2.5, 0.0, prec=prec, seed=12)
         for p in ("zinv", "yinv", "xpass", "yfwd"):
             E.set_variant(p, n, prec, variant if (variant < 2 or p == "xpass") else 0)
@@ -189,14 +189,16 @@ def test_every_kernel_variant_matches_oracle(orc, prec):
 @pytest.mark.parametrize("n,prec,count", [(128, "fp32", 6), (128, "fp64", 3), (256, "fp32", 25), (64, "fp32", 47),
                                           (256, "fp64", 1), (512, "fp32", 1)])
 def test_streamed_xpass_agrees_with_classic(n, prec, count):
-    """The persistent streamed x pass on long tile ranges per workgroup
-    (batches of the benchmark's shapes) against the classic 8-value kernel.
+    """The persistent streamed x pass (8 values per thread; FP32 also 16) on
+    long tile ranges per workgroup (batches of the benchmark's shapes) against
+    the classic 8-value kernel.
     Both perform the same operations; the compiler may fuse multiply-adds
     differently in the two kernels, so agreement is to rounding: a tile staged
     wrongly or read before its copy landed would differ at O(1)."""
     ens = ens_mod()
     finals = []
-    for variant in (0, 2):
+    variants = (0, 2, 3) if prec == "fp32" and 128 <= n <= 512 else (0, 2)
+    for variant in variants:
         E = ens.Ensemble()
         ms = [E.add_member(ens.MemberSpec(n=n, nu=0.03395, eps_ref=1.0, lam=0.3 * i - 1.0, kf_hi=2.5, dt=0.0, cfl=0.5,
                                           precision=prec, seed=700 + i)) for i in range(count)]
@@ -206,12 +208,13 @@ def test_streamed_xpass_agrees_with_classic(n, prec, count):
         finals.append(([ms[i].state().cpu().numpy() for i in pick], [m.diag()["dt"] for m in ms]))
         E.close()
     tol = 2e-6 if prec == "fp32" else 1e-13
-    for a, b in zip(finals[0][0], finals[1][0]):
-        err = rel(b, a)
-        worst = float(np.max(np.abs(b - a)) / np.max(np.abs(a)))
-        print(f"{n} {prec} x{count}: rel L2 {err:.2e}, max {worst:.2e}")
-        assert err <= tol and worst <= 5 * tol
-    assert np.allclose(finals[1][1], finals[0][1], rtol=tol, atol=0)   # per-member CFL steps
+    for k in range(1, len(variants)):
+        for a, b in zip(finals[0][0], finals[k][0]):
+            err = rel(b, a)
+            worst = float(np.max(np.abs(b - a)) / np.max(np.abs(a)))
+            print(f"{n} {prec} x{count} variant {variants[k]}: rel L2 {err:.2e}, max {worst:.2e}")
+            assert err <= tol and worst <= 5 * tol
+        assert np.allclose(finals[k][1], finals[0][1], rtol=tol, atol=0)   # per-member CFL steps
 
 
 def test_autotune_keeps_state_and_writes_cache(tmp_path):
@@ -220,7 +223,7 @@ def test_autotune_keeps_state_and_writes_cache(tmp_path):
     cache = tmp_path / "variants.txt"
     table = E.autotune(cache_path=str(cache))
     assert np.array_equal(m.state().cpu().numpy(), before)
-    assert set(table.values()) <= {0, 1, 2} and len(table) == 4
+    assert set(table.values()) <= {0, 1, 2, 3} and len(table) == 4
     text = cache.read_text()
     assert "zinv:32:fp64" in text
     E.close()
