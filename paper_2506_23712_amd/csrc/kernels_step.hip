@@ -772,7 +772,7 @@ __global__ void __launch_bounds__((Cfg<P, N, 8>::NTZ), (Cfg<P, N, 8>::ZMINB)) k_
                     Cx<P> q = stage == 0 ? czero<P>() : Q[c].ld(idx);
                     q = cscale(q, As) + cscale(g[c], Pdt);
                     u[c] = u[c] + cscale(q, Bs);
-                    Q[c].st(idx, q);
+                    if (stage < 2) Q[c].st(idx, q);       // the last stage's register is never read
                     U[c].st(idx, u[c]);
                 }
             } else {
@@ -782,7 +782,7 @@ __global__ void __launch_bounds__((Cfg<P, N, 8>::NTZ), (Cfg<P, N, 8>::ZMINB)) k_
                     Cx<P> q = stage == 0 ? czero<P>() : Q[c].ld(idx);
                     q = cscale(cscale(q, As) + cscale(g[c], Pdt), es);
                     u[c] = cscale(u[c], es) + cscale(q, Bs);
-                    Q[c].st(idx, q);
+                    if (stage < 2) Q[c].st(idx, q);       // the last stage's register is never read
                     U[c].st(idx, u[c]);
                 }
             }

@@ -56,8 +56,9 @@ def pass_bytes(n: int, prec: str) -> dict:
         "yinv": (5 * zl + 6 * yl) * cs,
         "xpass": (6 * yl + 3 * yl) * cs,
         "yfwd": (3 * yl + 3 * zl) * cs,
-        # stages 2 and 3 read the RK register too; average over the 3 stages
-        "zfwd_update": (3 * zl + 3 * S + 2 * 3 * S / 3 + 6 * S) * cs,
+        # stages 2 and 3 read the RK register, stages 1 and 2 write it;
+        # average over the 3 stages
+        "zfwd_update": (3 * zl + 3 * S + 2 * 3 * S / 3 + 3 * S + 2 * 3 * S / 3) * cs,
     }
 
 
@@ -139,7 +140,7 @@ def write_summary(n: int, counts, out: str) -> None:
         cs = 16 if prec == "fp64" else 8
         S, zl, yl = (2 * K + 1) ** 2 * (K + 1), n * (2 * K + 1) * (K + 1), n * n * (K + 1)
         rw = {"zinv": (3 * S, 5 * zl), "yinv": (5 * zl, 6 * yl), "xpass": (6 * yl, 3 * yl), "yfwd": (3 * yl, 3 * zl),
-              "zfwd_update": (3 * zl + 3 * S + 2 * S, 6 * S)}
+              "zfwd_update": (3 * zl + 3 * S + 2 * S, 3 * S + 2 * S)}
         for k in ("zinv", "yinv", "xpass", "yfwd", "zfwd_update"):
             for name, v in sorted(t["kernels"].items()):
                 short = name.replace("ens::", "")
@@ -157,7 +158,7 @@ def write_summary(n: int, counts, out: str) -> None:
                   "(their commands are recorded inside).  Counters: FETCH_SIZE and WRITE_SIZE (rocprofv3 `--pmc`, one "
                   "counter per run), KiB per dispatch, scaled by what the same counter reads for a plain 1 GiB device "
                   "copy.  Algorithmic bytes: each pass's inputs read once and outputs written once, truncated storage "
-                  "without line padding (the `zfwd_update` read averages the three RK stages).  The measured bytes "
+                  "without line padding (the `zfwd_update` read and write average the three RK stages).  The measured bytes "
                   "include the zero pad entries that the z/y passes write so that every store covers whole 128-byte "
                   "lines (FP32 rows of 86 complex values padded to 96, FP64 to 88).\n\n")
         f.write("| workload | kernel | algorithmic read / write GB | measured read / write GB | measured / algorithmic | kernel source hash |\n")
