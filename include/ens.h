@@ -115,8 +115,11 @@ ens_status ens_destroy(ens_ctx *ctx);
 const char *ens_last_error(void);
 
 /* 1: capture one RK step of a member set as a HIP graph and replay it
- * (default); 0: launch kernels directly. */
-ens_status ens_set_graphs(ens_ctx *ctx, int32_t enable);
+ * (default); 2: the same graph with one branch per group of members of equal
+ * grid size and precision, so that the groups' kernels may run side by side;
+ * 0: launch kernels directly.  Changing the mode synchronises the device and
+ * drops the graphs captured so far.  ENS_E_INVALID for other values. */
+ens_status ens_set_graphs(ens_ctx *ctx, int32_t mode);
 
 /* ---------------------------------------------------------------- members */
 

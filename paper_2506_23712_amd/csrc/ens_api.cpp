@@ -149,12 +149,14 @@ struct Plan {
 struct ens_ctx {
     int device = 0;
     bool poisoned = false;
-    bool graphs = true;
+    int graphs = 1;                   // 0 direct launches, 1 one graph per step, 2 ... with a branch per group
     bool has_hist = false;
     ens_hist_desc hist{};
     HistGeom hg{};
     double *ledge = nullptr;          // log-histogram edges 10^(lo + b (hi - lo) / bins), b = 0..bins
     hipStream_t cap = nullptr;   // private stream used for graph capture
+    std::vector<hipStream_t> side;    // capture streams of the per-group branches (graph mode 2)
+    std::vector<hipEvent_t> fork;     // fork / join events of those branches
     std::vector<std::unique_ptr<Member>> members;
     std::map<std::vector<int>, std::unique_ptr<Plan>> plans;
     std::vector<void *> dev_allocs;   // library-owned small device tables
@@ -252,6 +254,32 @@ struct Prof {
 int variant_of(const ens_ctx *ctx, int pass, int n, int prec) {
     auto it = ctx->variant.find(std::make_tuple(pass, n, prec));
     return it != ctx->variant.end() ? it->second : default_variant(pass, n, prec);
+}
+
+// One RK step of one group (three stages, then the end-of-step reduction) on
+// stream s; the groups of a plan are independent of each other.
+hipError_t enqueue_group(const ens_ctx *ctx, const Group &g, hipStream_t s) {
+    const int cnt = (int)g.ids.size();
+    hipError_t e;
+    for (int stage = 0; stage < 3; stage++)
+        for (int pass = P_BAND; pass <= P_ZFWD; pass++)
+            if ((e = launch_pass(pass, variant_of(ctx, pass, g.n, g.prec), g.n, g.prec, g.dev, cnt, stage, g.tw, s)))
+                return e;
+    return launch_pass(P_END, 0, g.n, g.prec, g.dev, cnt, 0, g.tw, s);
+}
+
+// Graph mode 2: inside the capture on ctx->cap, fork one branch per group onto
+// its own stream and join them again, so that the captured graph lets the
+// groups' kernels run side by side.  Streams and events exist before capture.
+hipError_t enqueue_step_branches(const ens_ctx *ctx, const Plan &pl) {
+    hipError_t e = hipEventRecord(ctx->fork[0], ctx->cap);
+    for (size_t i = 0; i < pl.groups.size() && e == hipSuccess; i++) {
+        if ((e = hipStreamWaitEvent(ctx->side[i], ctx->fork[0], 0))) break;
+        if ((e = enqueue_group(ctx, pl.groups[i], ctx->side[i]))) break;
+        if ((e = hipEventRecord(ctx->fork[i + 1], ctx->side[i]))) break;
+        e = hipStreamWaitEvent(ctx->cap, ctx->fork[i + 1], 0);
+    }
+    return e;
 }
 
 hipError_t enqueue_step(const ens_ctx *ctx, const Plan &pl, hipStream_t s, Prof *prof) {
@@ -361,13 +389,26 @@ ENS_API ens_status ens_destroy(ens_ctx *ctx) {
     for (void *p : ctx->dev_allocs) hipFree(p);
     if (ctx->mix_scratch) hipFree(ctx->mix_scratch);
     if (ctx->cap) hipStreamDestroy(ctx->cap);
+    for (hipStream_t st : ctx->side) hipStreamDestroy(st);
+    for (hipEvent_t ev : ctx->fork) hipEventDestroy(ev);
     delete ctx;
     return ENS_OK;
 }
 
-ENS_API ens_status ens_set_graphs(ens_ctx *ctx, int32_t enable) {
+ENS_API ens_status ens_set_graphs(ens_ctx *ctx, int32_t mode) {
     if (ens_status st = check_ctx(ctx)) return st;
-    ctx->graphs = enable != 0;
+    if (mode < 0 || mode > 2) return fail(ENS_E_INVALID, "graph mode must be 0, 1 or 2");
+    if (mode != ctx->graphs) {
+        HIPCK(ctx, hipSetDevice(ctx->device));
+        HIPCK(ctx, hipDeviceSynchronize());
+        for (auto &kv : ctx->plans) {                      // captured with the other mode
+            if (kv.second->exec) HIPCK(ctx, hipGraphExecDestroy(kv.second->exec));
+            if (kv.second->graph) HIPCK(ctx, hipGraphDestroy(kv.second->graph));
+            kv.second->exec = nullptr;
+            kv.second->graph = nullptr;
+        }
+    }
+    ctx->graphs = mode;
     return ENS_OK;
 }
 
@@ -468,8 +509,21 @@ ENS_API ens_status ens_step(ens_ctx *ctx, const int32_t *members, int32_t count,
     if (nsteps == 0) return ENS_OK;
     if (ctx->graphs) {
         if (!pl->exec) {
+            const bool branches = ctx->graphs == 2 && pl->groups.size() > 1;
+            if (branches) {
+                while (ctx->side.size() < pl->groups.size()) {
+                    hipStream_t st;
+                    HIPCK(ctx, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+                    ctx->side.push_back(st);
+                }
+                while (ctx->fork.size() < pl->groups.size() + 1) {
+                    hipEvent_t ev;
+                    HIPCK(ctx, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+                    ctx->fork.push_back(ev);
+                }
+            }
             HIPCK(ctx, hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
-            hipError_t e = enqueue_step(ctx, *pl, ctx->cap, nullptr);
+            hipError_t e = branches ? enqueue_step_branches(ctx, *pl) : enqueue_step(ctx, *pl, ctx->cap, nullptr);
             hipGraph_t g = nullptr;
             hipError_t e2 = hipStreamEndCapture(ctx->cap, &g);
             HIPCK(ctx, e);

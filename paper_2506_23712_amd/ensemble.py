@@ -167,10 +167,14 @@ class Ensemble:
         hd = hist.desc() if hist is not None else None
         with torch.cuda.device(self.device):
             check(L.ens_create(ctypes.byref(self.ctx), device, ctypes.byref(hd) if hd is not None else None))
-            check(L.ens_set_graphs(self.ctx, 1 if graphs else 0))
+            check(L.ens_set_graphs(self.ctx, int(graphs)))
         self.members: list[Member] = []
 
     # ---------------------------------------------------------------- members
+    def set_graph_mode(self, mode: int) -> None:
+        """0 direct launches, 1 one graph per step, 2 the same with a branch per group."""
+        check(lib().ens_set_graphs(self.ctx, mode))
+
     def workspace_bytes(self, spec: MemberSpec) -> int:
         b = ctypes.c_size_t()
         d = spec.desc()

@@ -121,6 +121,42 @@ def test_graph_and_direct_launch_agree_bitwise():
     assert np.array_equal(outs[0], outs[1])
 
 
+def test_graph_modes_agree_bitwise_on_mixed_groups():
+    """Direct launches, one graph per step and the graph with one branch per
+    group (three groups: 32^3 FP64, 64^3 FP64, 64^3 FP32), replayed several
+    times with eager work and synchronisations between the replays."""
+    ens = ens_mod()
+    specs = [ens.MemberSpec(n=32, nu=0.02, eps_ref=0.1, lam=-0.5, kf_hi=2.0, seed=31),
+             ens.MemberSpec(n=64, nu=0.02, eps_ref=0.1, lam=0.4, kf_hi=2.0, seed=32),
+             ens.MemberSpec(n=64, nu=0.02, eps_ref=0.1, lam=0.0, kf_hi=2.0, seed=33, precision="fp32"),
+             ens.MemberSpec(n=32, nu=0.02, eps_ref=0.1, lam=1.0, kf_hi=2.0, seed=34)]
+    outs = {}
+    for mode in (0, 1, 2):
+        E = ens.Ensemble(graphs=mode)
+        ms = [E.add_member(s) for s in specs]
+        states = []
+        for rep in range(3):
+            E.step(2)
+            states.append([m.state().cpu().numpy() for m in ms])   # eager copies, host sync between replays
+        outs[mode] = (states, [m.diag()["t"] for m in ms])
+        E.close()
+    for mode in (1, 2):
+        for a, b in zip(outs[0][0], outs[mode][0]):
+            for x, y in zip(a, b):
+                assert np.array_equal(x, y)
+        assert outs[0][1] == outs[mode][1]
+    # switching the mode of a live context drops its graphs and keeps stepping identically
+    E = ens.Ensemble(graphs=2)
+    ms = [E.add_member(s) for s in specs]
+    E.step(3)
+    E.set_graph_mode(1)
+    E.step(3)
+    assert np.array_equal(ms[1].state().cpu().numpy(), outs[0][0][2][1])
+    with pytest.raises(ens.EnsError):
+        E.set_graph_mode(3)
+    E.close()
+
+
 def test_repeat_runs_are_bitwise_identical():
     outs = []
     for _ in range(2):
