@@ -457,11 +457,15 @@ ENS_API ens_status ens_member_init(ens_ctx *ctx, const ens_member_desc *d, void 
     md.box = d->box;
     md.dk = 2.0 * M_PI / d->box;
     md.n = d->n; md.K = d->n / 3; md.prec = d->precision; md.visc_mode = d->visc_mode;
-    md.px = m->g.px; md.pad_ = 0;
+    md.px = m->g.px; md.zp = (int)m->g.zp;
     void *p = nullptr;
     HIPCK(ctx, hipMalloc(&p, sizeof(MemberDev)));
     m->dev = (MemberDev *)p;
     HIPCK(ctx, hipMemcpy(m->dev, &md, sizeof(MemberDev), hipMemcpyHostToDevice));
+    // the pad entries of the state planes are never read; zero them anyway
+    const long long state_doubles = 3 * m->g.S * (d->precision == ENS_FP32 ? 1 : 2);
+    HIPCK(ctx, launch_fill_f64((double *)md.uh, state_doubles, 0.0, s));
+    HIPCK(ctx, launch_fill_f64((double *)md.q, state_doubles, 0.0, s));
     HIPCK(ctx, launch_init_field(d->n, d->precision, m->dev, d->seed, d->k_peak, d->e0, s));
     if (ctx->has_hist) {
         HIPCK(ctx, launch_fill_u64(md.counts, ctx->hg.n_counts, 0ull, s));

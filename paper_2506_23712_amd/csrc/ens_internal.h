@@ -40,11 +40,21 @@ __host__ __device__ constexpr int kx_pitch(int K, int cbytes) {
     return 8 * (px - (K + 1)) <= K + 1 ? px : K + 1;
 }
 
+// Plane pitch of the state arrays (u_hat and the RK register, [3][2K+1 (kz)]
+// [ZP]): the (2K+1)(K+1) modes of one kz plane rounded up to whole 128-byte
+// lines, so that every plane and every field starts on a line and the z-line
+// tiles of the z passes (16 FP32 / 8 FP64 consecutive lines of a plane) load
+// and store whole lines.  The pad entries of a plane are never read.
+__host__ __device__ constexpr int state_pitch(int K, int cbytes) {
+    const int per = 128 / cbytes, p = (2 * K + 1) * (K + 1);
+    return (p + per - 1) / per * per;
+}
+
 // Everything a kernel needs to know about one member (lives in a device
 // table owned by the library; pointers refer to the caller's workspace).
 // PX = kx_pitch(K, complex size).  Layouts (x-mode index fastest):
 struct MemberDev {
-    void *uh;          // velocity  [3][2K+1 (kz)][2K+1 (ky)][K+1 (kx)] complex
+    void *uh;          // velocity  [3][2K+1 (kz)][ZP: 2K+1 (ky) x K+1 (kx), then pad] complex
     void *q;           // RK register, same layout
     void *bufA;        // [F][n (z)][2K+1][PX] (z-inverse out) / [3][n][n][K+1] (x-pass out, linear stores)
     void *bufB;        // [F][n (z)][n (y)][PX] (y-inverse out) / [3][n][2K+1][PX] (y-forward out)
@@ -55,14 +65,15 @@ struct MemberDev {
     double nu, eps_m, kf_lo2, kf_hi2, dt_fixed, cfl, box, dk;
     int n, K, prec, visc_mode;
     int px;            // x-mode pitch PX
-    int pad_;
+    int zp;            // state plane pitch ZP = state_pitch(K, complex size)
 };
 
 // Host-visible geometry of one member.
 struct Geom {
     int n, K, px;
     long long nzl;     // z-lines of the pencil buffers = (2K+1) PX (pad lines included)
-    long long S;       // retained modes per component = (2K+1)^2 (K+1)
+    long long zp;      // state plane pitch ZP
+    long long S;       // state elements per component = (2K+1) ZP (pad entries included)
     long long nyl;     // y-lines of the pencil buffers = n PX
 };
 
@@ -71,7 +82,8 @@ inline Geom make_geom(int n, int prec) {
     g.n = n; g.K = n / 3;
     g.px = kx_pitch(g.K, prec == ENS_FP32 ? 8 : 16);
     g.nzl = (long long)(2 * g.K + 1) * g.px;
-    g.S = (long long)(2 * g.K + 1) * (2 * g.K + 1) * (g.K + 1);
+    g.zp = state_pitch(g.K, prec == ENS_FP32 ? 8 : 16);
+    g.S = (long long)(2 * g.K + 1) * g.zp;
     g.nyl = (long long)n * g.px;
     return g;
 }

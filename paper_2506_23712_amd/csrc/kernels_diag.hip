@@ -25,8 +25,8 @@ __device__ __forceinline__ int shell_of(long long m2) {
 template <typename P, int RG, class F>
 __device__ __forceinline__ void plane_rows(const MemberDev &md, int iz, int v0, F &&f) {
     const int K = md.K, NY = 2 * K + 1, lane = threadIdx.x & 63;
-    const long long nzl = (long long)NY * (K + 1), S = (long long)NY * nzl;
-    const Fld<P> U[3] = {Fld<P>(md.uh, iz * nzl), Fld<P>(md.uh, S + iz * nzl), Fld<P>(md.uh, 2 * S + iz * nzl)};
+    const long long zp = md.zp, S = (long long)NY * zp;     // state plane pitch, component stride
+    const Fld<P> U[3] = {Fld<P>(md.uh, iz * zp), Fld<P>(md.uh, S + iz * zp), Fld<P>(md.uh, 2 * S + iz * zp)};
     constexpr int VS = 4 * kDiagParts;
     for (int iy0 = v0; iy0 < NY; iy0 += VS * RG) {
         for (int c0 = 0; c0 <= K; c0 += 64) {
@@ -189,29 +189,34 @@ hipError_t launch_scales(int prec, const MemberDev *mem, int K, double *out, hip
     return hipGetLastError();
 }
 
-// dst mode (iz, iy, m_x) of the finer grid: the src value where |m_i| <= K_src,
-// else zero; the RK register is cleared.  One thread per dst entry.
+// dst storage entry (component, iz, plane offset) of the finer grid: the src
+// value where the mode is retained by src, else zero (pad entries too); the RK
+// register is cleared.  One thread per dst entry.
 template <typename PS, typename PD>
 __global__ void __launch_bounds__(256) k_refine(const MemberDev *__restrict__ sp, const MemberDev *__restrict__ dp) {
     const MemberDev &ms = *sp, &md = *dp;
     const int Ks = ms.K, Kd = md.K;
-    const long long nzd = (long long)(2 * Kd + 1) * (Kd + 1), Sd = (long long)(2 * Kd + 1) * nzd;
-    const long long nzs = (long long)(2 * Ks + 1) * (Ks + 1), Ss = (long long)(2 * Ks + 1) * nzs;
+    const long long nzd = (long long)(2 * Kd + 1) * (Kd + 1), zpd = md.zp, Sd = (long long)(2 * Kd + 1) * zpd;
+    const long long zps = ms.zp, Ss = (long long)(2 * Ks + 1) * zps;
     const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
     if (i >= 3 * Sd) return;
     const int comp = (int)(i / Sd);
     const long long r = i - comp * Sd;
-    const int iz = (int)(r / nzd), rem = (int)(r - iz * nzd);
-    const int iy = rem / (Kd + 1), mx = rem % (Kd + 1);
-    const int my = iy <= Kd ? iy : iy - (2 * Kd + 1), mz = iz <= Kd ? iz : iz - (2 * Kd + 1);
+    const int iz = (int)(r / zpd);
+    const long long rem = r - iz * zpd;
     LdsT<PD> v;
     v.x = PD(0);
     v.y = PD(0);
-    if (mx <= Ks && my >= -Ks && my <= Ks && mz >= -Ks && mz <= Ks) {
-        const int sy = my >= 0 ? my : my + 2 * Ks + 1, sz = mz >= 0 ? mz : mz + 2 * Ks + 1;
-        const LdsT<PS> w = reinterpret_cast<const LdsT<PS> *>(ms.uh)[comp * Ss + (long long)sz * nzs + (long long)sy * (Ks + 1) + mx];
-        v.x = (PD)(double)w.x;
-        v.y = (PD)(double)w.y;
+    if (rem < nzd) {
+        const int iy = (int)(rem / (Kd + 1)), mx = (int)(rem % (Kd + 1));
+        const int my = iy <= Kd ? iy : iy - (2 * Kd + 1), mz = iz <= Kd ? iz : iz - (2 * Kd + 1);
+        if (mx <= Ks && my >= -Ks && my <= Ks && mz >= -Ks && mz <= Ks) {
+            const int sy = my >= 0 ? my : my + 2 * Ks + 1, sz = mz >= 0 ? mz : mz + 2 * Ks + 1;
+            const LdsT<PS> w = reinterpret_cast<const LdsT<PS> *>(ms.uh)[comp * Ss + (long long)sz * zps +
+                                                                         (long long)sy * (Ks + 1) + mx];
+            v.x = (PD)(double)w.x;
+            v.y = (PD)(double)w.y;
+        }
     }
     reinterpret_cast<LdsT<PD> *>(md.uh)[i] = v;
     LdsT<PD> z;

@@ -138,11 +138,13 @@ __global__ void __launch_bounds__(256) k_init_store(const MemberDev *__restrict_
     const double f = md.st->e_init;
     L2<P> *u = reinterpret_cast<L2<P> *>(md.uh);
     L2<P> *q = reinterpret_cast<L2<P> *>(md.q);
+    const long long nzl = (long long)(2 * K + 1) * (K + 1), zp = md.zp, Sp = (2 * K + 1) * zp;
+    const long long at = (s / nzl) * zp + s % nzl;          // storage index of mode s
     for (int comp = 0; comp < 3; comp++) {
         L2<P> v; v.x = (P)(c[2 * comp] * f); v.y = (P)(c[2 * comp + 1] * f);
-        u[comp * S + s] = v;
+        u[comp * Sp + at] = v;
         L2<P> z; z.x = P(0); z.y = P(0);
-        q[comp * S + s] = z;
+        q[comp * Sp + at] = z;
     }
 }
 
@@ -162,23 +164,27 @@ hipError_t launch_init_field(int n, int prec, const MemberDev *mem, uint64_t see
 }
 
 // ------------------------------------------------------------ state exchange
-// canonical [3][N][N][N/2+1] FP64 complex  <->  storage [3][2K+1][2K+1][K+1]
+// canonical [3][N][N][N/2+1] FP64 complex  <->  storage [3][2K+1][ZP], a plane
+// holding [2K+1 (ky)][K+1 (kx)] then pad entries (written as zeros here)
 template <typename P>
 __global__ void __launch_bounds__(256) k_set_state(const MemberDev *__restrict__ mp, const double *__restrict__ src) {
     const MemberDev &md = *mp;
     const int n = md.n, K = md.K, nh = n / 2 + 1;
-    const long long nzl = (long long)(2 * K + 1) * (K + 1);
-    const long long S = (2 * K + 1) * nzl;
+    const long long nzl = (long long)(2 * K + 1) * (K + 1), zp = md.zp;
+    const long long S = (2 * K + 1) * zp;
     const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
     if (i >= 3 * S) return;
     const int comp = (int)(i / S);
     const long long s = i % S;
-    const int iz = (int)(s / nzl), rem = (int)(s % nzl);
-    const int iy = rem / (K + 1), kx = rem % (K + 1);
-    const int zi = iz <= K ? iz : iz - (2 * K + 1) + n;
-    const int yi = iy <= K ? iy : iy - (2 * K + 1) + n;
-    const long long ci = (((long long)comp * n + zi) * n + yi) * nh + kx;
-    L2<P> v; v.x = (P)src[2 * ci]; v.y = (P)src[2 * ci + 1];
+    const int iz = (int)(s / zp), rem = (int)(s % zp);
+    L2<P> v; v.x = P(0); v.y = P(0);
+    if (rem < nzl) {
+        const int iy = rem / (K + 1), kx = rem % (K + 1);
+        const int zi = iz <= K ? iz : iz - (2 * K + 1) + n;
+        const int yi = iy <= K ? iy : iy - (2 * K + 1) + n;
+        const long long ci = (((long long)comp * n + zi) * n + yi) * nh + kx;
+        v.x = (P)src[2 * ci]; v.y = (P)src[2 * ci + 1];
+    }
     reinterpret_cast<L2<P> *>(md.uh)[i] = v;
     L2<P> z; z.x = P(0); z.y = P(0);
     reinterpret_cast<L2<P> *>(md.q)[i] = z;
@@ -188,8 +194,8 @@ template <typename P>
 __global__ void __launch_bounds__(256) k_get_state(const MemberDev *__restrict__ mp, double *__restrict__ dst) {
     const MemberDev &md = *mp;
     const int n = md.n, K = md.K, nh = n / 2 + 1;
-    const long long nzl = (long long)(2 * K + 1) * (K + 1);
-    const long long S = (2 * K + 1) * nzl;
+    const long long zp = md.zp;
+    const long long S = (2 * K + 1) * zp;
     const long long total = 3LL * n * n * nh;
     const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
     if (i >= total) return;
@@ -201,7 +207,7 @@ __global__ void __launch_bounds__(256) k_get_state(const MemberDev *__restrict__
     double re = 0.0, im = 0.0;
     if (kx <= K && my >= -K && my <= K && mz >= -K && mz <= K) {
         const int iy = my >= 0 ? my : my + 2 * K + 1, iz = mz >= 0 ? mz : mz + 2 * K + 1;
-        L2<P> v = reinterpret_cast<const L2<P> *>(md.uh)[comp * S + iz * nzl + (long long)iy * (K + 1) + kx];
+        L2<P> v = reinterpret_cast<const L2<P> *>(md.uh)[comp * S + iz * zp + (long long)iy * (K + 1) + kx];
         re = (double)v.x; im = (double)v.y;
     }
     dst[2 * i] = re;
@@ -209,8 +215,7 @@ __global__ void __launch_bounds__(256) k_get_state(const MemberDev *__restrict__
 }
 
 hipError_t launch_set_state(int n, int prec, const MemberDev *mem, const double *src, hipStream_t s) {
-    const int K = n / 3;
-    const long long S = (long long)(2 * K + 1) * (2 * K + 1) * (K + 1);
+    const long long S = make_geom(n, prec).S;
     const unsigned nb = (unsigned)((3 * S + 255) / 256);
     if (prec == ENS_FP32) k_set_state<float><<<nb, 256, 0, s>>>(mem, src);
     else k_set_state<double><<<nb, 256, 0, s>>>(mem, src);

@@ -25,7 +25,8 @@ template <typename P, int N, int EV> struct SCfg {
     static constexpr int PX = kx_pitch(K, (int)sizeof(Cx<P>));   // x-mode pitch (whole 128-byte lines)
     static constexpr int NZL = (2 * K + 1) * PX;                  // z-lines of a pencil buffer
     static constexpr int NZLS = (2 * K + 1) * (K + 1);            // z-lines of the state
-    static constexpr int S = (2 * K + 1) * NZLS;
+    static constexpr int ZP = state_pitch(K, (int)sizeof(Cx<P>));   // state plane pitch
+    static constexpr int S = (2 * K + 1) * ZP;                      // state elements per component
     static constexpr int NYL = N * PX;
     static constexpr int E = EV > N ? N : EV, M = N / E;
     static constexpr int TL = 128 / (int)sizeof(Cx<P>);       // lines for 128-byte runs
@@ -49,7 +50,7 @@ __device__ __forceinline__ void gload_trunc(Cx<P> *v, const Fld<P> &f, uint32_t 
 }
 
 // ------------------------------------------------------------------ gzinv
-// in u_hat [3][2K+1][2K+1][K+1]; out bufA [6][N][NZL]: U_c = Z^-1[u_c] (fields
+// in u_hat [3][2K+1][ZP]; out bufA [6][N][NZL]: U_c = Z^-1[u_c] (fields
 // 0..2), W_c = Z^-1[i k_z u_c] (3..5); pad lines (kx > K) carry zeros
 template <typename P, int N>
 __global__ void __launch_bounds__((SCfg<P, N, grad_e<P>()>::NT)) k_gzinv(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ twg) {
@@ -76,10 +77,10 @@ __global__ void __launch_bounds__((SCfg<P, N, grad_e<P>()>::NT)) k_gzinv(const M
         }
     };
     Cx<P> a[E], b[E], p[E];
-    gload_trunc<P, N, E>(a, Fld<P>(md.uh, 0), Ls, C::NZLS, t, valid);
+    gload_trunc<P, N, E>(a, Fld<P>(md.uh, 0), Ls, C::ZP, t, valid);
 #pragma unroll
     for (int c = 0; c < 3; c++) {
-        if (c < 2) gload_trunc<P, N, E>(p, Fld<P>(md.uh, (long long)(c + 1) * C::S), Ls, C::NZLS, t, valid);
+        if (c < 2) gload_trunc<P, N, E>(p, Fld<P>(md.uh, (long long)(c + 1) * C::S), Ls, C::ZP, t, valid);
 #pragma unroll
         for (int m = 0; m < E; m++) b[m] = mul_i(cscale(a[m], dk * (P)mode_of(t + M * m, N)));
         line_fft<P, N, E, T, +1>(b, lds, l, t, tw);

@@ -47,7 +47,8 @@ template <typename P, int N, int E_> struct Cfg {
     static constexpr int PX = kx_pitch(K, (int)sizeof(Cx<P>));  // x-mode pitch of the pencil buffers
     static constexpr int NZL = (2 * K + 1) * PX;                // z-lines of a pencil buffer (pad lines included)
     static constexpr int NZLS = (2 * K + 1) * (K + 1);          // z-lines of the state
-    static constexpr int S = (2 * K + 1) * NZLS;                // retained modes per component
+    static constexpr int ZP = state_pitch(K, (int)sizeof(Cx<P>));  // state plane pitch
+    static constexpr int S = (2 * K + 1) * ZP;                  // state elements per component
     static constexpr int NYL = N * PX;                          // y-lines
     static constexpr int E = E_ > N ? N : E_;
     static constexpr int M = N / E;
@@ -81,8 +82,8 @@ __global__ void __launch_bounds__(256) k_band_energy(const MemberDev *__restrict
     __shared__ double red[256];
     const MemberDev &md = mems[blockIdx.x];
     const int K = md.K;
-    const long long nzl = (long long)(2 * K + 1) * (K + 1);
-    const long long S = (long long)(2 * K + 1) * nzl;
+    const long long zp = md.zp;
+    const long long S = (long long)(2 * K + 1) * zp;
     int B = (int)floor(sqrt(md.kf_hi2));
     if (B > K) B = K;
     const int W = 2 * B + 1;
@@ -95,7 +96,7 @@ __global__ void __launch_bounds__(256) k_band_energy(const MemberDev *__restrict
         const int m2 = mx * mx + my * my + mz * mz;
         if (m2 == 0 || (double)m2 < md.kf_lo2 || (double)m2 > md.kf_hi2) continue;
         const int iy = my >= 0 ? my : my + 2 * K + 1, iz = mz >= 0 ? mz : mz + 2 * K + 1;
-        const long long idx = (long long)iz * nzl + (long long)iy * (K + 1) + mx;
+        const long long idx = (long long)iz * zp + (long long)iy * (K + 1) + mx;
         const double w = mx > 0 ? 1.0 : 0.5;
 #pragma unroll
         for (int comp = 0; comp < 3; comp++) {
@@ -132,7 +133,7 @@ __device__ __forceinline__ void load_trunc(Cx<P> *v, const Fld<P> &f, uint32_t b
 
 // ================================================================== zinv
 // z-lines L = iy PX + kx of the output (m_y, m_x) pairs; pad lines (kx > K)
-// carry zeros.  in u_hat [3][2K+1][2K+1][K+1]; out (bufA) [5][N (z)][NZL]:
+// carry zeros.  in u_hat [3][2K+1][ZP]; out (bufA) [5][N (z)][NZL]:
 // U_x, U_y, U_z, W_x = Z^-1[i k_z u_x], W_y = Z^-1[i k_z u_y]
 template <typename P, int N, int EV>
 __global__ void __launch_bounds__((Cfg<P, N, EV>::NT), (Cfg<P, N, EV>::PMINW)) k_zinv(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ twg) {
@@ -160,8 +161,8 @@ __global__ void __launch_bounds__((Cfg<P, N, EV>::NT), (Cfg<P, N, EV>::PMINW)) k
         }
     };
     Cx<P> a[E], b[E], p[E];
-    load_trunc<P, N, E>(a, Fld<P>(md.uh, 0), Ls, C::NZLS, t, valid);
-    load_trunc<P, N, E>(p, Fld<P>(md.uh, C::S), Ls, C::NZLS, t, valid);
+    load_trunc<P, N, E>(a, Fld<P>(md.uh, 0), Ls, C::ZP, t, valid);
+    load_trunc<P, N, E>(p, Fld<P>(md.uh, C::S), Ls, C::ZP, t, valid);
 #pragma unroll
     for (int m = 0; m < E; m++) b[m] = mul_i(cscale(a[m], kz(m)));
     line_fft<P, N, E, T, +1>(b, lds, l, t, tw);
@@ -170,7 +171,7 @@ __global__ void __launch_bounds__((Cfg<P, N, EV>::NT), (Cfg<P, N, EV>::PMINW)) k
     store(a, 0);
 #pragma unroll
     for (int m = 0; m < E; m++) a[m] = p[m];
-    load_trunc<P, N, E>(p, Fld<P>(md.uh, 2 * C::S), Ls, C::NZLS, t, valid);
+    load_trunc<P, N, E>(p, Fld<P>(md.uh, 2 * C::S), Ls, C::ZP, t, valid);
 #pragma unroll
     for (int m = 0; m < E; m++) b[m] = mul_i(cscale(a[m], kz(m)));
     line_fft<P, N, E, T, +1>(b, lds, l, t, tw);
@@ -743,7 +744,7 @@ __global__ void __launch_bounds__((Cfg<P, N, 8>::NTZ), (Cfg<P, N, 8>::ZMINB)) k_
             const int mz = mode_of(Plan<N, E>::out_pos(t, s), N);
             if (mz < -K || mz > K) continue;
             const int iz = mz >= 0 ? mz : mz + 2 * K + 1;
-            const uint32_t idx = (uint32_t)iz * C::NZLS + L;
+            const uint32_t idx = (uint32_t)iz * C::ZP + L;
             const int m2 = kx * kx + my * my + mz * mz;
             const P kxv = dk * (P)kx, kyv = dk * (P)my, kzv = dk * (P)mz;
             const P k2 = kxv * kxv + kyv * kyv + kzv * kzv;
