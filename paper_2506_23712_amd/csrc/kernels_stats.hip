@@ -210,10 +210,12 @@ __global__ void __launch_bounds__(256, 2) k_gxstats(const MemberDev *__restrict_
     // Hot bins are replicated: the central CW bins of each 1-D histogram and
     // the central CQ x CQ bins of the QR histogram get NC copies, one per
     // lane group (lane mod NC), so that lanes of a wavefront landing in the
-    // same bin collide at most NC ways.  Copies are merged before the flush.
+    // same bin collide at most NC ways.  The copies of a bin are adjacent
+    // words, i.e. in NC different LDS banks, so that the groups hitting one
+    // hot bin do not queue on one bank.  Copies are merged before the flush.
     constexpr int NC = 8, CW = 64, CQ = 16;
-    __shared__ unsigned int cen1[4][NC][CW];                // log eps, log Omega, A_L, A_T
-    __shared__ unsigned int cenq[NC][CQ * CQ];
+    __shared__ unsigned int cen1[4][CW][NC];                // log eps, log Omega, A_L, A_T
+    __shared__ unsigned int cenq[CQ * CQ][NC];
     const MemberDev &md = mems[blockIdx.y];
     const int l = threadIdx.x % T, t = threadIdx.x / T;
     const int grp = threadIdx.x & (NC - 1);
@@ -243,7 +245,7 @@ __global__ void __launch_bounds__(256, 2) k_gxstats(const MemberDev *__restrict_
     unsigned int *single[4] = {h_le, h_lw, h_al, h_at};
     auto add1 = [&](int hist, int slot) {
         const int rel = slot - c0[hist];
-        if (c0[hist] >= 0 && rel >= 0 && rel < CW) atomicAdd(&cen1[hist][grp][rel], 1u);
+        if (c0[hist] >= 0 && rel >= 0 && rel < CW) atomicAdd(&cen1[hist][rel][grp], 1u);
         else atomicAdd(&single[hist][slot], 1u);
     };
     double mom[26];
@@ -316,7 +318,7 @@ __global__ void __launch_bounds__(256, 2) k_gxstats(const MemberDev *__restrict_
                         widx = (bq - h.win0) * h.win + (br - h.win0);
                     else gidx = bq * h.qb + br;
                 }
-                if (cidx >= 0) atomicAdd(&cenq[grp][cidx], 1u);
+                if (cidx >= 0) atomicAdd(&cenq[cidx][grp], 1u);
                 else if (widx >= 0) atomicAdd(&h_qr[widx], 1u);
                 else atomicAdd(&G[gidx], 1ull);
             }
@@ -348,13 +350,13 @@ __global__ void __launch_bounds__(256, 2) k_gxstats(const MemberDev *__restrict_
         if (c0[hh] < 0) continue;
         unsigned int sum = 0;
 #pragma unroll
-        for (int c = 0; c < NC; c++) sum += cen1[hh][c][rel];
+        for (int c = 0; c < NC; c++) sum += cen1[hh][rel][c];
         single[hh][c0[hh] + rel] += sum;
     }
     for (int i = threadIdx.x; i < CQ * CQ; i += 256) {
         unsigned int sum = 0;
 #pragma unroll
-        for (int c = 0; c < NC; c++) sum += cenq[c][i];
+        for (int c = 0; c < NC; c++) sum += cenq[i][c];
         if (sum) atomicAdd(&G[(long long)(q0 + i / CQ) * h.qb + (r0 + i % CQ)], (unsigned long long)sum);
     }
     // deterministic reduction of the moments: wave butterfly, then waves in order
