@@ -188,6 +188,12 @@ __device__ __forceinline__ int log_bin(double x, const double *edge, int nb, flo
 }
 __device__ __forceinline__ int slot_1d(int b, int nb) { return b >= 0 ? b : (b == -1 ? nb : (b == -2 ? nb + 1 : nb + 2)); }
 
+// Replicated hot bins of the statistics pass: copies per bin and central bins
+// of each 1-D histogram; copies per bin and central bins per axis of the QR
+// histogram.
+constexpr int kHotCopies1 = 8, kHotBins1 = 64, kHotCopiesQ = 8, kHotBinsQ = 16;
+constexpr size_t kHotBytes = (4 * (size_t)kHotBins1 * kHotCopies1 + (size_t)kHotBinsQ * kHotBinsQ * kHotCopiesQ) * 4;
+
 // Persistent x pass of the gradient fields: each workgroup takes row tiles
 // blockIdx.x, blockIdx.x + gridDim.x, ...; per-point values are formed in FP64;
 // 1-D histograms and a central window of the QR histogram are accumulated in
@@ -207,25 +213,26 @@ __global__ void __launch_bounds__(256, 2) k_gxstats(const MemberDev *__restrict_
     __shared__ Cx<P> tw[twiddle_span(N, E)];               // twiddles in LDS: no global load inside the transforms
     for (int i = (int)threadIdx.x; i < twiddle_span(N, E); i += (int)blockDim.x) tw[i] = twg[i];
     __shared__ double red[4][32];
-    // Hot bins are replicated: the central CW bins of each 1-D histogram and
-    // the central CQ x CQ bins of the QR histogram get NC copies, one per
-    // lane group (lane mod NC), so that lanes of a wavefront landing in the
-    // same bin collide at most NC ways.  The copies of a bin are adjacent
-    // words, i.e. in NC different LDS banks, so that the groups hitting one
-    // hot bin do not queue on one bank.  Copies are merged before the flush.
-    constexpr int NC = 8, CW = 64, CQ = 16;
+    // Hot bins are replicated: the central CW bins of each 1-D histogram get
+    // NC copies and the central CQ x CQ bins of the QR histogram NQ copies,
+    // one per lane group (lane mod NC or NQ), so that lanes of a wavefront
+    // landing in the same bin collide on one word at most 64/NC (64/NQ) ways.
+    // The copies of a bin are adjacent words, i.e. in different LDS banks, so
+    // that the groups hitting one hot bin do not queue on one bank.  Copies
+    // are merged before the flush.
+    constexpr int NC = kHotCopies1, CW = kHotBins1, NQ = kHotCopiesQ, CQ = kHotBinsQ;
     __shared__ unsigned int cen1[4][CW][NC];                // log eps, log Omega, A_L, A_T
-    __shared__ unsigned int cenq[CQ * CQ][NC];
+    __shared__ unsigned int cenq[CQ * CQ][NQ];
     const MemberDev &md = mems[blockIdx.y];
     const int l = threadIdx.x % T, t = threadIdx.x / T;
-    const int grp = threadIdx.x & (NC - 1);
+    const int grp = threadIdx.x & (NC - 1), grq = threadIdx.x & (NQ - 1);
     const P dk = (P)md.dk;
     const int n1d = 2 * (h.lb + 3) + 2 * (h.ab + 3);
     const int nwin = h.win * h.win;
     for (int i = threadIdx.x; i < n1d + nwin; i += 256) hs[i] = 0u;
     for (int i = threadIdx.x; i <= h.lb; i += 256) ledge[i] = h.ledge[i];
     for (int i = threadIdx.x; i < 4 * NC * CW; i += 256) (&cen1[0][0][0])[i] = 0u;
-    for (int i = threadIdx.x; i < NC * CQ * CQ; i += 256) (&cenq[0][0])[i] = 0u;
+    for (int i = threadIdx.x; i < NQ * CQ * CQ; i += 256) (&cenq[0][0])[i] = 0u;
     unsigned int *h_le = hs, *h_lw = hs + (h.lb + 3), *h_al = hs + 2 * (h.lb + 3), *h_at = h_al + (h.ab + 3);
     unsigned int *h_qr = hs + n1d;
     unsigned long long *G = md.counts;
@@ -318,7 +325,7 @@ __global__ void __launch_bounds__(256, 2) k_gxstats(const MemberDev *__restrict_
                         widx = (bq - h.win0) * h.win + (br - h.win0);
                     else gidx = bq * h.qb + br;
                 }
-                if (cidx >= 0) atomicAdd(&cenq[cidx][grp], 1u);
+                if (cidx >= 0) atomicAdd(&cenq[cidx][grq], 1u);
                 else if (widx >= 0) atomicAdd(&h_qr[widx], 1u);
                 else atomicAdd(&G[gidx], 1ull);
             }
@@ -356,7 +363,7 @@ __global__ void __launch_bounds__(256, 2) k_gxstats(const MemberDev *__restrict_
     for (int i = threadIdx.x; i < CQ * CQ; i += 256) {
         unsigned int sum = 0;
 #pragma unroll
-        for (int c = 0; c < NC; c++) sum += cenq[i][c];
+        for (int c = 0; c < NQ; c++) sum += cenq[i][c];
         if (sum) atomicAdd(&G[(long long)(q0 + i / CQ) * h.qb + (r0 + i % CQ)], (unsigned long long)sum);
     }
     // deterministic reduction of the moments: wave butterfly, then waves in order
@@ -458,7 +465,7 @@ static hipError_t stats_pass(int pass, const MemberDev *mem, int count, const en
         h.loff = (float)(h.l_lo * h.l_scale);
         // LDS: transform tile + reduction (static) + log edges, 1-D histograms, QR window (dynamic) <= 64 KiB
         constexpr int T = 256 / (N / 4);
-        const size_t stat = (size_t)N * T * sizeof(LdsT<P>) + 4 * 32 * sizeof(double) + (4 * 8 * 64 + 8 * 16 * 16) * 4 +
+        const size_t stat = (size_t)N * T * sizeof(LdsT<P>) + 4 * 32 * sizeof(double) + kHotBytes +
                             (size_t)twiddle_span(N, 4) * sizeof(Cx<P>);
         const size_t n1d = 2 * (size_t)(h.lb + 3) + 2 * (size_t)(h.ab + 3);
         const size_t budget = 65536 - stat - 512;
@@ -515,7 +522,7 @@ hipError_t launch_stats_reduce(int n, int prec, const MemberDev *mem, int count,
 long long xstats_blocks(int n) { return 512; }
 bool stats_hist_fits(const ens_hist_desc &h) {
     const size_t n1d = 2 * (size_t)(h.log_bins + 3) + 2 * (size_t)(h.a_bins + 3);
-    return n1d * 4 + (size_t)(h.log_bins + 1) * 8 <= 65536 - 16384 - 4 * 32 * 8 - 16384 - 512 - 4096;
+    return n1d * 4 + (size_t)(h.log_bins + 1) * 8 <= 65536 - kHotBytes - 4 * 32 * 8 - 16384 - 512 - 4096;
 }
 
 // =================================================================== mixture
