@@ -79,3 +79,37 @@ def test_64_members_128cubed_fp64_batch(orc):
     area = (60 / 64) * (120 / 64)
     total = float(res0["qr"].sum()) * area
     assert 0.0 < total <= 1.0 + 1e-12
+
+
+def test_benchmark_workload_sampled_against_the_oracle(orc):
+    """The 96-member mixed FP32 workload exactly as the benchmark launches it
+    (autotuned variants, one captured graph per step): after two steps, one
+    member of each grid size (64^3, 128^3, 256^3) against two FP64 oracle steps
+    from the same field.  FP32 transforms against FP64: agreement to the FP32
+    rounding of two steps."""
+    import os
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    import paper_2506_23712_amd as ens
+    specs = bench.ens96_specs(ens)
+    E = ens.Ensemble(hist=bench.hist_for(ens, 0.03395), graphs=True)
+    ms = [E.add_member(s) for s in specs]
+    E.autotune()
+    picks = [next(i for i, s in enumerate(specs) if s.n == n) for n in (64, 128, 256)]
+    u0 = {i: ms[i].state().cpu().numpy() for i in picks}
+    E.step(2)
+    got = {i: ms[i].state().cpu().numpy() for i in picks}
+    dts = {i: ms[i].diag()["t"] for i in picks}
+    E.accumulate_stats()                                    # the snapshot of the timed loop runs too
+    assert not any(m.diag()["diverged"] for m in ms)
+    E.close()
+    for i in picks:
+        s = specs[i]
+        om = orc.Member(n=s.n, nu=s.nu, eps=s.eps_ref * math.exp(s.lam), kf_lo=s.kf_lo, kf_hi=s.kf_hi, dt=s.dt,
+                        cfl=s.cfl)
+        ref, rd = orc.run(om, u0[i], 2)
+        err = float(np.linalg.norm(got[i] - ref) / np.linalg.norm(ref))
+        print(f"member {i} ({s.n}^3, lambda {s.lam:+.2f}): rel L2 {err:.2e}, t {dts[i]:.6f} vs {rd[-1, 0]:.6f}")
+        assert err <= 1e-6                                    # measured 7e-8 to 9e-8
+        assert abs(dts[i] - rd[-1, 0]) <= 1e-6 * rd[-1, 0]
