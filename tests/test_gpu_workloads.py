@@ -3,7 +3,9 @@
   64 x 64 QR histogram -- whole-run parity with the oracle;
 * 64 members at 128^3 FP64, lambda ~ N(0, 2), eps = e^lambda, nu = 0.02964,
   band |k| <= 2.5, CFL 0.5, one batched graph -- one member sampled against
-  the oracle, statistics and the Gaussian mixture of all 64."""
+  the oracle, statistics and the Gaussian mixture of all 64;
+* the 96-member mixed FP32 benchmark workload in the benchmark's launch
+  configuration -- one member per grid size sampled against the oracle."""
 import math
 
 import numpy as np
