@@ -1,0 +1,92 @@
+"""Edge cases of the stepping path on the GPU: degenerate fields, empty and
+invalid requests, and a closed form that holds at any size (a single Fourier
+mode has no nonlinear term and, outside the forcing band, decays exactly by
+the viscous factor)."""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def ens_mod():
+    import paper_2506_23712_amd as ens
+    return ens
+
+
+@pytest.mark.parametrize("n,prec", [(16, "fp64"), (64, "fp32"), (256, "fp64"), (256, "fp32")])
+def test_single_mode_decays_by_the_viscous_factor(n, prec):
+    """u = (0, a, 0) e^{i m x} with m = (3, 0, 0) is a steady Euler solution
+    (u.grad u = 0 and it is divergence free): one RK3 step with the integrating
+    factor multiplies it by exp(-nu |k|^2 dt) exactly, at every grid size.
+    Without injection (eps = 0): the linear band forcing eps / (2 E_f) u is
+    singular for a band without energy, and would blow the round-off that the
+    transforms leave in the band up to the injection rate."""
+    import torch
+    ens = ens_mod()
+    nu, dt = 0.05, 0.01
+    E = ens.Ensemble()
+    m = E.add_member(ens.MemberSpec(n=n, nu=nu, eps_ref=0.0, kf_lo=0.0, kf_hi=1.5, dt=dt, precision=prec, seed=1))
+    u = np.zeros((3, n, n, n // 2 + 1), dtype=np.complex128)
+    u[1, 0, 0, 3] = 0.25 - 0.5j
+    m.set_state(torch.from_numpy(u))
+    E.step(4)
+    got = m.state().cpu().numpy()
+    E.close()
+    want = u * math.exp(-nu * 9.0 * 4 * dt)
+    tol = 1e-14 if prec == "fp64" else 1e-6
+    assert np.max(np.abs(got - want)) <= tol * np.max(np.abs(u))
+
+
+def test_zero_field_with_fixed_dt_stays_zero_and_cfl_reports_no_velocity():
+    import torch
+    ens = ens_mod()
+    E = ens.Ensemble()
+    a = E.add_member(ens.MemberSpec(n=32, nu=0.02, eps_ref=1.0, kf_hi=2.5, dt=0.01, seed=2))
+    b = E.add_member(ens.MemberSpec(n=32, nu=0.02, eps_ref=1.0, kf_hi=2.5, dt=0.0, cfl=0.5, seed=3))
+    z = torch.zeros((3, 32, 32, 17), dtype=torch.complex128)
+    a.set_state(z)
+    b.set_state(z)
+    E.step(2, members=[a])
+    assert np.all(a.state().cpu().numpy() == 0)              # no band energy: no forcing, no flow
+    da = a.diag()
+    assert not da["diverged"] and da["E"] == 0.0 and abs(da["t"] - 0.02) < 1e-15
+    E.step(1, members=[b])
+    assert b.diag()["diverged"]                              # no CFL velocity: flagged, not a fault
+    E.close()
+
+
+def test_zero_steps_and_invalid_requests_change_nothing():
+    import paper_2506_23712_amd as ens
+    from paper_2506_23712_amd import _lib
+    E = ens.Ensemble()
+    m = E.add_member(ens.MemberSpec(n=32, nu=0.02, eps_ref=1.0, kf_hi=2.5, seed=4))
+    before = m.state().cpu().numpy()
+    E.step(0)
+    assert np.array_equal(m.state().cpu().numpy(), before) and m.diag()["step"] == 0
+    L = _lib.lib()
+    ids = (ctypes.c_int32 * 2)(m.id, m.id)
+    assert L.ens_step(E.ctx, ids, 0, 1, None) == _lib.ENS_E_INVALID          # empty list
+    assert L.ens_step(E.ctx, ids, 2, 1, None) == _lib.ENS_E_INVALID          # duplicate member
+    bad = (ctypes.c_int32 * 1)(99)
+    assert L.ens_step(E.ctx, bad, 1, 1, None) == _lib.ENS_E_INVALID          # unknown member
+    assert L.ens_step(E.ctx, ids, 1, -1, None) == _lib.ENS_E_INVALID         # negative step count
+    with pytest.raises(ens.EnsError):
+        E.add_member(ens.MemberSpec(n=48, nu=0.02))                          # not a supported size
+    with pytest.raises(ens.EnsError):
+        E.add_member(ens.MemberSpec(n=1024, nu=0.02, precision="fp64"))      # 1024^3 is FP32 only
+    with pytest.raises(ens.EnsError):
+        E.add_member(ens.MemberSpec(n=32, nu=0.02, dt=0.0, cfl=0.0))         # no time step rule
+    # a workspace one byte short is refused before anything is written
+    import torch
+    spec = ens.MemberSpec(n=32, nu=0.02, seed=5)
+    need = E.workspace_bytes(spec)
+    ws = torch.empty(need - 1, dtype=torch.uint8, device="cuda")
+    mid = ctypes.c_int32(-1)
+    d = spec.desc()
+    st = L.ens_member_init(E.ctx, ctypes.byref(d), ctypes.c_void_p(ws.data_ptr()), need - 1, None, ctypes.byref(mid))
+    assert st == _lib.ENS_E_OOM and mid.value == -1
+    assert np.array_equal(m.state().cpu().numpy(), before)
+    E.close()
