@@ -227,7 +227,7 @@ def main():
                     help="only run a plain device copy of MIB MiB (reference for HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (members shard across GPUs by design, "
+        print("bench.py: runs on one GPU only (an ensemble would shard across GPUs by member, "
               "not implemented here); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch

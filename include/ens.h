@@ -42,7 +42,7 @@ typedef enum {
     ENS_E_INVALID = -1,      /* bad argument; nothing changed */
     ENS_E_OOM = -2,          /* a workspace is smaller than required */
     ENS_E_HIP = -3,          /* a HIP call failed; the context is poisoned */
-    ENS_E_UNSUPPORTED = -4,  /* valid request this build does not provide */
+    ENS_E_UNSUPPORTED = -4,  /* valid request this library does not provide */
     ENS_E_STATE = -5,        /* call not allowed in the current state */
     ENS_E_DIVERGED = -6      /* a member has non-finite energy or no CFL velocity */
 } ens_status;
