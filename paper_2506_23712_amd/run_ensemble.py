@@ -66,12 +66,15 @@ def run(E, members, transient: float, measure: float, snaps_per_T: float, chunk:
         E.step(chunk)
         steps += chunk
         sc = _scales(members)
-        prog = min(t / T for t, T in sc if T > 0)
+        prog = min((t / T if T > 0 else 0.0) for t, T in sc)
         log(f"transient: step {steps}, slowest member at {prog:.2f} T, {time.perf_counter() - t_start:.0f} s")
         if prog >= transient or steps >= max_steps:
             break
     # steps per integral time (median over members) sets the snapshot interval
-    per_T = sorted(T / m.diag()["dt"] for m, (t, T) in zip(members, sc))[len(members) // 2]
+    rates = sorted(T / d for d, (t, T) in ((m.diag()["dt"], s) for m, s in zip(members, sc)) if d > 0 and T > 0)
+    if not rates:
+        raise RuntimeError("no member has a positive time step and integral time after the transient")
+    per_T = rates[len(rates) // 2]
     every = max(1, int(round(per_T / snaps_per_T)))
     for m in members:
         m.reset_stats()
@@ -89,7 +92,7 @@ def run(E, members, transient: float, measure: float, snaps_per_T: float, chunk:
         for k, (_, T) in enumerate(sc):
             Tsum[k] += T
         e_central.append(central.diag()["E"])
-        prog = min((t - t0[k]) / (Tsum[k] / nsnap) for k, (t, _) in enumerate(sc))
+        prog = min(((t - t0[k]) / (Tsum[k] / nsnap) if Tsum[k] > 0 else 0.0) for k, (t, _) in enumerate(sc))
         if nsnap % 10 == 0:
             log(f"measure: step {steps + m_steps}, {nsnap} snapshots, slowest member at {prog:.2f} T, "
                 f"{time.perf_counter() - t_start:.0f} s")
@@ -109,7 +112,8 @@ def run(E, members, transient: float, measure: float, snaps_per_T: float, chunk:
         K = m.spec.n // 3
         per.append({"lambda": m.spec.lam, "n": m.spec.n, "E": Em, "D": Dm, "rlambda": gap["rlambda"][k],
                     "kmeta": K * (2 * math.pi / m.spec.box) * (m.spec.nu ** 3 / Dm) ** 0.25,
-                    "T": Tsum[k] / nsnap, "measured_T": (m.diag()["t"] - t0[k]) / (Tsum[k] / nsnap)})
+                    "T": Tsum[k] / nsnap,
+                    "measured_T": (m.diag()["t"] - t0[k]) / (Tsum[k] / nsnap) if Tsum[k] > 0 else 0.0})
     res["members"] = per
     # stationarity of the central member: mean energy of the two halves of the record
     h = len(e_central) // 2
