@@ -261,26 +261,72 @@ __global__ void __launch_bounds__(256, 2) k_gxstats(const MemberDev *__restrict_
     const double nu = md.nu;
     const int ntiles = N * N / T;
     __syncthreads();
+    // Gradient spectra, field f = 3 c + j: j = 0 i k_x u_c (from u_c, fields 0-2
+    // of bufB), j = 1 d_y u_c (fields 3-5), j = 2 d_z u_c (fields 6-8).  The raw
+    // row entries of a field pair are loaded one pair ahead of their use (the
+    // next tile's first pair during this tile's last transform and the
+    // pointwise work), so that the loads are in flight behind the arithmetic.
+    auto foff = [](int f) -> long long { return (long long)((f % 3 == 0 ? 0 : (f % 3 == 1 ? 3 : 6)) + f / 3) * FS; };
+    auto load_pair = [&](int tile, int pr, Cx<P> (&ra)[E], Cx<P> (&rb)[E]) {
+        const uint32_t rbase = (uint32_t)(tile * T + l) * PX;
+        const int fa = 2 * pr, fb = 2 * pr + 1;
+        const Fld<P> Fa(md.bufB, foff(fa)), Fb(md.bufB, fb < 9 ? foff(fb) : 0);
+#pragma unroll
+        for (int m = 0; m < E; m++) {
+            const int n = t + M * m;
+            const bool lo = n <= K, hi = n >= N - K;
+            const uint32_t kx = (uint32_t)(lo ? n : N - n);
+            ra[m] = czero<P>();
+            rb[m] = czero<P>();
+            if (lo || hi) {
+                ra[m] = Fa.ld(rbase + kx);
+                if (fb < 9) rb[m] = Fb.ld(rbase + kx);
+            }
+        }
+    };
+    // FP32 only: in FP64 the second pair of registers would spill
+    constexpr bool PF = sizeof(P) == 4;
+    Cx<P> ra[E], rb[E];
+    if (PF && (int)blockIdx.x < ntiles) load_pair(blockIdx.x, 0, ra, rb);
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const uint32_t rb = (uint32_t)(tile * T + l) * PX;
-        auto spec = [&](int f, uint32_t kx) -> Cx<P> {
-            const int c = f / 3, j = f % 3;
-            if (j == 0) return mul_i(cscale(Fld<P>(md.bufB, c * FS).ld(rb + kx), dk * (P)kx));
-            return Fld<P>(md.bufB, ((j == 1 ? 3 : 6) + c) * FS).ld(rb + kx);
-        };
         P g[9][E];
         Cx<P> v[E];
 #pragma unroll
         for (int pr = 0; pr < 5; pr++) {
             const int fa = 2 * pr, fb = 2 * pr + 1;
+            if constexpr (PF) {
+                Cx<P> ca[E], cb[E];
 #pragma unroll
-            for (int m = 0; m < E; m++) {
-                const int n = t + M * m;
-                Cx<P> A = czero<P>(), B = czero<P>();
-                if (n <= K) { A = spec(fa, n); if (fb < 9) B = spec(fb, n); }
-                else if (n >= N - K) { A = cconj(spec(fa, N - n)); if (fb < 9) B = cconj(spec(fb, N - n)); }
-                if (n == 0) { A.im = P(0); B.im = P(0); }
-                v[m] = {A.re - B.im, A.im + B.re};
+                for (int m = 0; m < E; m++) { ca[m] = ra[m]; cb[m] = rb[m]; }
+                if (pr < 4) load_pair(tile, pr + 1, ra, rb);
+                else if (tile + (int)gridDim.x < ntiles) load_pair(tile + gridDim.x, 0, ra, rb);
+#pragma unroll
+                for (int m = 0; m < E; m++) {
+                    const int n = t + M * m;
+                    const bool lo = n <= K, hi = n >= N - K;
+                    const P kx = (P)(lo ? n : N - n);
+                    Cx<P> A = ca[m], B = cb[m];
+                    if (fa % 3 == 0) A = mul_i(cscale(A, dk * kx));
+                    if (fb < 9 && fb % 3 == 0) B = mul_i(cscale(B, dk * kx));
+                    if (hi && !lo) { A = cconj(A); B = cconj(B); }
+                    if (n == 0) { A.im = P(0); B.im = P(0); }
+                    v[m] = {A.re - B.im, A.im + B.re};
+                }
+            } else {
+                const uint32_t rbase = (uint32_t)(tile * T + l) * PX;
+                auto spec = [&](int f, uint32_t kx) -> Cx<P> {
+                    const Cx<P> x = Fld<P>(md.bufB, foff(f)).ld(rbase + kx);
+                    return f % 3 == 0 ? mul_i(cscale(x, dk * (P)kx)) : x;
+                };
+#pragma unroll
+                for (int m = 0; m < E; m++) {
+                    const int n = t + M * m;
+                    Cx<P> A = czero<P>(), B = czero<P>();
+                    if (n <= K) { A = spec(fa, n); if (fb < 9) B = spec(fb, n); }
+                    else if (n >= N - K) { A = cconj(spec(fa, N - n)); if (fb < 9) B = cconj(spec(fb, N - n)); }
+                    if (n == 0) { A.im = P(0); B.im = P(0); }
+                    v[m] = {A.re - B.im, A.im + B.re};
+                }
             }
             line_fft<P, N, E, T, +1>(v, lds, l, t, tw);
 #pragma unroll
