@@ -1,0 +1,31 @@
+"""The ensemble driver's recipe against the paper's printed numbers (CPU):
+the lambda grid of the ensemble table and the paragraph after the reference
+table (48 members, spacing 0.23, range [-5.1, 5.8]), the forcing band
+[1.4, 2.3] dk and CFL 0.2, and k_M eta = 3 for the central member with k_M eta
+spanning 0.7 .. 10.6 over the members (tests/golden/paper_values.json)."""
+import json
+import math
+import os
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+
+
+def test_ens128_recipe_matches_the_printed_ensemble():
+    import paper_2506_23712_amd as ens
+    from paper_2506_23712_amd import run_ensemble as rd
+    specs = rd.ens128_specs(ens)
+    lam = [s.lam for s in specs]
+    assert len(specs) == GOLD["ens256_members"]["value"]
+    lo, hi = GOLD["ens256_lambda_range"]["value"]
+    assert round(min(lam), 1) == lo and round(max(lam), 1) == hi
+    assert round(lam[1] - lam[0], 2) == GOLD["ens256_dlambda"]["value"]
+    assert sum(1 for x in lam if x == 0.0) == 1
+    assert all(s.n == 128 and s.kf_lo == 1.4 and s.kf_hi == 2.3 and s.cfl == 0.2 and s.dt == 0.0 for s in specs)
+    # k_M eta = K dk (nu^3 / eps)^(1/4): 3 at eps = 1, e^(-lambda/4) times that across the members
+    K, nu = 128 // 3, specs[0].nu
+    kmeta = [K * (nu ** 3 / math.exp(x)) ** 0.25 for x in lam]
+    assert abs(K * nu ** 0.75 - GOLD["ens256_kmeta_central"]["value"]) < 1e-12
+    kmin, kmax = GOLD["ens256_kmeta_range"]["value"]
+    assert abs(min(kmeta) - kmin) / kmin < 0.02 and abs(max(kmeta) - kmax) / kmax < 0.02
+    assert len({s.seed for s in specs}) == len(specs)
+
