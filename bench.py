@@ -18,7 +18,9 @@ Workloads
                      25 x 256^3), FP32 transforms/RHS with FP64 reductions.
   single256_fp64   : one 256^3 member, nu = 4.594e-3 (k_max eta ~ 1.5),
                      eps = 1, band |m| <= 2.5, CFL 0.5, FP64.
-The JSON line reports the first as `value` and the second beside it.
+The JSON line reports the first as `value` and the second beside it, and for
+each workload the rate of RK steps alone (`rk_only`: median and interquartile
+range of five repeats, without statistics snapshots or the mixture).
   ens48_128_fp64   : (only with --only ens48_128_fp64) the 48-member 128^3 FP64
                      set of the ensemble driver: lambda = i ln2/3, i = -22..25,
                      band [1.4, 2.3], CFL 0.2, k_M eta = 3 for lambda = 0.
@@ -90,6 +92,17 @@ def run_workload(ens, torch, name, specs, steps, warmup, stats_every, hist_nu, a
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     pts = sum(s.n ** 3 for s in specs)
+    # RK steps alone (no statistics, no mixture): five repeats of a quarter of the
+    # timed steps each, for the median and the interquartile range
+    rk = []
+    for _ in range(5):
+        k = max(1, steps // 4)
+        torch.cuda.synchronize()
+        r0 = time.perf_counter()
+        E.step(k)
+        torch.cuda.synchronize()
+        rk.append(pts * k / (time.perf_counter() - r0))
+    rk.sort()
     diverged = [m.id for m in members if m.diag()["diverged"]]
     # per-kernel times with HIP events on the launch stream, per grid size
     groups = sorted({(s.n, s.precision) for s in specs}, reverse=True)
@@ -112,7 +125,8 @@ def run_workload(ens, torch, name, specs, steps, warmup, stats_every, hist_nu, a
     E.close()
     return {"name": name, "seconds": t1 - t0, "points": pts, "rate": pts * steps / (t1 - t0), "variants": variants,
             "ms_per_step": 1e3 * (t1 - t0) / steps, "prof": prof, "diverged": diverged,
-            "mix_weight_sum": float(mix["weights"].sum()), "stats_snapshot_ms": stats_ms}
+            "mix_weight_sum": float(mix["weights"].sum()), "stats_snapshot_ms": stats_ms,
+            "rk_only": {"median": rk[2], "iqr": [rk[1], rk[3]], "repeats": 5, "steps_each": max(1, steps // 4)}}
 
 
 def measured_traffic(workload: str, kernel: str):
@@ -172,9 +186,17 @@ def cpu_baseline(specs, steps=3):
         oracle.run(m, u, steps)
         pts += m.n ** 3 * steps
     dt = time.perf_counter() - t0
+    # the same on one thread, smallest grid only
+    m, u = work[0]
+    oracle.set_threads(1)
+    s0 = time.perf_counter()
+    oracle.run(m, u, steps)
+    d1 = time.perf_counter() - s0
+    oracle.set_threads(threads)
     return {"value": round(pts / dt, 1), "unit": "grid-pt RK steps/s", "cores": threads, "kind": "oracle",
             "sample": f"{steps} FP64 RK3 steps of one member at each of {sizes} (oracle, {threads} OpenMP threads), "
-                      f"{dt:.1f} s"}
+                      f"{dt:.1f} s",
+            "one_thread": {"value": round(m.n ** 3 * steps / d1, 1), "sample": f"{steps} steps at {m.n}^3, {d1:.1f} s"}}
 
 
 def diagnostics(ens, torch, reps=20):
@@ -286,6 +308,10 @@ def main():
                           for (n, p), (ms, c) in head["prof"].items()}
     out["diverged_members"] = head["diverged"]
     out["stats_snapshot_ms"] = {r["name"]: round(r["stats_snapshot_ms"], 3) for r in res.values()}
+    out["rk_only"] = {r["name"]: {"median": round(r["rk_only"]["median"], 1),
+                                  "iqr": [round(x, 1) for x in r["rk_only"]["iqr"]],
+                                  "repeats": r["rk_only"]["repeats"], "steps_each": r["rk_only"]["steps_each"]}
+                      for r in res.values()}
     out["kernel_variants"] = {k: v for r in res.values() for k, v in r["variants"].items()}
     if not args.no_cpu_baseline:
         specs = {"ens96_mixed_fp32": ens96_specs, "single256_fp64": single256_specs,
