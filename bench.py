@@ -71,7 +71,7 @@ def pass_bytes(n: int, prec: str) -> dict:
     return profiling.pass_bytes(n, prec)
 
 
-def run_workload(ens, torch, name, specs, steps, warmup, stats_every, hist_nu, autotune=True):
+def run_workload(ens, torch, name, specs, steps, warmup, stats_every, hist_nu, autotune=True, develop=0):
     E = ens.Ensemble(hist=hist_for(ens, hist_nu), graphs=True)
     members = [E.add_member(s) for s in specs]
     torch.cuda.synchronize()
@@ -116,6 +116,10 @@ def run_workload(ens, torch, name, specs, steps, warmup, stats_every, hist_nu, a
             acc = p if acc is None else {k: acc[k] + p[k] for k in p}
         prof[(n, prec)] = ({k: v / reps for k, v in acc.items()}, len(sel))
     # one statistics snapshot of the whole workload, HIP events on the launch stream
+    # (optionally after `develop` more steps, so that the gradients have their
+    # developed, heavy-tailed distribution)
+    if develop:
+        E.step(develop)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record()
     E.accumulate_stats()
@@ -243,6 +247,8 @@ def main():
     ap.add_argument("--only", choices=["ens96_mixed_fp32", "single256_fp64", "ens48_128_fp64"], default=None,
                     help="one workload; ens48_128_fp64 (the 48-member 128^3 FP64 set of the ensemble driver) "
                          "runs only when named")
+    ap.add_argument("--develop", type=int, default=0, metavar="STEPS",
+                    help="step the workload this many more steps before the timed statistics snapshot")
     ap.add_argument("--diagnostics", action="store_true",
                     help="only time the spectral diagnostics (spectrum, integral scales, refinement) and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -270,14 +276,14 @@ def main():
     res = {}
     if args.only in (None, "ens96_mixed_fp32"):
         res["ens"] = run_workload(ens, torch, "ens96_mixed_fp32", ens96_specs(ens), args.steps, args.warmup,
-                                  args.stats_every, 0.03395, not args.no_autotune)
+                                  args.stats_every, 0.03395, not args.no_autotune, args.develop)
     if args.only in (None, "single256_fp64"):
         res["single"] = run_workload(ens, torch, "single256_fp64", single256_specs(ens), args.steps, args.warmup,
-                                     args.stats_every, 4.594e-3, not args.no_autotune)
+                                     args.stats_every, 4.594e-3, not args.no_autotune, args.develop)
     if args.only == "ens48_128_fp64":
         specs = ens48_128_specs(ens)
         res["ens48"] = run_workload(ens, torch, "ens48_128_fp64", specs, args.steps, args.warmup,
-                                    args.stats_every, specs[0].nu, not args.no_autotune)
+                                    args.stats_every, specs[0].nu, not args.no_autotune, args.develop)
     head = res.get("ens") or res.get("single") or res["ens48"]
     out = {
         "metric": "grid-pt RK steps/s (batched FP32 ensemble; FP64 single member beside it)",
@@ -308,6 +314,8 @@ def main():
                           for (n, p), (ms, c) in head["prof"].items()}
     out["diverged_members"] = head["diverged"]
     out["stats_snapshot_ms"] = {r["name"]: round(r["stats_snapshot_ms"], 3) for r in res.values()}
+    if args.develop:
+        out["stats_snapshot_after_steps"] = args.develop
     out["rk_only"] = {r["name"]: {"median": round(r["rk_only"]["median"], 1),
                                   "iqr": [round(x, 1) for x in r["rk_only"]["iqr"]],
                                   "repeats": r["rk_only"]["repeats"], "steps_each": r["rk_only"]["steps_each"]}

@@ -19,9 +19,10 @@ __device__ __forceinline__ int shell_of(long long m2) {
 // wave v (0 .. 4 kDiagParts - 1 over the plane) takes rows iy = v, v + 4 kDiagParts, ...,
 // RG rows at a time whose loads are issued together (indices clamped into the
 // member so that every load is unconditional), a row in chunks of 64
-// consecutive m_x, one per lane.  `f(r_valid, mx, my, e)` receives each lane's
-// energy e_m = (1/2)|u_hat_m|^2 of the full spectrum (weight 1 for m_x > 0: the
-// mode and its mirror; 1/2 for m_x = 0); lanes past the row end get e = 0, mx > K.
+// consecutive m_x, one per lane.  `f(mx, my, e)` receives each lane's mode
+// numbers and energy e_m = (1/2)|u_hat_m|^2 of the full spectrum (weight 1 for
+// m_x > 0: the mode and its mirror; 1/2 for m_x = 0); lanes past the row end
+// get mx > K and e = 0.
 template <typename P, int RG, class F>
 __device__ __forceinline__ void plane_rows(const MemberDev &md, int iz, int v0, F &&f) {
     const int K = md.K, NY = 2 * K + 1, lane = threadIdx.x & 63;

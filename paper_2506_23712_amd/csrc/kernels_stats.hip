@@ -223,6 +223,10 @@ __global__ void __launch_bounds__(256, 2) k_gxstats(const MemberDev *__restrict_
     constexpr int NC = kHotCopies1, CW = kHotBins1, NQ = kHotCopiesQ, CQ = kHotBinsQ;
     __shared__ unsigned int cen1[4][CW][NC];                // log eps, log Omega, A_L, A_T
     __shared__ unsigned int cenq[CQ * CQ][NQ];
+    // QR points outside the axes and NaN points: one LDS counter each, flushed
+    // once (a developed field sends whole members' points there, which as
+    // global atomics on one address serialise)
+    __shared__ unsigned int qspec[3];
     const MemberDev &md = mems[blockIdx.y];
     const int l = threadIdx.x % T, t = threadIdx.x / T;
     const int grp = threadIdx.x & (NC - 1), grq = threadIdx.x & (NQ - 1);
@@ -233,6 +237,7 @@ __global__ void __launch_bounds__(256, 2) k_gxstats(const MemberDev *__restrict_
     for (int i = threadIdx.x; i <= h.lb; i += 256) ledge[i] = h.ledge[i];
     for (int i = threadIdx.x; i < 4 * NC * CW; i += 256) (&cen1[0][0][0])[i] = 0u;
     for (int i = threadIdx.x; i < NQ * CQ * CQ; i += 256) (&cenq[0][0])[i] = 0u;
+    if (threadIdx.x < 3) qspec[threadIdx.x] = 0u;
     unsigned int *h_le = hs, *h_lw = hs + (h.lb + 3), *h_al = hs + 2 * (h.lb + 3), *h_at = h_al + (h.ab + 3);
     unsigned int *h_qr = hs + n1d;
     unsigned long long *G = md.counts;
@@ -360,11 +365,11 @@ __global__ void __launch_bounds__(256, 2) k_gxstats(const MemberDev *__restrict_
             const double qs = q * h.inv_trs, rs = r * h.inv_trs15;
             const double es = 2.0 * nu * ss * h.inv_eps_ref, ws = ens * h.om_scale;
             {   // QR: replicated centre, then the LDS window, elsewhere global
-                int gidx = -1, widx = -1, cidx = -1;
-                if (qs != qs || rs != rs) gidx = h.qb * h.qb + 2;
+                int gidx = -1, widx = -1, cidx = -1, sidx = -1;
+                if (qs != qs || rs != rs) sidx = 2;
                 else {
                     const int bq = bin_of(qs, h.q_lo, h.q_scale, h.qb), br = bin_of(rs, h.r_lo, h.r_scale, h.qb);
-                    if (bq < 0 || br < 0) gidx = h.qb * h.qb;
+                    if (bq < 0 || br < 0) sidx = 0;
                     else if (q0 >= 0 && r0 >= 0 && bq >= q0 && bq < q0 + CQ && br >= r0 && br < r0 + CQ)
                         cidx = (bq - q0) * CQ + (br - r0);
                     else if (bq >= h.win0 && bq < h.win0 + h.win && br >= h.win0 && br < h.win0 + h.win)
@@ -373,6 +378,7 @@ __global__ void __launch_bounds__(256, 2) k_gxstats(const MemberDev *__restrict_
                 }
                 if (cidx >= 0) atomicAdd(&cenq[cidx][grq], 1u);
                 else if (widx >= 0) atomicAdd(&h_qr[widx], 1u);
+                else if (sidx >= 0) atomicAdd(&qspec[sidx], 1u);
                 else atomicAdd(&G[gidx], 1ull);
             }
             add1(0, slot_1d(es > 0.0 ? log_bin(es, ledge, h.lb, h.l2s, h.loff) : (es != es ? -3 : -1), h.lb));
@@ -412,6 +418,8 @@ __global__ void __launch_bounds__(256, 2) k_gxstats(const MemberDev *__restrict_
         for (int c = 0; c < NQ; c++) sum += cenq[i][c];
         if (sum) atomicAdd(&G[(long long)(q0 + i / CQ) * h.qb + (r0 + i % CQ)], (unsigned long long)sum);
     }
+    if (threadIdx.x < 3 && qspec[threadIdx.x])
+        atomicAdd(&G[(long long)h.qb * h.qb + threadIdx.x], (unsigned long long)qspec[threadIdx.x]);
     // deterministic reduction of the moments: wave butterfly, then waves in order
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
@@ -511,7 +519,7 @@ static hipError_t stats_pass(int pass, const MemberDev *mem, int count, const en
         h.loff = (float)(h.l_lo * h.l_scale);
         // LDS: transform tile + reduction (static) + log edges, 1-D histograms, QR window (dynamic) <= 64 KiB
         constexpr int T = 256 / (N / 4);
-        const size_t stat = (size_t)N * T * sizeof(LdsT<P>) + 4 * 32 * sizeof(double) + kHotBytes +
+        const size_t stat = (size_t)N * T * sizeof(LdsT<P>) + 4 * 32 * sizeof(double) + kHotBytes + 16 +
                             (size_t)twiddle_span(N, 4) * sizeof(Cx<P>);
         const size_t n1d = 2 * (size_t)(h.lb + 3) + 2 * (size_t)(h.ab + 3);
         const size_t budget = 65536 - stat - 512;
