@@ -1,0 +1,40 @@
+"""The byte model and kernel names the benchmark's roofline uses (CPU): the
+per-pass algorithmic bytes add up to the per-step totals, scale with the
+complex size, and the kernel named for each variant exists in the library's
+sources."""
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_pass_bytes_model():
+    from paper_2506_23712_amd import profiling as p
+    for n in (64, 128, 256, 512):
+        K = n // 3
+        S = (2 * K + 1) ** 2 * (K + 1)
+        zl, yl = n * (2 * K + 1) * (K + 1), n * n * (K + 1)
+        b64, b32 = p.pass_bytes(n, "fp64"), p.pass_bytes(n, "fp32")
+        assert set(b64) == {"zinv", "yinv", "xpass", "yfwd", "zfwd_update"}
+        for k in b64:
+            assert abs(b64[k] - 2 * b32[k]) < 1e-6                  # 16 vs 8 bytes per complex value
+        assert b64["xpass"] == 9 * yl * 16                             # 6 fields read, 3 written
+        assert b64["zinv"] == (3 * S + 5 * zl) * 16
+        # z forward + update: 3 z-line fields, u_hat read and written, q read in 2 and written in 2 of 3 stages
+        assert abs(b64["zfwd_update"] - (3 * zl + 3 * S + 2 * S + 3 * S + 2 * S) * 16) < 1e-6
+    per_pt = sum(p.pass_bytes(256, "fp64").values()) / 256 ** 3
+    assert 180 < per_pt < 190                                          # about 185 B per point and stage
+
+
+def test_kernel_names_exist_in_the_sources():
+    from paper_2506_23712_amd import profiling as p
+    src = open(os.path.join(ROOT, "paper_2506_23712_amd", "csrc", "kernels_step.hip")).read()
+    for (pass_name, n, prec, v) in (("xpass", 256, "fp32", 3), ("xpass", 256, "fp32", 2), ("xpass", 512, "fp64", 3),
+                                    ("xpass", 32, "fp32", 2), ("yinv", 256, "fp32", 1), ("zfwd_update", 128, "fp64", 0)):
+        name = p.kernel_name(pass_name, n, prec, v)
+        base = re.sub(r"<.*", "", name.replace("ens::", ""))
+        assert re.search(r"\b" + base + r"\b", src), name
+    assert p.kernel_name("xpass", 256, "fp32", 3).endswith(", 16>")
+    assert p.kernel_name("xpass", 256, "fp64", 3).endswith(", 8>")   # FP64 falls back to 8 values per thread
+    assert p.kernel_name("xpass", 32, "fp32", 2) == "ens::k_xpass<float, 32, 8>"
+
