@@ -25,7 +25,10 @@
  * Fourier pseudo-spectral method on [0,L)^3, cubic 2/3 truncation
  * |m_x|,|m_y|,|m_z| <= floor(N/3), rotational nonlinear term u x omega,
  * solenoidal projection, linear band forcing f = eps/(2 E_f) u on the band
- * (E_f evaluated at every Runge-Kutta stage), integrating-factor low-storage
+ * (E_f evaluated at every Runge-Kutta stage; f acts on the Hermitian part of
+ * the spectrum and is projected together with the nonlinear term, which
+ * changes nothing for the spectrum of a real solenoidal field), integrating-
+ * factor low-storage
  * (Williamson 2N) RK3 with A = (0,-5/9,-153/128), B = (1/3,15/16,8/15),
  * and CFL time step dt = cfl * dx / max(|u|+|v|+|w|) from the stage-1 field.
  *
@@ -348,14 +351,29 @@ static int in_band(const or_params *p, const int m[3]) {
     return d >= p->kf_lo * p->kf_lo && d <= p->kf_hi * p->kf_hi;
 }
 
-/* band energy E_f = (1/2) sum over band modes of the full spectrum */
+/* The velocity is a real field, so its spectrum has u(-k) = conj u(k).  A
+ * part of the stored spectrum that breaks this is invisible in physical space
+ * (the nonlinear term never sees it); the forcing acts on the Hermitian part
+ * (u(k) + conj u(-k)) / 2 only, so that such a part is not amplified. */
+static inline cplx herm(const grid_t *g, const cplx *f, long i) {
+    const int n = g->n;
+    const long x = i % n, y = (i / n) % n, z = i / ((long)n * n);
+    const long j = (((n - z) % n) * n + (n - y) % n) * n + (n - x) % n;
+    return 0.5 * (f[i] + conj(f[j]));
+}
+
+/* band energy E_f = (1/2) sum over band modes of the full spectrum (of its
+ * Hermitian part) */
 static double band_energy(const rhs_work *W, cplx *const uh[3]) {
     double ef = 0.0;
     for (long i = 0; i < W->g.n3; i++) {
         int m[3]; double k[3];
         kvec(&W->g, i, m, k);
         if (!in_band(&W->p, m)) continue;
-        for (int c = 0; c < 3; c++) ef += 0.5 * creal(uh[c][i] * conj(uh[c][i]));
+        for (int c = 0; c < 3; c++) {
+            cplx h = herm(&W->g, uh[c], i);
+            ef += 0.5 * creal(h * conj(h));
+        }
     }
     return ef;
 }
@@ -421,6 +439,9 @@ static void rhs_eval(rhs_work *W, cplx *const uh[3], cplx *G[3], int terms, doub
         }
     }
 
+    /* The forcing enters the right-hand side through the same projection as
+     * the nonlinear term (the pressure removes the divergent part of every
+     * non-viscous term); for a solenoidal field P u = u. */
     double ef = band_energy(W, uh), inj = 0.0;
     if ((terms & T_FORCING) && ef > 0.0) {
         double fac = W->p.eps / (2.0 * ef);
@@ -428,8 +449,13 @@ static void rhs_eval(rhs_work *W, cplx *const uh[3], cplx *G[3], int terms, doub
             int m[3]; double k[3];
             kvec(g, i, m, k);
             if (!in_band(&W->p, m)) continue;
+            double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+            if (k2 == 0.0) continue;
+            cplx h[3];
+            for (int c = 0; c < 3; c++) h[c] = herm(g, uh[c], i);
+            cplx kd = k[0] * h[0] + k[1] * h[1] + k[2] * h[2];
             for (int c = 0; c < 3; c++) {
-                cplx f = fac * uh[c][i];
+                cplx f = fac * (h[c] - k[c] * kd / k2);
                 G[c][i] += f;
                 inj += creal(conj(uh[c][i]) * f);
             }

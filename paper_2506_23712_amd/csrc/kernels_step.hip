@@ -76,7 +76,8 @@ template <typename P, int N, int E_> struct Cfg {
 };
 
 // ================================================================== band
-// One workgroup per member: E_f over the forcing band (FP64, fixed order).
+// One workgroup per member: the band's part of the m_x = 0 plane made
+// Hermitian, then E_f over the forcing band (FP64, fixed order).
 template <typename P>
 __global__ void __launch_bounds__(256) k_band_energy(const MemberDev *__restrict__ mems, int stage) {
     __shared__ double red[256];
@@ -88,6 +89,29 @@ __global__ void __launch_bounds__(256) k_band_energy(const MemberDev *__restrict
     if (B > K) B = K;
     const int W = 2 * B + 1;
     const long long ncand = (long long)(B + 1) * W * W;
+    // The velocity is real, so the m_x = 0 plane of its half spectrum is
+    // Hermitian: u(0, -m_y, -m_z) = conj u(0, m_y, m_z).  A part breaking
+    // that is invisible to the nonlinear term, and the linear forcing would
+    // amplify it in the band; the band's part of the plane is made Hermitian
+    // here (one thread per pair) before E_f is summed.
+    for (int c = (int)threadIdx.x; c < W * W; c += 256) {
+        const int my = c % W - B, mz = c / W - B;
+        const int m2 = my * my + mz * mz;
+        if (!(mz > 0 || (mz == 0 && my > 0)) || (double)m2 < md.kf_lo2 || (double)m2 > md.kf_hi2) continue;
+        const int iy = my >= 0 ? my : my + 2 * K + 1, iz = mz;
+        const int jy = my > 0 ? 2 * K + 1 - my : -my, jz = mz > 0 ? 2 * K + 1 - mz : 0;
+        const uint32_t i1 = (uint32_t)((long long)iz * zp + (long long)iy * (K + 1));
+        const uint32_t i2 = (uint32_t)((long long)jz * zp + (long long)jy * (K + 1));
+#pragma unroll
+        for (int comp = 0; comp < 3; comp++) {
+            const Fld<P> F(md.uh, comp * S);
+            const Cx<P> a = F.ld(i1), b = F.ld(i2);
+            const Cx<P> h = {P(0.5) * (a.re + b.re), P(0.5) * (a.im - b.im)};
+            F.st(i1, h);
+            F.st(i2, {h.re, -h.im});
+        }
+    }
+    __syncthreads();
     double acc = 0.0;
     for (long long c = threadIdx.x; c < ncand; c += 256) {
         const int mx = (int)(c % (B + 1));
@@ -755,15 +779,19 @@ __global__ void __launch_bounds__((Cfg<P, N, 8>::NTZ), (Cfg<P, N, 8>::ZMINB)) k_
                 g[0] = g[1] = g[2] = czero<P>();
             } else {
                 Cx<P> n0 = cscale(a[0][s], inv_n3), n1 = cscale(a[1][s], inv_n3), n2 = cscale(a[2][s], inv_n3);
+                // the band forcing joins the nonlinear term before the projection:
+                // unprojected, it would amplify the rounding-level divergent part
+                // of u in the band at the rate eps/(2 E_f) - nu k^2 > 0
+                if ((double)m2 >= md.kf_lo2 && (double)m2 <= md.kf_hi2) {
+                    n0 = n0 + cscale(u[0], ffac);
+                    n1 = n1 + cscale(u[1], ffac);
+                    n2 = n2 + cscale(u[2], ffac);
+                }
                 const P ik2 = P(1) / k2;
                 Cx<P> kn = cscale(n0, kxv) + cscale(n1, kyv) + cscale(n2, kzv);
                 g[0] = n0 - cscale(kn, kxv * ik2);
                 g[1] = n1 - cscale(kn, kyv * ik2);
                 g[2] = n2 - cscale(kn, kzv * ik2);
-                if ((double)m2 >= md.kf_lo2 && (double)m2 <= md.kf_hi2) {
-#pragma unroll
-                    for (int c = 0; c < 3; c++) g[c] = g[c] + cscale(u[c], ffac);
-                }
             }
             if (md.visc_mode == 1) {
 #pragma unroll

@@ -21,6 +21,7 @@ statistics runs in the library; this module only schedules calls.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import math
 import sys
@@ -54,22 +55,60 @@ def _scales(members):
     return out
 
 
+def refine_members(E, members, lam_min: float):
+    """Replace every member with lambda >= lam_min by a member on twice its grid
+    that takes over its field (the paper reruns its lambda >= 3.2 members at
+    twice the resolution, section "Extrapolating to the frontier of current
+    turbulence simulations").  Returns the new member list (same order); the
+    replaced members stay in the context, unused."""
+    out = []
+    for m in members:
+        if m.spec.lam >= lam_min:
+            m2 = E.add_member(dataclasses.replace(m.spec, n=2 * m.spec.n))
+            m2.refine_from(m)
+            out.append(m2)
+        else:
+            out.append(m)
+    return out
+
+
 def run(E, members, transient: float, measure: float, snaps_per_T: float, chunk: int = 50, log=print,
         c: float = 0.023, zs=(0.0, 0.25, math.log(2), 1.0, math.log(4), 1.75, math.log(8)),
-        rlambda_refs=(103.0, 173.0, 261.0), max_steps: int = 10 ** 7):
-    """Run transient and measurement; returns the result dictionary."""
+        rlambda_refs=(103.0, 173.0, 261.0), max_steps: int = 10 ** 7, refine_lambda: float | None = None,
+        refine_transient: float = 1.0):
+    """Run transient and measurement; returns the result dictionary.  With
+    `refine_lambda`, the members with lambda >= refine_lambda move to twice
+    their grid after the transient and run `refine_transient` more of their
+    integral times before the measurement."""
     t_start = time.perf_counter()
     steps = 0
+    members = list(members)
     central = min(members, key=lambda m: abs(m.spec.lam))
     # transient: every member runs `transient` of its own integral times
     while True:
-        E.step(chunk)
+        E.step(chunk, members=members)
         steps += chunk
         sc = _scales(members)
         prog = min((t / T if T > 0 else 0.0) for t, T in sc)
         log(f"transient: step {steps}, slowest member at {prog:.2f} T, {time.perf_counter() - t_start:.0f} s")
         if prog >= transient or steps >= max_steps:
             break
+    refined, refined_at = [], None
+    if refine_lambda is not None:
+        refined_at = steps
+        members = refine_members(E, members, refine_lambda)
+        refined = [k for k, m in enumerate(members) if m.spec.lam >= refine_lambda]
+        t_ref = {k: t for k, (t, _) in zip(range(len(members)), _scales(members)) if k in refined}
+        log(f"refined {len(refined)} members with lambda >= {refine_lambda} onto twice their grid")
+        while refined:
+            E.step(chunk, members=members)
+            steps += chunk
+            sc = _scales(members)
+            prog = min(((sc[k][0] - t_ref[k]) / sc[k][1] if sc[k][1] > 0 else 0.0) for k in refined)
+            log(f"refined transient: step {steps}, slowest refined member at {prog:.2f} T, "
+                f"{time.perf_counter() - t_start:.0f} s")
+            if prog >= refine_transient or steps >= max_steps:
+                break
     # steps per integral time (median over members) sets the snapshot interval
     rates = sorted(T / d for d, (t, T) in ((m.diag()["dt"], s) for m, s in zip(members, sc)) if d > 0 and T > 0)
     if not rates:
@@ -84,9 +123,9 @@ def run(E, members, transient: float, measure: float, snaps_per_T: float, chunk:
     e_central = []
     m_steps = 0
     while True:
-        E.step(every)
+        E.step(every, members=members)
         m_steps += every
-        E.accumulate_stats()
+        E.accumulate_stats(members=members)
         sc = _scales(members)
         nsnap += 1
         for k, (_, T) in enumerate(sc):
@@ -100,7 +139,8 @@ def run(E, members, transient: float, measure: float, snaps_per_T: float, chunk:
             break
     wall = time.perf_counter() - t_start
     res = {"steps": steps + m_steps, "transient_steps": steps, "snapshot_every": every, "snapshots": nsnap,
-           "wall_s": wall}
+           "wall_s": wall, "refined_members": refined,
+           "refined_at_step": refined_at}
     gap = E.scale_gap(rlambda_refs[0], members=members)
     res["rlambda_prefactor"] = gap["prefactor"]
     res["scale_gap"] = {str(r): E.scale_gap(r, members=members)["Z"] for r in rlambda_refs}
@@ -141,6 +181,10 @@ def main(argv=None):
     ap.add_argument("--measure", type=float, default=18.0, help="integral times measured")
     ap.add_argument("--snaps-per-T", type=float, default=10.0)
     ap.add_argument("--chunk", type=int, default=100)
+    ap.add_argument("--refine-lambda", type=float, default=None,
+                    help="after the transient, move the members with lambda >= this onto twice their grid")
+    ap.add_argument("--refine-transient", type=float, default=1.0,
+                    help="integral times the refined members run before the measurement")
     ap.add_argument("--out", required=True)
     a = ap.parse_args(argv)
     import torch
@@ -151,10 +195,11 @@ def main(argv=None):
     E.autotune()
     torch.cuda.synchronize()
     res = run(E, members, a.transient, a.measure, a.snaps_per_T, a.chunk,
-              log=lambda s: print(s, flush=True))
+              log=lambda s: print(s, flush=True), refine_lambda=a.refine_lambda,
+              refine_transient=a.refine_transient)
     res["config"] = {"n": a.n, "precision": a.precision, "members": len(specs), "nu": specs[0].nu,
                      "lambda": [s.lam for s in specs], "band": [1.4, 2.3], "cfl": 0.2}
-    diverged = [m.id for m in members if m.diag()["diverged"]]
+    diverged = [m.id for m in E.members if m.diag()["diverged"]]
     res["diverged"] = diverged
     E.close()
     with open(a.out, "w") as f:

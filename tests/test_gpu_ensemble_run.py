@@ -58,3 +58,33 @@ def test_small_ensemble_run_is_self_consistent(orc):
         s = float(np.sum(res["pdf_Z_ln4"][name]) * width)
         assert 0.99 < s <= 1.0 + 1e-12
     E.close()
+
+
+def test_small_ensemble_run_with_refined_members():
+    """The largest-lambda members move onto twice their grid after the
+    transient, run on there, and are measured and mixed on the finer grid."""
+    import paper_2506_23712_amd as ens
+    from paper_2506_23712_amd import run_ensemble as rd
+    specs = rd.ens128_specs(ens, n=32, precision="fp64", i_lo=-2, i_hi=3)
+    E = ens.Ensemble(hist=rd.hist_spec(ens, specs[0].nu))
+    members = [E.add_member(s) for s in specs]
+    res = rd.run(E, members, transient=0.5, measure=1.0, snaps_per_T=5, chunk=20, log=print,
+                 refine_lambda=0.4, refine_transient=0.25)
+    assert res["refined_members"] == [4, 5]
+    assert [r["n"] for r in res["members"]] == [32, 32, 32, 32, 64, 64]
+    assert [r["lambda"] for r in res["members"]] == [s.lam for s in specs]
+    assert len(E.members) == 8                                     # the two replaced members stay, unused
+    assert not any(m.diag()["diverged"] for m in E.members)
+    assert all(r["measured_T"] >= 1.0 for r in res["members"])
+    fine = E.members[6:]
+    for m in fine:
+        _, mom, npts = m.stats()
+        assert m.spec.n == 64 and npts == 64 ** 3 * res["snapshots"]
+        assert mom.numpy()[28] == res["snapshots"]
+    # the coarse originals stopped at the end of the transient
+    assert 0 < res["refined_at_step"] < res["transient_steps"]
+    assert all(E.members[k].diag()["step"] == res["refined_at_step"] for k in (4, 5))
+    assert all(E.members[k].diag()["step"] == res["steps"] for k in (0, 1, 2, 3))
+    for p in res["predictions"]:
+        assert abs(p["weight_sum"] - 1.0) < 1e-13
+    E.close()

@@ -145,6 +145,52 @@ def test_forcing_injects_exactly_eps(orc, band):
     assert np.max(np.abs(g - (0.37 / (2 * Ef)) * u * inband)) <= 1e-15
 
 
+def test_forcing_is_projected_like_the_nonlinear_term(orc):
+    """A solenoidal field plus a gradient field: the forcing acts on the
+    solenoidal part only (the pressure takes the divergent part), with E_f of
+    the whole field; a divergent part in the band is not amplified."""
+    n = 16
+    us = _random_field(orc, n, 5)
+    mz, my, mx = orc.modes(n)
+    rng = np.random.default_rng(6)
+    phi = rng.standard_normal(mx.shape) + 1j * rng.standard_normal(mx.shape)
+    m2 = mz * mz + my * my + mx * mx
+    inband = (m2 > 0) & (m2 <= 4)
+    phi = phi * inband * 0.1
+    phi[:, :, 0] = 0                                  # keep it away from the self-conjugate plane
+    ug = np.stack([1j * mx * phi, 1j * my * phi, 1j * mz * phi])
+    m = orc.Member(n=n, nu=0.0, eps=0.5, kf_lo=0.0, kf_hi=2.0)
+    g, info = orc.rhs(m, us + ug, terms=orc.T_FORCING)
+    w = np.ones(n // 2 + 1); w[1:] = 2
+    Ef = 0.5 * float(np.sum(np.sum(np.abs(us + ug) ** 2, axis=0) * inband * w))
+    assert abs(info[0] - Ef) <= 1e-14 * Ef
+    assert np.max(np.abs(g - (0.5 / (2 * Ef)) * us * inband)) <= 1e-15
+    assert orc.divergence_ratio(g) <= 1e-15
+    g0, _ = orc.rhs(m, ug, terms=orc.T_FORCING)
+    assert np.max(np.abs(g0)) <= 1e-15 * np.max(np.abs(ug))
+
+
+def test_forcing_acts_on_the_hermitian_part_of_the_m_x_0_plane(orc):
+    """The velocity is real: u(0, -m_y, -m_z) = conj u(0, m_y, m_z) on the
+    m_x = 0 plane of the half spectrum.  A part breaking that (here i r added
+    at both modes of a pair) is invisible in physical space; the forcing and
+    E_f ignore it, so it is not amplified."""
+    n = 16
+    u = _random_field(orc, n, 8)
+    m = orc.Member(n=n, nu=0.0, eps=0.5, kf_lo=1.4, kf_hi=2.3)
+    g, info = orc.rhs(m, u, terms=orc.T_FORCING)
+    v = u.copy()
+    for (my, mz), r in (((1, 1), (0.3, -0.2, 0.1)), ((2, 0), (0.0, 0.25, -0.4)), ((-1, 2), (0.1, 0.1, 0.2))):
+        for c in range(3):
+            v[c, mz % n, my % n, 0] += 1j * r[c]
+            v[c, (-mz) % n, (-my) % n, 0] += 1j * r[c]
+    gv, iv = orc.rhs(m, v, terms=orc.T_FORCING)
+    assert abs(iv[0] - info[0]) <= 1e-15 * info[0]
+    assert np.max(np.abs(gv - g)) <= 1e-15
+    # the injection rate stays eps exactly
+    assert abs(iv[1] - 0.5) <= 1e-14
+
+
 def test_forcing_with_empty_band_energy_is_zero(orc):
     n = 16
     u = np.zeros((3, n, n, n // 2 + 1), complex)
