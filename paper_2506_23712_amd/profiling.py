@@ -127,11 +127,30 @@ def traffic(copy_fetch: str, copy_write: str, copy_bytes: int, fetch: str, write
             "kernels": kernels}
 
 
-def write_summary(n: int, counts, out: str) -> None:
+def trace_averages(path: str) -> dict:
+    """kernel -> average duration (us) from a kernel-statistics table written
+    by ``stats`` (rows ``| `kernel` | calls | total us | average us | % |``)."""
+    out = {}
+    with open(path) as f:
+        for line in f:
+            m = re.match(r"\|\s*`([^`]+)`\s*\|\s*(\d+)\s*\|\s*([\d.]+)\s*\|\s*([\d.]+)\s*\|", line)
+            if m:
+                out[m.group(1)] = float(m.group(4))
+    return out
+
+
+PEAK_GBS = 8000.0
+
+
+def write_summary(n: int, counts, out: str, trace: str | None = None) -> None:
     """Markdown table: measured HBM bytes per launch (profiles/traffic_*.json)
-    against the algorithmic bytes of each pass, for the n^3 kernels."""
+    against the algorithmic bytes of each pass, for the n^3 kernels; with a
+    kernel-statistics table of the same kernel sources, each kernel's
+    achieved HBM rate (measured and algorithmic bytes over its average
+    duration) against the MI355X peak."""
     rows = []
     prof = os.path.join(os.path.dirname(HERE), "profiles")
+    avg = trace_averages(trace) if trace else {}
     for (wl, prec), cnt in zip((("single256_fp64", "fp64"), ("ens96_mixed_fp32", "fp32")), counts):
         path = os.path.join(prof, f"traffic_{wl}.json")
         t = json.load(open(path))
@@ -149,11 +168,15 @@ def write_summary(n: int, counts, out: str) -> None:
                 if f", {n}" not in short or ("float" in short) != (prec == "fp32"):
                     continue
                 ar, aw = rw[k][0] * cs * cnt, rw[k][1] * cs * cnt
+                us = avg.get(name)
                 rows.append((wl, short, ar / 1e9, aw / 1e9, v["fetch_bytes"] / 1e9, v["write_bytes"] / 1e9,
-                             (v["fetch_bytes"] + v["write_bytes"]) / (ar + aw), t["source_hash"]))
+                             (v["fetch_bytes"] + v["write_bytes"]) / (ar + aw), t["source_hash"], us,
+                             (v["fetch_bytes"] + v["write_bytes"]) / (us * 1e3) if us else None,
+                             (ar + aw) / (us * 1e3) if us else None))
     with open(out, "w") as f:
         f.write(f"# HBM traffic per launch vs algorithmic bytes ({n}^3 members)\n\n")
         f.write("Made by `python -m paper_2506_23712_amd.profiling summary --out " + os.path.relpath(out, os.path.dirname(HERE))
+                + (" --trace " + os.path.relpath(trace, os.path.dirname(HERE)) if trace else "")
                 + "` from `profiles/traffic_single256_fp64.json` and `profiles/traffic_ens96_mixed_fp32.json` "
                   "(their commands are recorded inside).  Counters: FETCH_SIZE and WRITE_SIZE (rocprofv3 `--pmc`, one "
                   "counter per run), KiB per dispatch, scaled by what the same counter reads for a plain 1 GiB device "
@@ -161,10 +184,17 @@ def write_summary(n: int, counts, out: str) -> None:
                   "without line padding (the `zfwd_update` read and write average the three RK stages).  The measured bytes "
                   "include the zero pad entries that the z/y passes write so that every store covers whole 128-byte "
                   "lines (FP32 rows of 86 complex values padded to 96, FP64 to 88).\n\n")
-        f.write("| workload | kernel | algorithmic read / write GB | measured read / write GB | measured / algorithmic | kernel source hash |\n")
-        f.write("|---|---|---|---|---|---|\n")
+        if trace:
+            f.write("Durations: kernel-trace averages from `" + os.path.relpath(trace, os.path.dirname(HERE)) +
+                    "` (same kernel sources; averages include the autotuner's launches of each variant).  "
+                    f"Rates against the MI355X HBM peak of {PEAK_GBS:.0f} GB/s.\n\n")
+        f.write("| workload | kernel | algorithmic read / write GB | measured read / write GB | measured / algorithmic |"
+                " average us | measured GB/s (frac) | algorithmic GB/s (frac) | kernel source hash |\n")
+        f.write("|---|---|---|---|---|---|---|---|---|\n")
         for r in rows:
-            f.write(f"| {r[0]} | `{r[1]}` | {r[2]:.3f} / {r[3]:.3f} | {r[4]:.3f} / {r[5]:.3f} | {r[6]:.2f} | `{r[7]}` |\n")
+            rate = (f"{r[8]:.1f} | {r[9]:.0f} ({r[9] / PEAK_GBS:.2f}) | {r[10]:.0f} ({r[10] / PEAK_GBS:.2f})"
+                    if r[8] else "— | — | —")
+            f.write(f"| {r[0]} | `{r[1]}` | {r[2]:.3f} / {r[3]:.3f} | {r[4]:.3f} / {r[5]:.3f} | {r[6]:.2f} | {rate} | `{r[7]}` |\n")
 
 
 def main(argv=None):
@@ -185,10 +215,12 @@ def main(argv=None):
     m.add_argument("--n", type=int, default=256)
     m.add_argument("--counts", type=int, nargs=2, default=(1, 25), metavar=("FP64", "FP32"),
                    help="members of that size per launch in the two workloads")
+    m.add_argument("--trace", default=None,
+                   help="kernel-statistics table (from `stats`) of the same kernel sources, for the rate columns")
     m.add_argument("--out", required=True)
     a = ap.parse_args(argv)
     if a.cmd == "summary":
-        write_summary(a.n, a.counts, a.out)
+        write_summary(a.n, a.counts, a.out, a.trace)
         return
     if a.cmd == "stats":
         rows = kernel_stats(a.db)[: a.top]

@@ -38,3 +38,19 @@ def test_kernel_names_exist_in_the_sources():
     assert p.kernel_name("xpass", 256, "fp64", 3).endswith(", 8>")   # FP64 falls back to 8 values per thread
     assert p.kernel_name("xpass", 32, "fp32", 2) == "ens::k_xpass<float, 32, 8>"
 
+
+
+def test_trace_averages_read_the_committed_kernel_table():
+    """The rate columns of the traffic summary take each kernel's average
+    duration from the committed kernel-statistics table."""
+    from paper_2506_23712_amd import profiling as p
+    path = os.path.join(ROOT, "profiles", "ens96_mixed_fp32_and_single256_fp64_kernel_stats.md")
+    avg = p.trace_averages(path)
+    assert "ens::k_xpass_dma<float, 256, 16>" in avg
+    rows = [l for l in open(path) if l.startswith("| `")]
+    assert len(avg) == len(rows)
+    for l in rows:
+        cells = [c.strip() for c in l.strip().strip("|").split("|")]
+        name = cells[0].strip("`")
+        assert avg[name] == float(cells[3])
+        assert abs(float(cells[2]) - int(cells[1]) * float(cells[3])) <= 0.01 * float(cells[2]) + 1
