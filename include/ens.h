@@ -231,6 +231,32 @@ ens_status ens_get_stats(ens_ctx *ctx, int32_t m, uint64_t *counts, double *mome
 /* Zero member m's statistics (asynchronous on `stream`). */
 ens_status ens_reset_stats(ens_ctx *ctx, int32_t m, void *stream);
 
+/* ------------------------------------------------------------ checkpointing */
+
+/* Members run for tens of integral times after their transient (section
+ * "Description of the ensemble simulations"), which a long run may have to
+ * split over several processes.  A member's checkpoint at a step boundary is
+ * its velocity (ens_member_get_state), its ens_diag record (ens_get_diag:
+ * time, step count, last dt, diagnostics, flags) and its statistics sums
+ * (ens_get_stats).  Restored into a member of the same descriptor, in a
+ * context of the same histogram descriptor, with ens_member_set_state and the
+ * two calls below, the member continues bitwise as the uninterrupted run
+ * would: between steps the RK register holds nothing the next step reads,
+ * and the band energy and the CFL velocity are recomputed by that step. */
+
+/* Restore member m's clock and diagnostics from a record `d` that
+ * ens_get_diag returned.  Refuses (ENS_E_INVALID, nothing written) a record
+ * with a negative or non-finite time, a negative step count or reserved != 0.
+ * Host record; returns after the copy has completed on `stream`. */
+ens_status ens_member_set_diag(ens_ctx *ctx, int32_t m, const ens_diag *d, void *stream);
+
+/* Replace member m's statistics sums with host arrays as ens_get_stats
+ * returns them: `counts` (ens_stats_len entries) and `moments` (ENS_NMOM
+ * entries); either may be NULL to keep that part.  Needs a histogram
+ * descriptor (ENS_E_STATE otherwise).  Returns after the copies have
+ * completed on `stream`. */
+ens_status ens_set_stats(ens_ctx *ctx, int32_t m, const uint64_t *counts, const double *moments, void *stream);
+
 /* ------------------------------------------------------------------ mixture */
 
 /* Mix the statistics of `count` members with Gaussian weights in lambda

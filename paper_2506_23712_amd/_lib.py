@@ -17,6 +17,7 @@ PASS_NAMES = ("band", "zinv", "yinv", "xpass", "yfwd", "zfwd_update", "end_step"
 EXPORTS = ("ens_create", "ens_destroy", "ens_last_error", "ens_set_graphs", "ens_member_workspace_bytes",
            "ens_member_init", "ens_member_set_state", "ens_member_get_state", "ens_step", "ens_profile_step",
            "ens_get_diag", "ens_accumulate_stats", "ens_stats_len", "ens_get_stats", "ens_reset_stats",
+           "ens_member_set_diag", "ens_set_stats",
            "ens_mix_len", "ens_mix", "ens_mix_table", "ens_lambda_pdf_from_cf", "ens_scale_gap", "ens_spectrum", "ens_integral_scales", "ens_member_refine",
            "ens_fft_pencils", "ens_autotune", "ens_set_variant", "ens_get_variant")
 
@@ -80,6 +81,8 @@ def lib() -> ctypes.CDLL:
         "ens_stats_len": [vp, P(sz)],
         "ens_get_stats": [vp, i32, P(ctypes.c_uint64), P(dp), P(ctypes.c_uint64)],
         "ens_reset_stats": [vp, i32, vp],
+        "ens_member_set_diag": [vp, i32, P(Diag), vp],
+        "ens_set_stats": [vp, i32, P(ctypes.c_uint64), P(dp), vp],
         "ens_mix_len": [vp, i32, P(sz)],
         "ens_mix": [vp, P(i32), i32, dp, dp, i32, dp, vp, vp],
         "ens_mix_table": [vp, P(i32), i32, vp, i32, dp, dp, vp, vp],

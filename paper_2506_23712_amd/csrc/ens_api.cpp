@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <fstream>
@@ -624,6 +625,42 @@ ENS_API ens_status ens_get_stats(ens_ctx *ctx, int32_t mid, uint64_t *counts, do
         for (long long i = 0; i < ctx->hg.off_le; i++) s += c[i];
         *n_points = s;
     }
+    return ENS_OK;
+}
+
+static_assert(offsetof(DevState, diag) == 0, "ens_member_set_diag writes the record at the start of DevState");
+
+ENS_API ens_status ens_member_set_diag(ens_ctx *ctx, int32_t mid, const ens_diag *d, void *stream) {
+    if (ens_status st = check_ctx(ctx)) return st;
+    Member *m;
+    if (ens_status st = member_of(ctx, mid, &m)) return st;
+    if (!d) return fail(ENS_E_INVALID, "null diagnostics record");
+    if (!(d->t >= 0.0) || !std::isfinite(d->t)) return fail(ENS_E_INVALID, "time must be finite and >= 0");
+    if (d->step < 0) return fail(ENS_E_INVALID, "step count must be >= 0");
+    if (d->reserved != 0) return fail(ENS_E_INVALID, "reserved must be 0");
+    HIPCK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    const ens_diag rec = *d;
+    // DevState begins with the ens_diag record
+    HIPCK(ctx, hipMemcpyAsync(m->md.st, &rec, sizeof(ens_diag), hipMemcpyHostToDevice, s));
+    HIPCK(ctx, hipStreamSynchronize(s));
+    m->last = s;
+    return ENS_OK;
+}
+
+ENS_API ens_status ens_set_stats(ens_ctx *ctx, int32_t mid, const uint64_t *counts, const double *moments, void *stream) {
+    if (ens_status st = check_ctx(ctx)) return st;
+    if (!ctx->has_hist) return fail(ENS_E_STATE, "context has no histogram descriptor");
+    Member *m;
+    if (ens_status st = member_of(ctx, mid, &m)) return st;
+    HIPCK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    if (counts)
+        HIPCK(ctx, hipMemcpyAsync(m->md.counts, counts, ctx->hg.n_counts * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+    if (moments)
+        HIPCK(ctx, hipMemcpyAsync(m->md.moments, moments, ENS_NMOM * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCK(ctx, hipStreamSynchronize(s));
+    m->last = s;
     return ENS_OK;
 }
 

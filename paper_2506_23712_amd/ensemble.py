@@ -132,6 +132,39 @@ class Member:
     def reset_stats(self) -> None:
         check(lib().ens_reset_stats(self.ens.ctx, self.id, _stream_ptr()))
 
+    # ------------------------------------------------------------ checkpoints
+    def checkpoint(self) -> dict:
+        """Host copy of everything the member carries between steps: velocity
+        (canonical layout, complex128), the diagnostics record (time, step
+        count, ...) and, with a histogram descriptor, the statistics sums."""
+        d = _lib.Diag()
+        st = lib().ens_get_diag(self.ens.ctx, self.id, ctypes.byref(d))
+        if st not in (_lib.ENS_OK, _lib.ENS_E_DIVERGED):
+            check(st)
+        out = {"state": self.state().cpu().numpy(), "diag": bytes(d)}
+        if self.ens.hist is not None:
+            counts, mom, _ = self.stats()
+            out["counts"] = counts.numpy().astype("uint64")
+            out["moments"] = mom.numpy()
+        return out
+
+    def restore(self, ck: dict) -> None:
+        """Continue from `checkpoint()` output of a member of the same spec."""
+        import numpy as np
+        self.set_state(torch.from_numpy(np.asarray(ck["state"])))
+        d = _lib.Diag.from_buffer_copy(bytes(ck["diag"]))
+        check(lib().ens_member_set_diag(self.ens.ctx, self.id, ctypes.byref(d), _stream_ptr()))
+        if "counts" in ck and self.ens.hist is not None:
+            counts = np.ascontiguousarray(ck["counts"], dtype=np.uint64)
+            mom = np.ascontiguousarray(ck["moments"], dtype=np.float64)
+            n = ctypes.c_size_t()
+            check(lib().ens_stats_len(self.ens.ctx, ctypes.byref(n)))
+            if counts.size != n.value or mom.size != _lib.ENS_NMOM:
+                raise ValueError("statistics of the checkpoint do not match this context's histograms")
+            check(lib().ens_set_stats(self.ens.ctx, self.id,
+                                      counts.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                      mom.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream_ptr()))
+
     def spectrum(self, nshell: int | None = None) -> torch.Tensor:
         """Shell energy spectrum E[s], s = 0 .. nshell-1 (float64 on the device);
         by default every shell that holds retained modes."""
@@ -192,6 +225,50 @@ class Ensemble:
         m = Member(self, spec, mid.value, ws)
         self.members.append(m)
         return m
+
+    # ------------------------------------------------------------ checkpoints
+    def save_checkpoint(self, path: str, members=None) -> None:
+        """Write the members' checkpoints, their specs and the histogram spec to
+        one .npz file (plain arrays and JSON text; nothing pickled)."""
+        import dataclasses
+        import json
+        import numpy as np
+        ms = members if members is not None else self.members
+        # the kernel variants in use: results are bitwise only under the same ones
+        arrays = {"specs": np.array(json.dumps([dataclasses.asdict(m.spec) for m in ms])),
+                  "hist": np.array(json.dumps(dataclasses.asdict(self.hist) if self.hist is not None else None)),
+                  "variants": np.array(json.dumps(self.variants(ms)))}
+        for k, m in enumerate(ms):
+            ck = m.checkpoint()
+            arrays[f"m{k}_state"] = ck["state"]
+            arrays[f"m{k}_diag"] = np.frombuffer(ck["diag"], dtype=np.uint8)
+            if "counts" in ck:
+                arrays[f"m{k}_counts"] = ck["counts"]
+                arrays[f"m{k}_moments"] = ck["moments"]
+        np.savez(path, **arrays)
+
+    @classmethod
+    def load_checkpoint(cls, path: str, device: int = 0, graphs: bool = True):
+        """New context and members from `save_checkpoint` output; returns
+        (ensemble, members in the saved order)."""
+        import json
+        import numpy as np
+        with np.load(path, allow_pickle=False) as z:
+            specs = [MemberSpec(**s) for s in json.loads(str(z["specs"]))]
+            h = json.loads(str(z["hist"]))
+            E = cls(hist=HistSpec(**h) if h is not None else None, device=device, graphs=graphs)
+            for key, v in json.loads(str(z["variants"])).items():
+                pass_name, n, prec = key.split(":")
+                E.set_variant(pass_name, int(n), prec, int(v))
+            ms = []
+            for k, spec in enumerate(specs):
+                m = E.add_member(spec)
+                ck = {"state": z[f"m{k}_state"], "diag": z[f"m{k}_diag"].tobytes()}
+                if f"m{k}_counts" in z:
+                    ck["counts"], ck["moments"] = z[f"m{k}_counts"], z[f"m{k}_moments"]
+                m.restore(ck)
+                ms.append(m)
+        return E, ms
 
     # ----------------------------------------------------------------- stepping
     def step(self, nsteps: int = 1, members=None) -> None:

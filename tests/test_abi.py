@@ -53,6 +53,8 @@ def test_argument_validation_without_a_gpu(L):
     assert L.ens_mix_table(None, None, 0, None, 64, 0.0, 0.1, None, None) == _lib.ENS_E_INVALID
     assert L.ens_scale_gap(None, None, 0, 100.0, None, None, None) == _lib.ENS_E_INVALID
     assert L.ens_member_refine(None, 0, 1, None) == _lib.ENS_E_INVALID
+    assert L.ens_member_set_diag(None, 0, None, None) == _lib.ENS_E_INVALID
+    assert L.ens_set_stats(None, 0, None, None, None) == _lib.ENS_E_INVALID
     ctx = ctypes.c_void_p()
     bad = _lib.HistDesc(0, -1, 1, -1, 1, 8, -1, 1, 8, -1, 1, 1.0, 1.0)
     assert L.ens_create(ctypes.byref(ctx), 0, ctypes.byref(bad)) == _lib.ENS_E_INVALID
