@@ -46,12 +46,21 @@ def hist_spec(ens, nu: float):
                         log10_hi=5.0, a_bins=2048, a_lo=-120.0, a_hi=120.0, eps_ref=1.0, nu_ref=nu)
 
 
-def _scales(members):
-    """(t, T) of every member: its time and current integral time."""
-    out = []
+def _scales(members, record=None, phase="", steps=0):
+    """(t, T) of every member: its time and current integral time.  With
+    `record` (a text file), one JSON line of every member's diagnostics."""
+    out, rows = [], []
     for m in members:
         T = float(m.integral_scales()[3].item())
-        out.append((m.diag()["t"], T))
+        d = m.diag()
+        out.append((d["t"], T))
+        if record is not None:
+            rows.append({"lambda": m.spec.lam, "n": m.spec.n, "t": d["t"], "dt": d["dt"], "E": d["E"], "D": d["D"],
+                         "E_f": d["E_f"], "cfl": d["cfl"], "rlambda": d["rlambda"], "kmax_eta": d["kmax_eta"], "T": T,
+                         "diverged": d["diverged"]})
+    if record is not None:
+        record.write(json.dumps({"phase": phase, "steps": steps, "members": rows}) + "\n")
+        record.flush()
     return out
 
 
@@ -75,11 +84,12 @@ def refine_members(E, members, lam_min: float):
 def run(E, members, transient: float, measure: float, snaps_per_T: float, chunk: int = 50, log=print,
         c: float = 0.023, zs=(0.0, 0.25, math.log(2), 1.0, math.log(4), 1.75, math.log(8)),
         rlambda_refs=(103.0, 173.0, 261.0), max_steps: int = 10 ** 7, refine_lambda: float | None = None,
-        refine_transient: float = 1.0):
+        refine_transient: float = 1.0, record=None):
     """Run transient and measurement; returns the result dictionary.  With
     `refine_lambda`, the members with lambda >= refine_lambda move to twice
     their grid after the transient and run `refine_transient` more of their
-    integral times before the measurement."""
+    integral times before the measurement.  `record` (a text file) receives one
+    JSON line of all members' diagnostics per check."""
     t_start = time.perf_counter()
     steps = 0
     members = list(members)
@@ -88,7 +98,7 @@ def run(E, members, transient: float, measure: float, snaps_per_T: float, chunk:
     while True:
         E.step(chunk, members=members)
         steps += chunk
-        sc = _scales(members)
+        sc = _scales(members, record, "transient", steps)
         prog = min((t / T if T > 0 else 0.0) for t, T in sc)
         log(f"transient: step {steps}, slowest member at {prog:.2f} T, {time.perf_counter() - t_start:.0f} s")
         if prog >= transient or steps >= max_steps:
@@ -103,7 +113,7 @@ def run(E, members, transient: float, measure: float, snaps_per_T: float, chunk:
         while refined:
             E.step(chunk, members=members)
             steps += chunk
-            sc = _scales(members)
+            sc = _scales(members, record, "refined transient", steps)
             prog = min(((sc[k][0] - t_ref[k]) / sc[k][1] if sc[k][1] > 0 else 0.0) for k in refined)
             log(f"refined transient: step {steps}, slowest refined member at {prog:.2f} T, "
                 f"{time.perf_counter() - t_start:.0f} s")
@@ -126,7 +136,7 @@ def run(E, members, transient: float, measure: float, snaps_per_T: float, chunk:
         E.step(every, members=members)
         m_steps += every
         E.accumulate_stats(members=members)
-        sc = _scales(members)
+        sc = _scales(members, record, "measure", steps + m_steps)
         nsnap += 1
         for k, (_, T) in enumerate(sc):
             Tsum[k] += T
@@ -185,6 +195,7 @@ def main(argv=None):
                     help="after the transient, move the members with lambda >= this onto twice their grid")
     ap.add_argument("--refine-transient", type=float, default=1.0,
                     help="integral times the refined members run before the measurement")
+    ap.add_argument("--record", default=None, help="JSON-lines file of every member's diagnostics per check")
     ap.add_argument("--out", required=True)
     a = ap.parse_args(argv)
     import torch
@@ -194,9 +205,14 @@ def main(argv=None):
     members = [E.add_member(s) for s in specs]
     E.autotune()
     torch.cuda.synchronize()
-    res = run(E, members, a.transient, a.measure, a.snaps_per_T, a.chunk,
-              log=lambda s: print(s, flush=True), refine_lambda=a.refine_lambda,
-              refine_transient=a.refine_transient)
+    rec = open(a.record, "w") if a.record else None
+    try:
+        res = run(E, members, a.transient, a.measure, a.snaps_per_T, a.chunk,
+                  log=lambda s: print(s, flush=True), refine_lambda=a.refine_lambda,
+                  refine_transient=a.refine_transient, record=rec)
+    finally:
+        if rec is not None:
+            rec.close()
     res["config"] = {"n": a.n, "precision": a.precision, "members": len(specs), "nu": specs[0].nu,
                      "lambda": [s.lam for s in specs], "band": [1.4, 2.3], "cfl": 0.2}
     diverged = [m.id for m in E.members if m.diag()["diverged"]]

@@ -18,7 +18,16 @@ def test_small_ensemble_run_is_self_consistent(orc):
     assert abs((32 // 3) * (specs[0].nu ** 3) ** 0.25 - 3.0) < 1e-12          # k_M eta = 3 at eps = 1
     E = ens.Ensemble(hist=rd.hist_spec(ens, specs[0].nu))
     members = [E.add_member(s) for s in specs]
-    res = rd.run(E, members, transient=0.5, measure=1.0, snaps_per_T=5, chunk=20, log=print)
+    import io
+    import json
+    rec = io.StringIO()
+    res = rd.run(E, members, transient=0.5, measure=1.0, snaps_per_T=5, chunk=20, log=print, record=rec)
+    lines = [json.loads(x) for x in rec.getvalue().splitlines()]
+    assert [x["phase"] for x in lines].count("measure") == res["snapshots"]
+    assert lines[0]["phase"] == "transient" and lines[-1]["steps"] == res["steps"]
+    assert all(len(x["members"]) == len(members) for x in lines)
+    assert all(a["steps"] < b["steps"] for a, b in zip(lines, lines[1:]))
+    assert lines[-1]["members"][4]["t"] == members[4].diag()["t"]
     central = members[4]
     assert central.spec.lam == 0.0
     # every member measured at least one of its integral times, nothing diverged
