@@ -214,6 +214,21 @@ template <bool SB> __device__ __forceinline__ void stage_barrier() {
     else __syncthreads();
 }
 
+// LDS slot of (position p, line l) in the [position][line] layout of the
+// exchanges between stages.  When a row of T values covers only half of the
+// 32 banks (64 bytes: T = 8 complex FP32 or T = 4 complex FP64), the bank half
+// is set by the parity of p, and in the radix-16 exchanges whose lanes all
+// address positions 16 t + m of one parity an instruction would use half of
+// the banks (two-way conflicts).  Exchanging the two rows of each even/odd
+// pair in every other block of 16 positions (flipping bit 0 of p by bit 4)
+// spreads those over both halves; positions t + 16 m, whose parity already
+// varies across lanes, stay spread.  A bijection on positions: the
+// transforms compute the same values.
+template <typename P, int T> __device__ __forceinline__ int xslot(int p, int l) {
+    if constexpr (T * (int)sizeof(LdsT<P>) == 64) return (p ^ ((p >> 4) & 1)) * T + l;
+    else return p * T + l;
+}
+
 template <typename P> __device__ __forceinline__ void lds_put(LdsT<P> *lds, int i, Cx<P> v) {
     LdsT<P> x; x.x = v.re; x.y = v.im; lds[i] = x;
 }
@@ -230,7 +245,7 @@ __device__ __forceinline__ void stage_gather(Cx<P> *v, const LdsT<P> *lds, int l
         const int j = t + M * b, k = j % NS;
 #pragma unroll
         for (int m = 0; m < R; m++) {
-            Cx<P> x = lds_get<P>(lds, (j + m * (N / R)) * T + l);
+            Cx<P> x = lds_get<P>(lds, xslot<P, T>(j + m * (N / R), l));
             if (m > 0) x = cmul(x, tw_at<DIR, s>(tw, b, m, m * k * (N / (NS * R))));
             v[b * R + m] = x;
         }
@@ -246,7 +261,7 @@ __device__ __forceinline__ void stage_scatter(const Cx<P> *v, LdsT<P> *lds, int 
     for (int b = 0; b < E / R; b++) {
         const int j = t + M * b, k = j % NS;
 #pragma unroll
-        for (int m = 0; m < R; m++) lds_put<P>(lds, ((j / NS) * NS * R + k + m * NS) * T + l, v[b * R + m]);
+        for (int m = 0; m < R; m++) lds_put<P>(lds, xslot<P, T>((j / NS) * NS * R + k + m * NS, l), v[b * R + m]);
     }
 }
 
@@ -292,7 +307,7 @@ __device__ __forceinline__ void stageT_scatter(const Cx<P> *v, LdsT<P> *lds, int
     for (int b = 0; b < E / R; b++) {
         const int j = t + M * b;
 #pragma unroll
-        for (int m = 0; m < R; m++) lds_put<P>(lds, (j + m * (N / R)) * T + l, v[b * R + m]);
+        for (int m = 0; m < R; m++) lds_put<P>(lds, xslot<P, T>(j + m * (N / R), l), v[b * R + m]);
     }
 }
 // stage s (transposed) reads from its output positions
@@ -303,7 +318,7 @@ __device__ __forceinline__ void stageT_gather(Cx<P> *v, const LdsT<P> *lds, int 
     for (int b = 0; b < E / R; b++) {
         const int j = t + M * b, k = j % NS;
 #pragma unroll
-        for (int m = 0; m < R; m++) v[b * R + m] = lds_get<P>(lds, ((j / NS) * NS * R + k + m * NS) * T + l);
+        for (int m = 0; m < R; m++) v[b * R + m] = lds_get<P>(lds, xslot<P, T>((j / NS) * NS * R + k + m * NS, l));
     }
 }
 
