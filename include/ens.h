@@ -155,12 +155,17 @@ ens_status ens_member_get_state(ens_ctx *ctx, int32_t m, double *dev_uhat, void 
 /* Advance `count` members by `nsteps` steps of the low-storage integrating-
  * factor RK3 (Williamson 2N coefficients A = (0,-5/9,-153/128),
  * B = (1/3,15/16,8/15); q <- E_s (A_s q + dt G(u)), u <- E_s u + B_s q with
- * E_s = exp(-nu k^2 h_s dt), h = (1/3,5/12,1/4)).  G = P(u x omega) + f:
+ * E_s = exp(-nu k^2 h_s dt), h = (1/3,5/12,1/4)).  G = P(u x omega + f):
  * rotational nonlinear term by inverse transforms of u and omega = i k x u,
- * forward transform truncated to D, projection perpendicular to k; band
- * forcing f = eps_m / (2 E_f) u on the band with E_f its FP64 energy at the
- * stage (the paper's forcing amplifies band coefficients every step so that the
- * injection rate is fixed, section "Description of the ensemble simulations").
+ * forward transform truncated to D, band forcing f = eps_m / (2 E_f) u on the
+ * band with E_f its FP64 energy at the stage (the paper's forcing amplifies
+ * band coefficients every step so that the injection rate is fixed, section
+ * "Description of the ensemble simulations"), projection perpendicular to k
+ * of the sum.  The velocity is real and solenoidal; parts of the stored
+ * spectrum that are not (rounding) would be invisible to the nonlinear term
+ * and grow under the linear forcing, so the forcing is projected with the
+ * nonlinear term and, at every stage, the band's part of the m_x = 0 plane
+ * is made Hermitian in place before E_f is summed.
  * Members may differ in N and precision.  Device-side dt: members with dt <= 0
  * take the CFL step from their stage-1 field.  Asynchronous on `stream`. */
 ens_status ens_step(ens_ctx *ctx, const int32_t *members, int32_t count, int32_t nsteps,
