@@ -227,9 +227,10 @@ class Ensemble:
         return m
 
     # ------------------------------------------------------------ checkpoints
-    def save_checkpoint(self, path: str, members=None) -> None:
+    def save_checkpoint(self, path: str, members=None, extra: dict | None = None) -> None:
         """Write the members' checkpoints, their specs and the histogram spec to
-        one .npz file (plain arrays and JSON text; nothing pickled)."""
+        one .npz file (plain arrays and JSON text; nothing pickled); `extra`
+        (JSON-serialisable) is stored beside them for the caller."""
         import dataclasses
         import json
         import numpy as np
@@ -237,7 +238,8 @@ class Ensemble:
         # the kernel variants in use: results are bitwise only under the same ones
         arrays = {"specs": np.array(json.dumps([dataclasses.asdict(m.spec) for m in ms])),
                   "hist": np.array(json.dumps(dataclasses.asdict(self.hist) if self.hist is not None else None)),
-                  "variants": np.array(json.dumps(self.variants(ms)))}
+                  "variants": np.array(json.dumps(self.variants(ms))),
+                  "extra": np.array(json.dumps(extra))}
         for k, m in enumerate(ms):
             ck = m.checkpoint()
             arrays[f"m{k}_state"] = ck["state"]
@@ -246,6 +248,14 @@ class Ensemble:
                 arrays[f"m{k}_counts"] = ck["counts"]
                 arrays[f"m{k}_moments"] = ck["moments"]
         np.savez(path, **arrays)
+
+    @staticmethod
+    def read_checkpoint_extra(path: str):
+        """The `extra` object a checkpoint was written with (None if none)."""
+        import json
+        import numpy as np
+        with np.load(path, allow_pickle=False) as z:
+            return json.loads(str(z["extra"])) if "extra" in z.files else None
 
     @classmethod
     def load_checkpoint(cls, path: str, device: int = 0, graphs: bool = True):

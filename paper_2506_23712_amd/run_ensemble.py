@@ -31,13 +31,16 @@ LAMBDA_STEP = math.log(2) / 3
 
 
 def ens128_specs(ens, n: int = 128, precision: str = "fp64", i_lo: int = -22, i_hi: int = 25,
-                 kmeta: float = 3.0, cfl: float = 0.2, seed0: int = 23712):
+                 kmeta: float = 3.0, cfl: float = 0.2, seed0: int = 23712, box: float = 2 * math.pi):
     """Member specs: lambda_i = i ln2/3, eps = e^lambda, nu from k_M eta of the
-    central member (k_M = K dk, dk = 1, eps = 1: nu = (kmeta / K)^(4/3))."""
+    central member (k_M = K dk, dk = 2 pi / box, eps = 1:
+    nu = (kmeta / (K dk))^(4/3)).  The ens256 set of Table I is n = 256 in a
+    box of 4 pi (dk = 1/2), the band still [1.4, 2.3] dk."""
     K = n // 3
-    nu = (kmeta / K) ** (4.0 / 3.0)
+    dk = 2 * math.pi / box
+    nu = (kmeta / (K * dk)) ** (4.0 / 3.0)
     return [ens.MemberSpec(n=n, nu=nu, eps_ref=1.0, lam=i * LAMBDA_STEP, kf_lo=1.4, kf_hi=2.3, dt=0.0, cfl=cfl,
-                           precision=precision, seed=seed0 + (i - i_lo)) for i in range(i_lo, i_hi + 1)]
+                           precision=precision, seed=seed0 + (i - i_lo), box=box) for i in range(i_lo, i_hi + 1)]
 
 
 def hist_spec(ens, nu: float):
@@ -84,70 +87,100 @@ def refine_members(E, members, lam_min: float):
 def run(E, members, transient: float, measure: float, snaps_per_T: float, chunk: int = 50, log=print,
         c: float = 0.023, zs=(0.0, 0.25, math.log(2), 1.0, math.log(4), 1.75, math.log(8)),
         rlambda_refs=(103.0, 173.0, 261.0), max_steps: int = 10 ** 7, refine_lambda: float | None = None,
-        refine_transient: float = 1.0, record=None):
+        refine_transient: float = 1.0, record=None, state: dict | None = None, stop=None):
     """Run transient and measurement; returns the result dictionary.  With
     `refine_lambda`, the members with lambda >= refine_lambda move to twice
     their grid after the transient and run `refine_transient` more of their
     integral times before the measurement.  `record` (a text file) receives one
-    JSON line of all members' diagnostics per check."""
+    JSON line of all members' diagnostics per check.
+
+    The run can be split over processes: `stop()` is asked after every check
+    that does not end a phase; when it returns True the run returns
+    {"stopped": True, "state": ..., "members": ...} at that step boundary, and
+    a later call with the members restored from their checkpoint and
+    `state=` that state continues it exactly as if uninterrupted."""
     t_start = time.perf_counter()
-    steps = 0
     members = list(members)
     central = min(members, key=lambda m: abs(m.spec.lam))
+    st = dict(state) if state else {"phase": "transient", "steps": 0, "wall": 0.0}
+
+    def elapsed():
+        return st["wall"] + time.perf_counter() - t_start
+
+    def stopped():
+        out = dict(st)
+        out["wall"] = elapsed()
+        return {"stopped": True, "state": out, "members": members}
+
     # transient: every member runs `transient` of its own integral times
-    while True:
-        E.step(chunk, members=members)
-        steps += chunk
-        sc = _scales(members, record, "transient", steps)
-        prog = min((t / T if T > 0 else 0.0) for t, T in sc)
-        log(f"transient: step {steps}, slowest member at {prog:.2f} T, {time.perf_counter() - t_start:.0f} s")
-        if prog >= transient or steps >= max_steps:
-            break
-    refined, refined_at = [], None
-    if refine_lambda is not None:
-        refined_at = steps
+    if st["phase"] == "transient":
+        while True:
+            E.step(chunk, members=members)
+            st["steps"] += chunk
+            sc = _scales(members, record, "transient", st["steps"])
+            prog = min((t / T if T > 0 else 0.0) for t, T in sc)
+            log(f"transient: step {st['steps']}, slowest member at {prog:.2f} T, {elapsed():.0f} s")
+            if prog >= transient or st["steps"] >= max_steps:
+                st["phase"] = "refine" if refine_lambda is not None else "measure setup"
+                break
+            if stop is not None and stop():
+                return stopped()
+    if st["phase"] == "refine":
+        st["refined_at"] = st["steps"]
         members = refine_members(E, members, refine_lambda)
-        refined = [k for k, m in enumerate(members) if m.spec.lam >= refine_lambda]
-        t_ref = {k: t for k, (t, _) in zip(range(len(members)), _scales(members)) if k in refined}
-        log(f"refined {len(refined)} members with lambda >= {refine_lambda} onto twice their grid")
+        st["refined"] = [k for k, m in enumerate(members) if m.spec.lam >= refine_lambda]
+        sc = _scales(members)
+        st["t_ref"] = [sc[k][0] for k in st["refined"]]
+        log(f"refined {len(st['refined'])} members with lambda >= {refine_lambda} onto twice their grid")
+        st["phase"] = "refined transient"
+    if st["phase"] == "refined transient":
+        refined, t_ref = st["refined"], st["t_ref"]
         while refined:
             E.step(chunk, members=members)
-            steps += chunk
-            sc = _scales(members, record, "refined transient", steps)
-            prog = min(((sc[k][0] - t_ref[k]) / sc[k][1] if sc[k][1] > 0 else 0.0) for k in refined)
-            log(f"refined transient: step {steps}, slowest refined member at {prog:.2f} T, "
-                f"{time.perf_counter() - t_start:.0f} s")
-            if prog >= refine_transient or steps >= max_steps:
+            st["steps"] += chunk
+            sc = _scales(members, record, "refined transient", st["steps"])
+            prog = min(((sc[k][0] - t0) / sc[k][1] if sc[k][1] > 0 else 0.0) for k, t0 in zip(refined, t_ref))
+            log(f"refined transient: step {st['steps']}, slowest refined member at {prog:.2f} T, {elapsed():.0f} s")
+            if prog >= refine_transient or st["steps"] >= max_steps:
                 break
-    # steps per integral time (median over members) sets the snapshot interval
-    rates = sorted(T / d for d, (t, T) in ((m.diag()["dt"], s) for m, s in zip(members, sc)) if d > 0 and T > 0)
-    if not rates:
-        raise RuntimeError("no member has a positive time step and integral time after the transient")
-    per_T = rates[len(rates) // 2]
-    every = max(1, int(round(per_T / snaps_per_T)))
-    for m in members:
-        m.reset_stats()
-    t0 = [t for t, _ in sc]
-    Tsum = [0.0] * len(members)
-    nsnap = 0
-    e_central = []
-    m_steps = 0
-    while True:
+            if stop is not None and stop():
+                return stopped()
+        st["phase"] = "measure setup"
+    if st["phase"] == "measure setup":
+        # steps per integral time (median over members) sets the snapshot interval
+        sc = _scales(members)
+        rates = sorted(T / d for d, (t, T) in ((m.diag()["dt"], s) for m, s in zip(members, sc)) if d > 0 and T > 0)
+        if not rates:
+            raise RuntimeError("no member has a positive time step and integral time after the transient")
+        per_T = rates[len(rates) // 2]
+        st["every"] = max(1, int(round(per_T / snaps_per_T)))
+        for m in members:
+            m.reset_stats()
+        st.update(t0=[t for t, _ in sc], Tsum=[0.0] * len(members), nsnap=0, e_central=[], m_steps=0,
+                  phase="measure")
+    every, t0, Tsum, e_central = st["every"], st["t0"], st["Tsum"], st["e_central"]
+    steps = st["steps"]
+    while st["phase"] == "measure":
         E.step(every, members=members)
-        m_steps += every
+        st["m_steps"] += every
         E.accumulate_stats(members=members)
-        sc = _scales(members, record, "measure", steps + m_steps)
-        nsnap += 1
+        sc = _scales(members, record, "measure", steps + st["m_steps"])
+        st["nsnap"] += 1
+        nsnap = st["nsnap"]
         for k, (_, T) in enumerate(sc):
             Tsum[k] += T
         e_central.append(central.diag()["E"])
         prog = min(((t - t0[k]) / (Tsum[k] / nsnap) if Tsum[k] > 0 else 0.0) for k, (t, _) in enumerate(sc))
         if nsnap % 10 == 0:
-            log(f"measure: step {steps + m_steps}, {nsnap} snapshots, slowest member at {prog:.2f} T, "
-                f"{time.perf_counter() - t_start:.0f} s")
-        if prog >= measure or steps + m_steps >= max_steps:
-            break
-    wall = time.perf_counter() - t_start
+            log(f"measure: step {steps + st['m_steps']}, {nsnap} snapshots, slowest member at {prog:.2f} T, "
+                f"{elapsed():.0f} s")
+        if prog >= measure or steps + st["m_steps"] >= max_steps:
+            st["phase"] = "done"
+        elif stop is not None and stop():
+            return stopped()
+    m_steps, nsnap = st["m_steps"], st["nsnap"]
+    refined, refined_at = st.get("refined", []), st.get("refined_at")
+    wall = elapsed()
     res = {"steps": steps + m_steps, "transient_steps": steps, "snapshot_every": every, "snapshots": nsnap,
            "wall_s": wall, "refined_members": refined,
            "refined_at_step": refined_at}
@@ -181,12 +214,17 @@ def run(E, members, transient: float, measure: float, snaps_per_T: float, chunk:
     return res
 
 
+RUN_KEYS = ("n", "precision", "i_lo", "i_hi", "box_scale", "transient", "measure", "snaps_per_T", "chunk",
+            "refine_lambda", "refine_transient")
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(prog="python -m paper_2506_23712_amd.run_ensemble")
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--i-lo", type=int, default=-22)
     ap.add_argument("--i-hi", type=int, default=25)
+    ap.add_argument("--box-scale", type=float, default=1.0, help="box = box_scale * 2 pi (2 for the ens256 set)")
     ap.add_argument("--transient", type=float, default=5.0, help="integral times before measuring")
     ap.add_argument("--measure", type=float, default=18.0, help="integral times measured")
     ap.add_argument("--snaps-per-T", type=float, default=10.0)
@@ -196,25 +234,49 @@ def main(argv=None):
     ap.add_argument("--refine-transient", type=float, default=1.0,
                     help="integral times the refined members run before the measurement")
     ap.add_argument("--record", default=None, help="JSON-lines file of every member's diagnostics per check")
+    ap.add_argument("--wall-limit", type=float, default=None,
+                    help="stop at the first check after this many seconds and write --checkpoint")
+    ap.add_argument("--checkpoint", default=None, help=".npz file written when the run stops early")
+    ap.add_argument("--resume", default=None, help="continue a stopped run from its checkpoint (its settings apply)")
     ap.add_argument("--out", required=True)
     a = ap.parse_args(argv)
+    if a.wall_limit is not None and not a.checkpoint:
+        ap.error("--wall-limit needs --checkpoint")
     import torch
     import paper_2506_23712_amd as ens
-    specs = ens128_specs(ens, a.n, a.precision, a.i_lo, a.i_hi)
-    E = ens.Ensemble(hist=hist_spec(ens, specs[0].nu), graphs=True)
-    members = [E.add_member(s) for s in specs]
-    E.autotune()
+    state = None
+    if a.resume:
+        extra = ens.Ensemble.read_checkpoint_extra(a.resume)
+        state, cfg = extra["driver"], extra["run"]
+        for k in RUN_KEYS:
+            setattr(a, k, cfg[k])
+        E, members = ens.Ensemble.load_checkpoint(a.resume)
+    else:
+        specs = ens128_specs(ens, a.n, a.precision, a.i_lo, a.i_hi, box=a.box_scale * 2 * math.pi)
+        E = ens.Ensemble(hist=hist_spec(ens, specs[0].nu), graphs=True)
+        members = [E.add_member(s) for s in specs]
+        E.autotune()
     torch.cuda.synchronize()
-    rec = open(a.record, "w") if a.record else None
+    t_proc = time.perf_counter()
+    stop = (lambda: time.perf_counter() - t_proc > a.wall_limit) if a.wall_limit is not None else None
+    rec = open(a.record, "a" if a.resume else "w") if a.record else None
     try:
         res = run(E, members, a.transient, a.measure, a.snaps_per_T, a.chunk,
                   log=lambda s: print(s, flush=True), refine_lambda=a.refine_lambda,
-                  refine_transient=a.refine_transient, record=rec)
+                  refine_transient=a.refine_transient, record=rec, state=state, stop=stop)
     finally:
         if rec is not None:
             rec.close()
+    if res.get("stopped"):
+        E.save_checkpoint(a.checkpoint, members=res["members"],
+                          extra={"driver": res["state"], "run": {k: getattr(a, k) for k in RUN_KEYS}})
+        E.close()
+        print(json.dumps({"stopped": True, "phase": res["state"]["phase"], "steps": res["state"]["steps"]
+                          + res["state"].get("m_steps", 0), "checkpoint": a.checkpoint}), flush=True)
+        return 0
+    specs = [m.spec for m in members]
     res["config"] = {"n": a.n, "precision": a.precision, "members": len(specs), "nu": specs[0].nu,
-                     "lambda": [s.lam for s in specs], "band": [1.4, 2.3], "cfl": 0.2}
+                     "box": specs[0].box, "lambda": [s.lam for s in specs], "band": [1.4, 2.3], "cfl": 0.2}
     diverged = [m.id for m in E.members if m.diag()["diverged"]]
     res["diverged"] = diverged
     E.close()

@@ -97,3 +97,47 @@ def test_small_ensemble_run_with_refined_members():
     for p in res["predictions"]:
         assert abs(p["weight_sum"] - 1.0) < 1e-13
     E.close()
+
+
+def test_run_split_over_three_contexts_equals_the_uninterrupted_run(tmp_path):
+    """The driver stopped twice (once in the transient, once later) and
+    resumed each time in a fresh context from the .npz checkpoint with its
+    state gives the uninterrupted run's results exactly (all but wall time)."""
+    import paper_2506_23712_amd as ens
+    from paper_2506_23712_amd import run_ensemble as rd
+    specs = rd.ens128_specs(ens, n=32, precision="fp64", i_lo=-2, i_hi=3)
+    kw = dict(transient=0.5, measure=1.0, snaps_per_T=5, chunk=20, log=print, refine_lambda=0.4,
+              refine_transient=0.25)
+
+    def fresh():
+        E = ens.Ensemble(hist=rd.hist_spec(ens, specs[0].nu))
+        return E, [E.add_member(s) for s in specs]
+
+    def stop_after(k):
+        n = [0]
+
+        def stop():
+            n[0] += 1
+            return n[0] >= k
+        return stop
+
+    E, ms = fresh()
+    ref = rd.run(E, ms, **kw)
+    E.close()
+    E, ms = fresh()
+    state, phases = None, []
+    for k in (2, 6, None):
+        res = rd.run(E, ms, state=state, stop=stop_after(k) if k else None, **kw)
+        if not res.get("stopped"):
+            break
+        phases.append(res["state"]["phase"])
+        path = str(tmp_path / f"ck{len(phases)}.npz")
+        E.save_checkpoint(path, members=res["members"], extra=res["state"])
+        E.close()
+        E, ms = ens.Ensemble.load_checkpoint(path)
+        state = ens.Ensemble.read_checkpoint_extra(path)
+    E.close()
+    assert phases[0] == "transient" and len(phases) == 2
+    for key in ref:
+        if key != "wall_s":
+            assert res[key] == ref[key], key

@@ -29,3 +29,18 @@ def test_ens128_recipe_matches_the_printed_ensemble():
     assert abs(min(kmeta) - kmin) / kmin < 0.02 and abs(max(kmeta) - kmax) / kmax < 0.02
     assert len({s.seed for s in specs}) == len(specs)
 
+
+
+def test_ens256_recipe_doubles_the_box_at_the_same_resolution():
+    """Table I's ens256: 256^3 in a (4 pi)^3 box (dk = 1/2), k_M eta = 3 for
+    the central member, band [1.4, 2.3] dk."""
+    import paper_2506_23712_amd as ens
+    from paper_2506_23712_amd import run_ensemble as rd
+    specs = rd.ens128_specs(ens, n=256, box=4 * math.pi)
+    K, dk = 256 // 3, 0.5
+    assert all(s.box == 4 * math.pi and s.n == 256 and (s.kf_lo, s.kf_hi) == (1.4, 2.3) for s in specs)
+    nu = specs[0].nu
+    assert abs(K * dk * nu ** 0.75 - GOLD["ens256_kmeta_central"]["value"]) < 1e-12
+    kmeta = [K * dk * (nu ** 3 / math.exp(s.lam)) ** 0.25 for s in specs]
+    kmin, kmax = GOLD["ens256_kmeta_range"]["value"]
+    assert abs(min(kmeta) - kmin) / kmin < 0.02 and abs(max(kmeta) - kmax) / kmax < 0.02
