@@ -142,7 +142,18 @@ def trace_averages(path: str) -> dict:
 PEAK_GBS = 8000.0
 
 
-def write_summary(n: int, counts, out: str, trace: str | None = None) -> None:
+def _pitch(n: int, cbytes: int) -> int:
+    """Row pitch of the pencil buffers (complex values): K + 1 rounded up to
+    whole 128-byte lines unless that pads more than 1/8 of the row."""
+    k1, per = n // 3 + 1, 128 // cbytes
+    px = (k1 + per - 1) // per * per
+    return px if 8 * (px - k1) <= k1 else k1
+
+
+DEFAULT_WORKLOADS = (("single256_fp64", "fp64", 1), ("ens96_mixed_fp32", "fp32", 25))
+
+
+def write_summary(n: int, counts, out: str, trace: str | None = None, workloads=None) -> None:
     """Markdown table: measured HBM bytes per launch (profiles/traffic_*.json)
     against the algorithmic bytes of each pass, for the n^3 kernels; with a
     kernel-statistics table of the same kernel sources, each kernel's
@@ -151,7 +162,8 @@ def write_summary(n: int, counts, out: str, trace: str | None = None) -> None:
     rows = []
     prof = os.path.join(os.path.dirname(HERE), "profiles")
     avg = trace_averages(trace) if trace else {}
-    for (wl, prec), cnt in zip((("single256_fp64", "fp64"), ("ens96_mixed_fp32", "fp32")), counts):
+    wls = workloads if workloads else [(w, p, c) for (w, p, _), c in zip(DEFAULT_WORKLOADS, counts)]
+    for wl, prec, cnt in wls:
         path = os.path.join(prof, f"traffic_{wl}.json")
         t = json.load(open(path))
         pb = pass_bytes(n, prec)
@@ -175,15 +187,19 @@ def write_summary(n: int, counts, out: str, trace: str | None = None) -> None:
                              (ar + aw) / (us * 1e3) if us else None))
     with open(out, "w") as f:
         f.write(f"# HBM traffic per launch vs algorithmic bytes ({n}^3 members)\n\n")
-        f.write("Made by `python -m paper_2506_23712_amd.profiling summary --out " + os.path.relpath(out, os.path.dirname(HERE))
+        f.write("Made by `python -m paper_2506_23712_amd.profiling summary"
+                + (f" --n {n}" if n != 256 else "")
+                + "".join(f" --workload {w}:{p}:{c}" for w, p, c in (workloads or []))
+                + " --out " + os.path.relpath(out, os.path.dirname(HERE))
                 + (" --trace " + os.path.relpath(trace, os.path.dirname(HERE)) if trace else "")
-                + "` from `profiles/traffic_single256_fp64.json` and `profiles/traffic_ens96_mixed_fp32.json` "
-                  "(their commands are recorded inside).  Counters: FETCH_SIZE and WRITE_SIZE (rocprofv3 `--pmc`, one "
+                + "` from " + " and ".join(f"`profiles/traffic_{w}.json`" for w, _, _ in wls)
+                + " (their commands are recorded inside).  Counters: FETCH_SIZE and WRITE_SIZE (rocprofv3 `--pmc`, one "
                   "counter per run), KiB per dispatch, scaled by what the same counter reads for a plain 1 GiB device "
                   "copy.  Algorithmic bytes: each pass's inputs read once and outputs written once, truncated storage "
                   "without line padding (the `zfwd_update` read and write average the three RK stages).  The measured bytes "
                   "include the zero pad entries that the z/y passes write so that every store covers whole 128-byte "
-                  "lines (FP32 rows of 86 complex values padded to 96, FP64 to 88).\n\n")
+                  f"lines (rows of {n // 3 + 1} complex values padded to {_pitch(n, 8)} in FP32, "
+                  f"{_pitch(n, 16)} in FP64).\n\n")
         if trace:
             f.write("Durations: kernel-trace averages from `" + os.path.relpath(trace, os.path.dirname(HERE)) +
                     "` (same kernel sources; averages include the autotuner's launches of each variant).  "
@@ -215,12 +231,18 @@ def main(argv=None):
     m.add_argument("--n", type=int, default=256)
     m.add_argument("--counts", type=int, nargs=2, default=(1, 25), metavar=("FP64", "FP32"),
                    help="members of that size per launch in the two workloads")
+    m.add_argument("--workload", action="append", default=None, metavar="NAME:PREC:COUNT",
+                   help="workload of profiles/traffic_NAME.json, its precision and members per launch of the n^3 "
+                        "kernels (repeatable; default single256_fp64 and ens96_mixed_fp32)")
     m.add_argument("--trace", default=None,
                    help="kernel-statistics table (from `stats`) of the same kernel sources, for the rate columns")
     m.add_argument("--out", required=True)
     a = ap.parse_args(argv)
     if a.cmd == "summary":
-        write_summary(a.n, a.counts, a.out, a.trace)
+        wls = None
+        if a.workload:
+            wls = [(w.split(":")[0], w.split(":")[1], int(w.split(":")[2])) for w in a.workload]
+        write_summary(a.n, a.counts, a.out, a.trace, wls)
         return
     if a.cmd == "stats":
         rows = kernel_stats(a.db)[: a.top]
