@@ -203,3 +203,43 @@ def test_mixture_with_tabulated_density_matches_oracle(orc):
     with pytest.raises(ens.EnsError):
         E.mix_table(pdf[:1], lam0, h)
     E.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("fp32", 2e-5)])
+def test_member_in_a_4pi_box_steps_and_bins_like_the_oracle(orc, prec, tol):
+    """The ens256 geometry: box (4 pi)^3, dk = 1/2, band [1.4, 2.3] dk, CFL
+    steps from dx = 4 pi / N.  Initial field, 20 steps and a statistics
+    snapshot (gradients scale with dk) against the oracle on the same box."""
+    import math
+    import paper_2506_23712_amd as ens
+    n, box = 32, 4 * math.pi
+    E = ens.Ensemble(hist=ens.HistSpec(**HK))
+    spec = ens.MemberSpec(n=n, nu=0.02, eps_ref=0.1, kf_lo=1.4, kf_hi=2.3, dt=0.0, cfl=0.5, box=box,
+                          precision=prec, seed=91)
+    m = E.add_member(spec)
+    u0 = m.state().cpu().numpy()
+    ref0 = orc.init_field(n, 91, box=box)
+    assert np.max(np.abs(u0 - ref0)) <= (1e-14 if prec == "fp64" else 1e-7) * np.max(np.abs(ref0))
+    E.step(20)
+    got = m.state().cpu().numpy()
+    om = orc.Member(n=n, nu=0.02, eps=0.1, kf_lo=1.4, kf_hi=2.3, dt=0.0, cfl=0.5, box=box)
+    ref, rd = orc.run(om, ref0, 20)
+    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    print(f"{prec} 4pi box: rel L2 after 20 steps {err:.2e}")
+    assert err <= tol
+    assert abs(m.diag()["t"] - rd[-1, 0]) <= 1e-12 * rd[-1, 0] + (0 if prec == "fp64" else 1e-6 * rd[-1, 0])
+    E.accumulate_stats()
+    counts, mom, npts = m.stats()
+    E.close()
+    if prec != "fp64":
+        return
+    h = orc.Hist(**HK)
+    rc, rm, near, _ = orc.stats(om, h, got)
+    gs, rs = h.split(counts.numpy().astype(np.uint64)), h.split(rc)
+    for k, name in enumerate(("qr", "log_eps", "log_ens", "a_long", "a_trans")):
+        counts_close(np.concatenate([gs[name].ravel(), gs[name + "_special"]]),
+                     np.concatenate([rs[name].ravel(), rs[name + "_special"]]), near[k])
+    mm = mom.numpy()
+    sc = moment_scales(rm, n ** 3)
+    for i in range(26):
+        assert abs(mm[i] - rm[i]) <= 1e-11 * sc[i], (i, mm[i], rm[i], sc[i])
