@@ -16,6 +16,12 @@ gradient components against the scale gap Z, the mixed gradient PDFs, and Z for
 the reference Reynolds numbers of Table II.  All arithmetic on fields and
 statistics runs in the library; this module only schedules calls.
 
+Options: the ens256 set (n = 256 in a box of 4 pi: --box-scale 2), moving the
+largest-lambda members onto twice their grid after the transient
+(--refine-lambda), a JSON-lines record of every member's diagnostics
+(--record), and stopping at a wall-time limit with a checkpoint that a later
+process resumes exactly (--wall-limit, --checkpoint, --resume).
+
     python -m paper_2506_23712_amd.run_ensemble --n 128 --precision fp64 --out run.json
 """
 from __future__ import annotations
