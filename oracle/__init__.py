@@ -65,7 +65,8 @@ def lib():
                                     ctypes.c_double, ctypes.c_double, dp]
         L.or_rhs.argtypes = [ctypes.POINTER(Params), dp, dp, ctypes.c_int, dp]
         L.or_run.argtypes = [ctypes.POINTER(Params), dp, ctypes.c_int, ctypes.c_double, dp]
-        L.or_stats.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(HistDesc), dp, u64p, dp, u64p, dp]
+        L.or_stats.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(HistDesc), dp, u64p, dp, u64p, dp,
+                               ctypes.c_double]
         L.or_counts_len.argtypes = [ctypes.POINTER(HistDesc)]
         L.or_counts_len.restype = ctypes.c_long
         L.or_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
@@ -303,8 +304,14 @@ class Hist:
 NMOM = 32
 
 
-def stats(m: Member, h: Hist, uhat: np.ndarray):
-    """Gradient statistics of one snapshot: (counts, moments, near_edge, max|Tr A|)."""
+def stats(m: Member, h: Hist, uhat: np.ndarray, grad_tol: float = 0.0):
+    """Gradient statistics of one snapshot: (counts, moments, near_edge, max|Tr A|).
+
+    near_edge[k] counts the samples of histogram k (QR, log eps, log Omega,
+    A_L, A_T) whose bin may differ on a path that rounds differently: bin
+    coordinate within 1e-9 (relative) of an edge, or, with grad_tol > 0,
+    within the first-order change caused by gradient errors up to
+    grad_tol * max|A_ij| (the bound a path with FP32 transforms is held to)."""
     u = np.ascontiguousarray(uhat, dtype=np.complex128)
     d = h.desc()
     counts = np.zeros(int(lib().or_counts_len(ctypes.byref(d))), dtype=np.uint64)
@@ -314,7 +321,7 @@ def stats(m: Member, h: Hist, uhat: np.ndarray):
     p = m.params()
     rc = lib().or_stats(ctypes.byref(p), ctypes.byref(d), _dp(u),
                         counts.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), _dp(mom),
-                        near.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), _dp(trmax))
+                        near.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), _dp(trmax), float(grad_tol))
     if rc != 0:
         raise ValueError("or_stats: bad arguments")
     return counts, mom, near, float(trmax[0])

@@ -243,20 +243,18 @@ def mix(ws: Sequence[float], values: Sequence[Sequence[float]]) -> list[float]:
     return out
 
 
-def normalised_pdf(counts: Sequence[int], total: int, bin_width: float) -> list[float]:
-    """count / (total samples x bin width); total includes under/overflow."""
-    return [c / (total * bin_width) for c in counts] if total > 0 else [0.0] * len(counts)
-
-
 def skewness(m2: float, m3: float) -> float:
+    """S = <x^3> / <x^2>^(3/2) of a zero-mean variable (eq. def_skewness_flatness)."""
     return m3 / m2 ** 1.5
 
 
 def flatness(m2: float, m4: float) -> float:
+    """F = <x^4> / <x^2>^2 of a zero-mean variable (eq. def_skewness_flatness)."""
     return m4 / (m2 * m2)
 
 
 def hyperflatness(m2: float, m6: float) -> float:
+    """H = <x^6> / <x^2>^3 of a zero-mean variable (eq. def_skewness_flatness)."""
     return m6 / (m2 * m2 * m2)
 
 

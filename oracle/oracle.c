@@ -27,8 +27,9 @@
  * solenoidal projection, linear band forcing f = eps/(2 E_f) u on the band
  * (E_f evaluated at every Runge-Kutta stage; f acts on the Hermitian part of
  * the spectrum and is projected together with the nonlinear term, which
- * changes nothing for the spectrum of a real solenoidal field), integrating-
- * factor low-storage
+ * changes nothing for the spectrum of a real solenoidal field; a band that
+ * holds no more than FORCE_EMPTY_FRAC of the member's energy at the start of
+ * the step counts as empty and is not forced), integrating-factor low-storage
  * (Williamson 2N) RK3 with A = (0,-5/9,-153/128), B = (1/3,15/16,8/15),
  * and CFL time step dt = cfl * dx / max(|u|+|v|+|w|) from the stage-1 field.
  *
@@ -323,11 +324,29 @@ typedef struct {
     grid_t g;
     or_params p;
     cplx *u[3], *w[3], *nl[3];    /* physical-space work (complex storage) */
+    double eref;                  /* energy of the field at the start of the step */
 } rhs_work;
+
+/* The linear band forcing eps/(2 E_f) u is singular as E_f -> 0: a band that
+ * holds only rounding-level energy would be amplified to inject eps.  The
+ * paper's forcing amplifies the band's existing coefficients; with nothing
+ * there it has nothing to amplify.  A band holding no more than this fraction
+ * of the member's energy at the start of the step is not forced.  Rounding
+ * puts about 1e-30 (FP64) or 1e-13 (FP32 transforms) of the energy in a band
+ * that should be empty; a developed field holds a sizeable fraction there. */
+#define FORCE_EMPTY_FRAC 1e-10
+
+static double field_energy(long n3, cplx *const uh[3]) {
+    double e = 0.0;
+    for (long i = 0; i < n3; i++)
+        for (int c = 0; c < 3; c++) e += 0.5 * creal(uh[c][i] * conj(uh[c][i]));
+    return e;
+}
 
 static void work_alloc(rhs_work *W, const or_params *p) {
     W->p = *p;
     W->g = make_grid(p->n, p->box);
+    W->eref = 0.0;
     for (int c = 0; c < 3; c++) {
         W->u[c] = alloc_c(W->g.n3); W->w[c] = alloc_c(W->g.n3); W->nl[c] = alloc_c(W->g.n3);
     }
@@ -443,7 +462,7 @@ static void rhs_eval(rhs_work *W, cplx *const uh[3], cplx *G[3], int terms, doub
      * the nonlinear term (the pressure removes the divergent part of every
      * non-viscous term); for a solenoidal field P u = u. */
     double ef = band_energy(W, uh), inj = 0.0;
-    if ((terms & T_FORCING) && ef > 0.0) {
+    if ((terms & T_FORCING) && ef > FORCE_EMPTY_FRAC * W->eref) {
         double fac = W->p.eps / (2.0 * ef);
         for (long i = 0; i < n3; i++) {
             int m[3]; double k[3];
@@ -482,6 +501,7 @@ int or_rhs(const or_params *p, const double *uhat_can, double *g_can, int terms,
     cplx *uh[3], *G[3];
     for (int c = 0; c < 3; c++) { uh[c] = alloc_c(W.g.n3); G[c] = alloc_c(W.g.n3); }
     canon_to_full(&W.g, (const cplx *)uhat_can, uh);
+    W.eref = field_energy(W.g.n3, uh);
     rhs_eval(&W, uh, G, terms, info);
     full_to_canon(&W.g, G, (cplx *)g_can);
     for (int c = 0; c < 3; c++) { free(uh[c]); free(G[c]); }
@@ -519,6 +539,7 @@ int or_run(const or_params *p, double *uhat_can, int nsteps, double t0, double *
     const double dx = p->box / p->n;
     double t = t0;
     int rc = 0;
+    W.eref = field_energy(n3, uh);
     for (int step = 0; step < nsteps; step++) {
         double dt = p->dt, info0[4] = { 0 };
         for (int s = 0; s < 3; s++) {
@@ -551,17 +572,18 @@ int or_run(const or_params *p, double *uhat_can, int nsteps, double t0, double *
             }
         }
         t += dt;
-        if (diag) {
-            double E = 0.0, D = 0.0;
-            for (long i = 0; i < n3; i++) {
-                int m[3]; double k[3];
-                kvec(g, i, m, k);
-                double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
-                for (int c = 0; c < 3; c++) {
-                    double a2 = creal(uh[c][i] * conj(uh[c][i]));
-                    E += 0.5 * a2; D += p->nu * k2 * a2;
-                }
+        double E = 0.0, D = 0.0;
+        for (long i = 0; i < n3; i++) {
+            int m[3]; double k[3];
+            kvec(g, i, m, k);
+            double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+            for (int c = 0; c < 3; c++) {
+                double a2 = creal(uh[c][i] * conj(uh[c][i]));
+                E += 0.5 * a2; D += p->nu * k2 * a2;
             }
+        }
+        W.eref = E;                        /* the next step's empty-band threshold */
+        if (diag) {
             double *d = diag + (long)step * D_NDIAG;
             d[D_T] = t; d[D_DT] = dt; d[D_E] = E; d[D_DISS] = D;
             d[D_INJ] = info0[1]; d[D_EF] = info0[0]; d[D_UMAX] = info0[2];
@@ -593,8 +615,16 @@ done:
  *   [25] sum R*^2, [26..31] zero.
  * Starred quantities use the reference member: tau = sqrt(nu_ref/eps_ref),
  *   Q* = Q / <TrS^2>_ref, R* = R / <TrS^2>_ref^(3/2), <TrS^2>_ref = eps_ref/(2 nu_ref).
- * near_edge[5]: points whose bin coordinate lies within 1e-9 (relative) of an
- *   integer, i.e. whose bin may legitimately differ under rounding. */
+ * near_edge[5]: samples (QR and the log histograms: points; the component
+ *   histograms: each A_ij) whose bin coordinate lies within rounding of an
+ *   integer (a bin edge), i.e. whose bin may legitimately differ on a path that
+ *   rounds differently.  "Within rounding" is 1e-9 relative to the coordinate
+ *   (FP64 paths), or, with grad_tol > 0, the first-order change of the
+ *   coordinate under a perturbation of every gradient component by
+ *   dA = grad_tol * max |A_ij| over the field (FP32 transforms): |dA_ij| <= dA
+ *   gives |dQ| <= 3|A| dA, |dR| <= 3|A|^2 dA (|.| the Frobenius norm),
+ *   |d eps| <= 12 nu |S| dA, |d omega_i| <= 2 dA, hence
+ *   |d omega^2| <= 4 sqrt(3) |omega| dA + 12 dA^2, and d log10 x = dx / (x ln 10). */
 #define OR_NMOM 32
 
 static long counts_len(const or_hist_desc *h) {
@@ -604,20 +634,31 @@ static long counts_len(const or_hist_desc *h) {
 long or_counts_len(const or_hist_desc *h) { return counts_len(h); }
 int or_nmom(void) { return OR_NMOM; }
 
-static int near_edge(double frac) {
+/* frac within max(1e-9 |frac|, dfrac) of an integer */
+static int near_edge(double frac, double dfrac) {
     double r = nearbyint(frac);
-    return fabs(frac - r) <= 1e-9 * fmax(1.0, fabs(frac));
+    return fabs(frac - r) <= fmax(1e-9 * fmax(1.0, fabs(frac)), dfrac);
 }
 
-/* returns bin in [0,nb), or -1 under, -2 over, -3 nan */
-static int bin1(double x, double lo, double hi, int nb, int *amb) {
+/* returns bin in [0,nb), or -1 under, -2 over, -3 nan; *amb += 1 if the bin
+ * coordinate is within dx (absolute, in units of x) of an edge */
+static int bin1(double x, double lo, double hi, int nb, double dx, int *amb) {
     if (x != x) return -3;
-    if (x < lo) return -1;
     double frac = (x - lo) * ((double)nb / (hi - lo));
-    if (near_edge(frac)) *amb = 1;
+    if (frac > -0.5 && frac < nb + 0.5 && near_edge(frac, dx * ((double)nb / (hi - lo)))) *amb += 1;
+    if (x < lo) return -1;
     double b = floor(frac);
     if (b >= (double)nb) return -2;
     return (int)b;
+}
+
+/* Compensated (Neumaier) accumulation of the moment sums: the sums are over up
+ * to 10^8 samples whose terms span many orders of magnitude (sixth powers), and
+ * a plain running sum drops every term below half an ulp of itself. */
+static inline void kadd(double *s, double *c, double x) {
+    const double t = *s + x;
+    *c += fabs(*s) >= fabs(x) ? (*s - t) + x : (x - t) + *s;
+    *s = t;
 }
 
 static void add1(uint64_t *h, int nb, int b) {
@@ -628,7 +669,7 @@ static void add1(uint64_t *h, int nb, int b) {
 }
 
 int or_stats(const or_params *p, const or_hist_desc *h, const double *uhat_can,
-             uint64_t *counts, double *moments, uint64_t *near, double *trace_max) {
+             uint64_t *counts, double *moments, uint64_t *near, double *trace_max, double grad_tol) {
     if (!is_pow2(p->n) || p->n < 8) return -1;
     if (h->qr_bins <= 0 || h->log_bins <= 0 || h->a_bins <= 0) return -1;
     grid_t g = make_grid(p->n, p->box);
@@ -655,7 +696,12 @@ int or_stats(const or_params *p, const or_hist_desc *h, const double *uhat_can,
     memset(near, 0, sizeof(uint64_t) * 5);
     const double tau = sqrt(h->nu_ref / h->eps_ref);
     const double trs_ref = h->eps_ref / (2.0 * h->nu_ref);
-    double tmax = 0.0;
+    double tmax = 0.0, amax = 0.0;
+    if (grad_tol > 0.0)
+        for (int ij = 0; ij < 9; ij++)
+            for (long idx = 0; idx < n3; idx++) amax = fmax(amax, fabs(creal(A[ij][idx])));
+    const double dA = grad_tol * amax;
+    double comp[OR_NMOM] = { 0 };              /* compensations of the moment sums */
     for (long idx = 0; idx < n3; idx++) {
         double a[3][3];
         for (int i = 0; i < 3; i++)
@@ -676,21 +722,31 @@ int or_stats(const or_params *p, const or_hist_desc *h, const double *uhat_can,
         double epsv = 2.0 * p->nu * ss;
         double qs = q / trs_ref, rs = r / pow(trs_ref, 1.5);
         double es = epsv / h->eps_ref, ws = w2s * h->nu_ref / h->eps_ref;
+        /* first-order bounds of the changes under gradient errors <= dA */
+        double fa2 = 0.0;
+        for (int i = 0; i < 3; i++)
+            for (int j = 0; j < 3; j++) fa2 += a[i][j] * a[i][j];
+        const double dq = 3.0 * sqrt(fa2) * dA / trs_ref, dr = 3.0 * fa2 * dA / pow(trs_ref, 1.5);
+        const double de = 12.0 * p->nu * sqrt(ss) * dA / h->eps_ref;
+        const double dw = (4.0 * sqrt(3.0) * sqrt(w2s) * dA + 12.0 * dA * dA) * h->nu_ref / h->eps_ref;
+        const double ln10 = log(10.0);
         /* QR joint histogram */
         int amb = 0, amb2 = 0;
-        int bq = bin1(qs, h->q_lo, h->q_hi, qb, &amb);
-        int br = bin1(rs, h->r_lo, h->r_hi, qb, &amb);
+        int bq = bin1(qs, h->q_lo, h->q_hi, qb, dq, &amb);
+        int br = bin1(rs, h->r_lo, h->r_hi, qb, dr, &amb);
         if (qs != qs || rs != rs) hq[(long)qb * qb + 2]++;
         else if (bq < 0 || br < 0) hq[(long)qb * qb]++;
         else hq[(long)bq * qb + br]++;
         if (amb) near[0]++;
-        /* log histograms */
+        /* log histograms (a value within its error of zero: ambiguous) */
         amb = 0;
-        add1(hle, lb, es > 0.0 ? bin1(log10(es), h->log10_lo, h->log10_hi, lb, &amb) : (es != es ? -3 : -1));
-        if (amb) near[1]++;
+        add1(hle, lb, es > 0.0 ? bin1(log10(es), h->log10_lo, h->log10_hi, lb, de >= es ? INFINITY : de / (es * ln10), &amb)
+                               : (es != es ? -3 : -1));
+        if (amb || (dA > 0.0 && !(es > de))) near[1]++;
         amb = 0;
-        add1(hlw, lb, ws > 0.0 ? bin1(log10(ws), h->log10_lo, h->log10_hi, lb, &amb) : (ws != ws ? -3 : -1));
-        if (amb) near[2]++;
+        add1(hlw, lb, ws > 0.0 ? bin1(log10(ws), h->log10_lo, h->log10_hi, lb, dw >= ws ? INFINITY : dw / (ws * ln10), &amb)
+                               : (ws != ws ? -3 : -1));
+        if (amb || (dA > 0.0 && !(ws > dw))) near[2]++;
         /* gradient components */
         amb = 0; amb2 = 0;
         for (int i = 0; i < 3; i++)
@@ -698,25 +754,26 @@ int or_stats(const or_params *p, const or_hist_desc *h, const double *uhat_can,
                 double x = a[i][j] * tau;
                 double xp = 1.0;
                 if (i == j) {
-                    add1(hal, ab, bin1(x, h->a_lo, h->a_hi, ab, &amb));
-                    for (int pw = 0; pw < 6; pw++) { xp *= x; moments[pw] += xp; }
+                    add1(hal, ab, bin1(x, h->a_lo, h->a_hi, ab, dA * tau, &amb));
+                    for (int pw = 0; pw < 6; pw++) { xp *= x; kadd(&moments[pw], &comp[pw], xp); }
                 } else {
-                    add1(hat, ab, bin1(x, h->a_lo, h->a_hi, ab, &amb2));
-                    for (int pw = 0; pw < 6; pw++) { xp *= x; moments[6 + pw] += xp; }
+                    add1(hat, ab, bin1(x, h->a_lo, h->a_hi, ab, dA * tau, &amb2));
+                    for (int pw = 0; pw < 6; pw++) { xp *= x; kadd(&moments[6 + pw], &comp[6 + pw], xp); }
                 }
             }
-        if (amb) near[3]++;
-        if (amb2) near[4]++;
+        near[3] += (uint64_t)amb;
+        near[4] += (uint64_t)amb2;
         double ep = 1.0, wp = 1.0;
         for (int pw = 0; pw < 4; pw++) {
             ep *= es; wp *= ws;
-            moments[12 + pw] += ep; moments[16 + pw] += wp;
+            kadd(&moments[12 + pw], &comp[12 + pw], ep); kadd(&moments[16 + pw], &comp[16 + pw], wp);
         }
-        moments[20] += qs; moments[21] += rs;
-        moments[22] += ss * tau * tau;
-        moments[23] += tr * tr * tau * tau;
-        moments[24] += qs * qs; moments[25] += rs * rs;
+        kadd(&moments[20], &comp[20], qs); kadd(&moments[21], &comp[21], rs);
+        kadd(&moments[22], &comp[22], ss * tau * tau);
+        kadd(&moments[23], &comp[23], tr * tr * tau * tau);
+        kadd(&moments[24], &comp[24], qs * qs); kadd(&moments[25], &comp[25], rs * rs);
     }
+    for (int k = 0; k < OR_NMOM; k++) moments[k] += comp[k];
     if (trace_max) *trace_max = tmax;
     for (int c = 0; c < 3; c++) free(uh[c]);
     for (int ij = 0; ij < 9; ij++) free(A[ij]);

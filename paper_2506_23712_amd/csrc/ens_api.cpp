@@ -486,6 +486,7 @@ ENS_API ens_status ens_member_set_state(ens_ctx *ctx, int32_t mid, const double 
     HIPCK(ctx, hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
     HIPCK(ctx, launch_set_state(m->d.n, m->d.precision, m->dev, dev_uhat, s));
+    HIPCK(ctx, launch_refresh_energy(m->d.precision, m->dev, m->md.st, m->g.K, s));
     m->last = s;
     return ENS_OK;
 }

@@ -24,6 +24,9 @@ hipError_t launch_spectrum(int prec, const MemberDev *mem, int K, int nshell, do
 // E, u', integral length L and integral time T of one member into `out`
 // (device, 4 doubles); uses the member's FP64 partials (scales_partials(K)).
 hipError_t launch_scales(int prec, const MemberDev *mem, int K, double *out, hipStream_t s);
+// Set diag.E of one member to the energy of its current field (the scales'
+// passes, with DevState::pad as their output); `st` is the member's DevState.
+hipError_t launch_refresh_energy(int prec, const MemberDev *mem, DevState *st, int K, hipStream_t s);
 // Copy member src onto the finer grid of member dst (retained modes of src,
 // zeros elsewhere), clear dst's RK register, carry time and diagnostics.
 hipError_t launch_refine(int prec_src, int prec_dst, const MemberDev *src, const MemberDev *dst, int n_dst,

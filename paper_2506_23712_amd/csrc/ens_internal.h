@@ -10,11 +10,12 @@
 
 namespace ens {
 
-// Lines (pencils) per workgroup and threads per workgroup of the FFT passes.
-// Each thread owns 16 complex values of one line; a line of length n uses
-// n/16 threads, so a 256-thread workgroup holds 16*256/n lines.
-constexpr int kThreads = 256;
-constexpr int kPerThread = 16;
+// The linear band forcing eps/(2 E_f) u is singular as E_f -> 0.  A band
+// holding no more than this fraction of the member's energy at the start of
+// the step (the energy of the previous step's end, or of the field as set)
+// is treated as empty and not forced: rounding puts about 1e-30 (FP64) or
+// 1e-13 (FP32) of the energy into a band that should be empty.
+constexpr double kForceEmptyFrac = 1e-10;
 
 // Per-member scalars kept in device memory.  `diag` is what ens_get_diag
 // returns; the rest carries values between kernels of one step.
@@ -58,7 +59,7 @@ struct MemberDev {
     void *q;           // RK register, same layout
     void *bufA;        // [F][n (z)][2K+1][PX] (z-inverse out) / [3][n][n][K+1] (x-pass out, linear stores)
     void *bufB;        // [F][n (z)][n (y)][PX] (y-inverse out) / [3][n][2K+1][PX] (y-forward out)
-    DevState *st;
+    DevState *st;      // diag.E: energy at the end of the last step (or of the field as set)
     double *partials;  // per-workgroup FP64 partial sums
     unsigned long long *counts;   // statistics counters
     double *moments;              // ENS_NMOM sums

@@ -190,6 +190,20 @@ hipError_t launch_scales(int prec, const MemberDev *mem, int K, double *out, hip
     return hipGetLastError();
 }
 
+// diag.E of a member whose field was replaced: the empty-band threshold of its
+// next step is relative to the energy of the field it starts from.
+__global__ void k_take_energy(const MemberDev *__restrict__ mp) {
+    DevState *st = mp->st;
+    st->diag.E = st->pad[0];
+}
+
+hipError_t launch_refresh_energy(int prec, const MemberDev *mem, DevState *st, int K, hipStream_t s) {
+    hipError_t e = launch_scales(prec, mem, K, st->pad, s);
+    if (e != hipSuccess) return e;
+    k_take_energy<<<1, 1, 0, s>>>(mem);
+    return hipGetLastError();
+}
+
 // dst storage entry (component, iz, plane offset) of the finer grid: the src
 // value where the mode is retained by src, else zero (pad entries too); the RK
 // register is cleared.  One thread per dst entry.

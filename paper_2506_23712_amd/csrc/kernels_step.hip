@@ -130,12 +130,17 @@ __global__ void __launch_bounds__(256) k_band_energy(const MemberDev *__restrict
     }
     const double ef = block_sum<256>(acc, red);
     if (threadIdx.x == 0) {
-        md.st->Ef = ef;
+        // A band holding no more than kForceEmptyFrac of the energy the field
+        // had at the start of the step (diag.E) is empty: the linear forcing,
+        // eps/(2 E_f) u, would otherwise amplify rounding-level band modes to
+        // inject eps.  Ef = 0 tells the update to add no forcing.
+        const bool forced = ef > kForceEmptyFrac * md.st->diag.E;
+        md.st->Ef = forced ? ef : 0.0;
         if (stage == 0) {
             md.st->diag.E_f = ef;
-            md.st->diag.inj = ef > 0.0 ? md.eps_m : 0.0;
+            md.st->diag.inj = forced ? md.eps_m : 0.0;
             md.st->umax_bits = 0ull;
-            if (!(ef > 0.0) && md.eps_m != 0.0) md.st->diag.flags |= 2;
+            if (!forced && md.eps_m != 0.0) md.st->diag.flags |= 2;
         }
     }
 }

@@ -40,6 +40,35 @@ def test_single_mode_decays_by_the_viscous_factor(n, prec):
     assert np.max(np.abs(got - want)) <= tol * np.max(np.abs(u))
 
 
+@pytest.mark.parametrize("n,prec", [(32, "fp64"), (32, "fp32"), (256, "fp64"), (256, "fp32")])
+def test_single_off_band_mode_with_injection_is_not_forced(n, prec):
+    """The same mode with eps > 0: the band holds only the rounding the
+    transforms leave there, at most 1e-10 of the field's energy, so it counts
+    as empty on both sides (no forcing, no injection, flag bit 1); the mode
+    decays by the viscous factor over 20 steps, as in the oracle."""
+    import torch
+    import oracle
+    ens = ens_mod()
+    nu, dt, steps = 0.05, 0.01, 20
+    E = ens.Ensemble()
+    m = E.add_member(ens.MemberSpec(n=n, nu=nu, eps_ref=1.0, kf_lo=0.0, kf_hi=2.5, dt=dt, precision=prec, seed=1))
+    u = np.zeros((3, n, n, n // 2 + 1), dtype=np.complex128)
+    u[1, 0, 0, 3] = 0.25 - 0.5j
+    m.set_state(torch.from_numpy(u))
+    E.step(steps)
+    got = m.state().cpu().numpy()
+    d = m.diag()
+    E.close()
+    assert d["inj"] == 0.0 and (d["flags"] & 2) and not d["diverged"]
+    want = u * math.exp(-nu * 9.0 * steps * dt)
+    tol = 1e-13 if prec == "fp64" else 2e-6
+    assert np.max(np.abs(got - want)) <= tol * np.max(np.abs(u))
+    if n == 32:
+        ref, diag = oracle.run(oracle.Member(n=n, nu=nu, eps=1.0, kf_lo=0.0, kf_hi=2.5, dt=dt), u, steps)
+        assert np.all(diag[:, 4] == 0)
+        assert np.linalg.norm(got - ref) <= (1e-13 if prec == "fp64" else 2e-6) * np.linalg.norm(ref)
+
+
 def test_zero_field_with_fixed_dt_stays_zero_and_cfl_reports_no_velocity():
     import torch
     ens = ens_mod()

@@ -10,6 +10,17 @@ HK = dict(qr_bins=64, q_lo=-30.0, q_hi=30.0, r_lo=-60.0, r_hi=60.0, log_bins=512
           log10_hi=5.0, a_bins=1024, a_lo=-100.0, a_hi=100.0, eps_ref=0.1, nu_ref=0.02)
 
 
+# FP32 statistics (FP32 gradient transforms, values and sums in FP64) against
+# the oracle's FP64 statistics of the same field.  Gradient errors of FP32
+# transforms: about 6e-8 (the FP32 rounding of i k_j u_i) times a few per
+# transform pass, relative to the field's largest gradient; the allowance
+# for samples near a bin edge takes 1e-5 of max|A_ij| (oracle grad_tol), and
+# moment sums, at most sixth powers of those values, agree to 5e-5 of their
+# scale.
+FP32_GRAD_TOL = 1e-5
+FP32_MOMENT_TOL = 5e-5
+
+
 def moment_scales(rm, npts):
     """Size against which each moment sum is compared.  Sums that vanish by
     symmetry (odd moments, <Q>, <R>, Tr A) are measured against the
@@ -58,6 +69,35 @@ def test_snapshot_statistics_match_oracle(orc, n, steps, prec):
     tol = moment_scales(rm, n ** 3)
     for i in range(26):
         assert abs(m[i] - rm[i]) <= 1e-11 * tol[i], (i, m[i], rm[i], tol[i])
+
+
+@pytest.mark.parametrize("n,steps", [(32, 20), (64, 10), (128, 4)])
+def test_fp32_snapshot_statistics_match_oracle(orc, n, steps):
+    """FP32 members (FP32 gradient transforms, values, bins and sums in FP64):
+    the statistics of the member's field against the oracle's FP64 statistics
+    of the same field (its state read back), at sizes that use each FP32
+    exchange layout of the statistics kernel (128^3: 8-line rows)."""
+    import paper_2506_23712_amd as ens
+    E = ens.Ensemble(hist=ens.HistSpec(**HK))
+    spec = ens.MemberSpec(n=n, nu=0.02, eps_ref=0.1, kf_hi=2.0, dt=0.0, cfl=0.5, seed=5 + n, precision="fp32")
+    m = E.add_member(spec)
+    E.step(steps)
+    E.accumulate_stats()
+    counts, mom, npts = m.stats()
+    state = m.state().cpu().numpy()
+    E.close()
+    h = orc.Hist(**HK)
+    om = orc.Member(n=n, nu=0.02, eps=0.1, kf_hi=2.0, dt=0.0, cfl=0.5)
+    rc, rm, near, _ = orc.stats(om, h, state, grad_tol=FP32_GRAD_TOL)
+    got, ref = h.split(counts.numpy().astype(np.uint64)), h.split(rc)
+    assert npts == n ** 3
+    for k, name in enumerate(("qr", "log_eps", "log_ens", "a_long", "a_trans")):
+        counts_close(np.concatenate([got[name].ravel(), got[name + "_special"]]),
+                     np.concatenate([ref[name].ravel(), ref[name + "_special"]]), near[k])
+    mm = mom.numpy()
+    sc = moment_scales(rm, n ** 3)
+    for i in range(26):
+        assert abs(mm[i] - rm[i]) <= FP32_MOMENT_TOL * sc[i], (i, mm[i], rm[i], sc[i])
 
 
 def test_statistics_accumulate_and_reset(orc):
@@ -231,15 +271,14 @@ def test_member_in_a_4pi_box_steps_and_bins_like_the_oracle(orc, prec, tol):
     E.accumulate_stats()
     counts, mom, npts = m.stats()
     E.close()
-    if prec != "fp64":
-        return
     h = orc.Hist(**HK)
-    rc, rm, near, _ = orc.stats(om, h, got)
+    rc, rm, near, _ = orc.stats(om, h, got, grad_tol=0.0 if prec == "fp64" else FP32_GRAD_TOL)
     gs, rs = h.split(counts.numpy().astype(np.uint64)), h.split(rc)
     for k, name in enumerate(("qr", "log_eps", "log_ens", "a_long", "a_trans")):
         counts_close(np.concatenate([gs[name].ravel(), gs[name + "_special"]]),
                      np.concatenate([rs[name].ravel(), rs[name + "_special"]]), near[k])
     mm = mom.numpy()
     sc = moment_scales(rm, n ** 3)
+    mtol = 1e-11 if prec == "fp64" else FP32_MOMENT_TOL
     for i in range(26):
-        assert abs(mm[i] - rm[i]) <= 1e-11 * sc[i], (i, mm[i], rm[i], sc[i])
+        assert abs(mm[i] - rm[i]) <= mtol * sc[i], (i, mm[i], rm[i], sc[i])

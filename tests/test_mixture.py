@@ -6,7 +6,7 @@ import os
 
 import numpy as np
 import pytest
-from scipy import integrate
+from scipy import integrate, stats
 
 from oracle import mixture as mx
 
@@ -114,6 +114,38 @@ def test_mixture_of_identical_members_is_that_member():
     # skewness from mixed moments of identical members is the member's
     m2, m3 = mx.mix(w, [[2.0, -1.0]] * len(lam))
     assert abs(mx.skewness(m2, m3) - (-1.0 / 2.0 ** 1.5)) < 1e-15
+
+
+# Skewness, flatness and hyper-flatness (section "Modeling choices",
+# eq. def_skewness_flatness) of zero-mean variables whose moments are fixed by
+# mathematics.  The moments come from scipy's distributions (not from the ratio
+# formulas under test); scales other than 1 make a wrong power of m2 visible.
+@pytest.mark.parametrize("dist, S, F, H", [
+    (stats.norm(scale=1.7), 0.0, 3.0, 15.0),                  # Gaussian: 3 = 3!!, 15 = 5!!
+    (stats.expon(loc=-0.6, scale=0.6), 2.0, 9.0, 265.0),      # centred exponential: subfactorials !3, !4, !6
+    (stats.laplace(scale=2.3), 0.0, 6.0, 90.0),               # 4!/2^2, 6!/2^3
+    (stats.uniform(loc=-1.9, scale=3.8), 0.0, 9.0 / 5.0, 27.0 / 7.0),
+])
+def test_moment_ratios_of_known_distributions(dist, S, F, H):
+    assert abs(dist.mean()) < 1e-14
+    m2, m3, m4, m6 = (float(dist.moment(p)) for p in (2, 3, 4, 6))
+    assert abs(mx.skewness(m2, m3) - S) <= 1e-12
+    assert abs(mx.flatness(m2, m4) - F) <= 1e-12 * F
+    assert abs(mx.hyperflatness(m2, m6) - H) <= 1e-8 * H      # scipy's 6th moment of the shifted exponential: 3e-9
+    sk, ek = dist.stats(moments="sk")
+    assert abs(mx.skewness(m2, m3) - float(sk)) <= 1e-12
+    assert abs(mx.flatness(m2, m4) - (3.0 + float(ek))) <= 1e-12 * F
+
+
+def test_moment_ratios_match_sample_statistics():
+    """On a skewed sample (centred), the ratios of its central moments equal
+    scipy's sample skewness and (Pearson) kurtosis."""
+    rng = np.random.default_rng(11)
+    x = rng.gamma(2.0, 1.5, 200000)
+    x = x - x.mean()
+    m2, m3, m4 = (float(np.mean(x ** p)) for p in (2, 3, 4))
+    assert abs(mx.skewness(m2, m3) - float(stats.skew(x))) <= 1e-12
+    assert abs(mx.flatness(m2, m4) - float(stats.kurtosis(x, fisher=True) + 3.0)) <= 1e-10
 
 
 def test_cost_saving_matches_paper():

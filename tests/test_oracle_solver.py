@@ -199,6 +199,41 @@ def test_forcing_with_empty_band_energy_is_zero(orc):
     assert info[0] == 0 and np.all(g == 0)
 
 
+@pytest.mark.parametrize("frac, forced", [(1e-12, False), (1e-11, False), (1e-9, True), (1e-6, True)])
+def test_band_below_the_empty_threshold_is_not_forced(orc, frac, forced):
+    """The linear forcing eps/(2 E_f) u is singular as E_f -> 0; a band holding
+    at most 1e-10 of the field's energy counts as empty (no forcing, no
+    injection), above it the injection is eps exactly."""
+    n = 16
+    u = np.zeros((3, n, n, n // 2 + 1), complex)
+    u[1, 0, 0, 5] = -0.5j                            # energy 1/4 off the band
+    E_off = orc.energy(u)
+    a, _ = _single_mode(n, (1, 1, 0), amp=1.0)        # one band mode pair, |m|^2 = 2
+    a *= math.sqrt(frac * E_off / orc.energy(a))
+    v = u + a
+    Ef = orc.energy(a)
+    assert abs(Ef / orc.energy(v) - frac / (1 + frac)) <= 1e-15
+    g, info = orc.rhs(orc.Member(n=n, nu=0.0, eps=0.7, kf_hi=2.0), v, terms=orc.T_FORCING)
+    assert abs(info[0] - Ef) <= 1e-14 * Ef
+    if forced:
+        assert abs(info[1] - 0.7) <= 1e-14
+        assert np.max(np.abs(g - (0.7 / (2 * Ef)) * a)) <= 1e-14 * 0.7 / (2 * Ef) * np.max(np.abs(a))
+    else:
+        assert info[1] == 0 and np.all(g == 0)
+
+
+def test_single_off_band_mode_with_injection_decays_viscously(orc):
+    """A single Fourier mode outside the band, eps > 0: the band stays empty,
+    nothing is forced, and the mode decays exactly as exp(-nu k^2 t) (its own
+    nonlinear term vanishes)."""
+    n, nu = 16, 0.05
+    u0, k2 = _single_mode(n, (3, 1, 0))
+    m = orc.Member(n=n, nu=nu, eps=1.0, kf_lo=0, kf_hi=2.0, dt=0.05)
+    u, diag = orc.run(m, u0, 20)
+    assert np.max(np.abs(u - u0 * math.exp(-nu * k2 * 20 * 0.05))) <= 1e-14 * np.max(np.abs(u0))
+    assert np.all(diag[:, 4] == 0)                    # no injection at any step
+
+
 # ----------------------------------------------------------------- time stepping
 def _single_mode(n, kv, amp=0.3):
     """u = a cos(k.x) with a perpendicular to k, written directly in spectral space."""

@@ -127,3 +127,42 @@ def test_zero_field_fills_one_bin(orc):
     assert got["log_eps_special"][0] == n ** 3            # eps = 0 -> underflow
     assert got["a_long"][4] == 3 * n ** 3
     assert np.all(mom == 0)
+
+
+def test_gradient_tolerance_bounds_the_bin_changes_of_a_perturbed_field(orc):
+    """The near-edge allowance with grad_tol covers every bin change that a
+    gradient perturbation of at most grad_tol * max|A_ij| can cause: the field
+    u + s u + w (w random, its largest possible gradient t max|A| by the
+    triangle inequality over its modes) bins like u except for at most the
+    samples the oracle marks as near an edge; the plain rounding allowance
+    does not cover it."""
+    n, nu = 32, 0.02
+    u = orc.init_field(n, seed=77, k_peak=3.0, e0=0.5)
+    h = orc.Hist(qr_bins=64, log_bins=256, a_bins=256, a_lo=-20, a_hi=20, eps_ref=0.1, nu_ref=nu)
+    m = orc.Member(n=n, nu=nu, eps=0.1)
+    c0, _, near0, _ = orc.stats(m, h, u)
+    # max |A_ij| of u from its physical gradients
+    mz, my, mx = orc.modes(n)
+    kk = [mx, my, mz]
+    amax = 0.0
+    for i in range(3):
+        for j in range(3):
+            g = np.fft.irfftn(1j * kk[j] * u[i], s=(n, n, n), axes=(0, 1, 2)) * n ** 3
+            amax = max(amax, float(np.max(np.abs(g))))
+    rng = np.random.default_rng(5)
+    w = (rng.standard_normal(u.shape) + 1j * rng.standard_normal(u.shape)) * orc.retained_mask(n)
+    wt = np.ones(n // 2 + 1); wt[1:] = 2.0
+    wbound = max(float(np.sum(np.abs(kk[j] * w[i]) * wt)) for i in range(3) for j in range(3))
+    s, t = 3e-5, 2e-5
+    v = u * (1 + s) + w * (t * amax / wbound)
+    c1, _, _, _ = orc.stats(m, h, v)
+    _, _, near, _ = orc.stats(m, h, u, grad_tol=s + t)
+    a, b = h.split(c0), h.split(c1)
+    moved = 0
+    for k, name in enumerate(("qr", "log_eps", "log_ens", "a_long", "a_trans")):
+        diff = int(np.abs(np.concatenate([a[name].ravel(), a[name + "_special"]]).astype(np.int64)
+                          - np.concatenate([b[name].ravel(), b[name + "_special"]]).astype(np.int64)).sum())
+        assert diff <= 2 * int(near[k]), (name, diff, int(near[k]))
+        assert int(near[k]) >= int(near0[k])
+        moved += diff > 2 * int(near0[k])
+    assert moved >= 3                                     # the perturbation does move samples across edges
