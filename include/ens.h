@@ -288,6 +288,24 @@ ens_status ens_mix_len(const ens_ctx *ctx, int32_t count, size_t *n_out);
 ens_status ens_mix(ens_ctx *ctx, const int32_t *members, int32_t count, double c, double Z,
                    int32_t weight_mode, double q_sigma, double *dev_out, void *stream);
 
+/* Mixture as ens_mix for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): no device memory is allocated; the member table that ens_mix
+ * keeps in a buffer the library allocates lives instead in a fixed
+ * file-scope device array of ENS_MIX_STATIC_MAX entries (48 bytes each,
+ * about 48 KiB), one copy on each GPU the library runs on, held until the
+ * process ends.  Arguments, output layout and results are those of ens_mix
+ * (bitwise equal on the same input); count > ENS_MIX_STATIC_MAX returns
+ * ENS_E_INVALID.  Each call rewrites every table entry it reads (nothing of an
+ * earlier call is used), but all calls on one GPU share the array: calls that
+ * overlap on one GPU (concurrent calls from several threads, or on several
+ * streams whose kernels may run at once) race.  Synchronises the members'
+ * streams and `stream` (as ens_mix does) before enqueuing the mixture kernels
+ * on `stream`. */
+#define ENS_MIX_STATIC_MAX 1023
+ens_status ens_mix_noalloc(ens_ctx *ctx, const int32_t *members, int32_t count, double c, double Z,
+                           int32_t weight_mode, double q_sigma, double *dev_out, void *stream);
+
 /* Mixture as ens_mix, with each member's weight the mass of its lambda bin
  * (bins of mode 0: midpoints, open end bins) under a tabulated lambda density
  * instead of a parametric one: for any exponent parameterisation whose lambda

@@ -11,6 +11,7 @@ ENS_OK, ENS_E_INVALID, ENS_E_OOM, ENS_E_HIP, ENS_E_UNSUPPORTED, ENS_E_STATE, ENS
 ENS_FP64, ENS_FP32 = 0, 1
 ENS_NPASS = 7
 ENS_NMOM = 32
+ENS_MIX_STATIC_MAX = 1023
 PASS_NAMES = ("band", "zinv", "yinv", "xpass", "yfwd", "zfwd_update", "end_step")
 
 # every symbol the header declares
@@ -18,7 +19,7 @@ EXPORTS = ("ens_create", "ens_destroy", "ens_last_error", "ens_set_graphs", "ens
            "ens_member_init", "ens_member_set_state", "ens_member_get_state", "ens_step", "ens_profile_step",
            "ens_get_diag", "ens_accumulate_stats", "ens_stats_len", "ens_get_stats", "ens_reset_stats",
            "ens_member_set_diag", "ens_set_stats",
-           "ens_mix_len", "ens_mix", "ens_mix_table", "ens_lambda_pdf_from_cf", "ens_scale_gap", "ens_spectrum", "ens_integral_scales", "ens_member_refine",
+           "ens_mix_len", "ens_mix", "ens_mix_noalloc", "ens_mix_table", "ens_lambda_pdf_from_cf", "ens_scale_gap", "ens_spectrum", "ens_integral_scales", "ens_member_refine",
            "ens_fft_pencils", "ens_autotune", "ens_set_variant", "ens_get_variant")
 
 
@@ -85,6 +86,7 @@ def lib() -> ctypes.CDLL:
         "ens_set_stats": [vp, i32, P(ctypes.c_uint64), P(dp), vp],
         "ens_mix_len": [vp, i32, P(sz)],
         "ens_mix": [vp, P(i32), i32, dp, dp, i32, dp, vp, vp],
+        "ens_mix_noalloc": [vp, P(i32), i32, dp, dp, i32, dp, vp, vp],
         "ens_mix_table": [vp, P(i32), i32, vp, i32, dp, dp, vp, vp],
         "ens_lambda_pdf_from_cf": [vp, i32, dp, dp, vp, vp],
         "ens_scale_gap": [vp, P(i32), i32, dp, P(dp), P(dp), P(dp)],

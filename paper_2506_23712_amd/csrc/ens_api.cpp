@@ -350,6 +350,9 @@ ENS_API ens_status ens_create(ens_ctx **out, int device, const ens_hist_desc *h)
     if (device < 0 || device >= ndev) return fail(ENS_E_INVALID, "device index out of range");
     e = hipSetDevice(device);
     if (e != hipSuccess) return fail(ENS_E_HIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    // device address of the static mixture table (ens_mix_noalloc), once per device
+    e = mix_static_setup(device);
+    if (e != hipSuccess) return fail(ENS_E_HIP, std::string("hipGetSymbolAddress: ") + hipGetErrorString(e));
     auto ctx = std::make_unique<ens_ctx>();
     ctx->device = device;
     if (h) {
@@ -716,6 +719,38 @@ ENS_API ens_status ens_mix(ens_ctx *ctx, const int32_t *members, int32_t count, 
     }
     HIPCK(ctx, launch_mix(mds.data(), lam.data(), count, ctx->hist, c, Z, weight_mode, q_sigma, dev_out,
                           ctx->mix_scratch, s));
+    return ENS_OK;
+}
+
+ENS_API ens_status ens_mix_noalloc(ens_ctx *ctx, const int32_t *members, int32_t count, double c, double Z,
+                                   int32_t weight_mode, double q_sigma, double *dev_out, void *stream) {
+    if (ens_status st = check_ctx(ctx)) return st;
+    if (!ctx->has_hist) return fail(ENS_E_STATE, "context has no histogram descriptor");
+    if (!members || count <= 0) return fail(ENS_E_INVALID, "empty member list");
+    if (count > ENS_MIX_STATIC_MAX)
+        return fail(ENS_E_INVALID, "too many members for the static mixture table (at most " +
+                                       std::to_string(ENS_MIX_STATIC_MAX) + ")");
+    if (!dev_out) return fail(ENS_E_INVALID, "null output pointer");
+    if (!(c > 0) || !(Z >= 0) || !std::isfinite(Z)) return fail(ENS_E_INVALID, "need c > 0 and Z >= 0");
+    if (weight_mode < 0 || weight_mode > 3) return fail(ENS_E_INVALID, "weight_mode must be 0, 1, 2 or 3");
+    if (weight_mode == 2 && (!(q_sigma > 0) || !(Z > 0))) return fail(ENS_E_INVALID, "mode 2 needs q_sigma > 0 and Z > 0");
+    // ids checked without heap allocation: bounds, then duplicates on a sorted copy
+    int32_t sorted[ENS_MIX_STATIC_MAX];
+    const MemberDev *mds[ENS_MIX_STATIC_MAX];
+    double lam[ENS_MIX_STATIC_MAX];
+    for (int32_t i = 0; i < count; i++) {
+        Member *m;
+        if (ens_status st = member_of(ctx, members[i], &m)) return st;
+        sorted[i] = members[i];
+        mds[i] = &m->md;
+        lam[i] = m->d.lambda;
+    }
+    std::sort(sorted, sorted + count);
+    if (std::adjacent_find(sorted, sorted + count) != sorted + count) return fail(ENS_E_INVALID, "duplicate member id");
+    HIPCK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    for (int32_t i = 0; i < count; i++) HIPCK(ctx, hipStreamSynchronize(ctx->members[members[i]]->last));
+    HIPCK(ctx, launch_mix_static(ctx->device, mds, lam, count, ctx->hist, c, Z, weight_mode, q_sigma, dev_out, s));
     return ENS_OK;
 }
 

@@ -143,6 +143,14 @@ hipError_t launch_mix(const MemberDev *const *members_host, const double *lambda
 
 size_t mix_scratch_bytes(int count);
 int mix_max_members();
+// Mixture with the member table in the library's static device array (no
+// allocation).  mix_static_setup(device) takes that array's device address on
+// `device`, which must be current; launch_mix_static uses it.
+hipError_t mix_static_setup(int device);
+size_t mix_static_bytes();
+hipError_t launch_mix_static(int device, const MemberDev *const *members_host, const double *lambdas, int count,
+                             const ens_hist_desc &h, double c, double Z, int mode, double q_sigma, double *out,
+                             hipStream_t s);
 
 // Number of workgroups that write FP64 partials, per member.
 long long zfwd_blocks(int n, int prec);

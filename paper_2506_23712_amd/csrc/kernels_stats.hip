@@ -8,6 +8,8 @@
 //            then per point in FP64: Q, R, eps, omega^2, histograms, moments.
 #include <vector>
 
+#include <mutex>
+
 #include "ens_internal.h"
 #include "ens_lambda.h"
 #include "fft.hpp"
@@ -621,6 +623,7 @@ __device__ double nmass(double a, double b, double mu, double sig) {
 }
 
 constexpr int kMaxMix = 1023;
+static_assert(kMaxMix == ENS_MIX_STATIC_MAX, "the static mixture table holds the largest mixture");
 
 // Mean of the truncated Gaussian in lambda (support lambda <= Z, variance
 // 9cZ, eq. truncated_gaussian) that satisfies the mean-injection constraint.
@@ -783,23 +786,80 @@ hipError_t launch_mix(const MemberDev *const *members_host, const double *lambda
     return launch_mix_table(members_host, lambdas, count, h, c, Z, mode, q_sigma, nullptr, 0, 0.0, 0.0, out, scratch, s);
 }
 
+// Host side of the member table: pointers to each member's sums, its lambda,
+// and zeros for what the kernels fill in (every entry the kernels read is
+// written here, so a table left by an earlier call is never read).
+static void fill_mix_table(MixIn *tbl, const MemberDev *const *members_host, const double *lambdas, int count) {
+    for (int i = 0; i < count; i++) {
+        tbl[i].counts = members_host[i]->counts;
+        tbl[i].moments = members_host[i]->moments;
+        tbl[i].lambda = lambdas[i];
+        tbl[i].ntot = 0.0; tbl[i].w = 0.0; tbl[i].order = 0; tbl[i].pad = 0;
+    }
+}
+
+// Copy the host table into the device table `mi` and enqueue the mixture.
+// Returns after the copy has completed (the host table may then be reused);
+// the kernels read `mi` asynchronously on `s`.
+static hipError_t run_mix(const MixIn *tbl, MixIn *mi, int count, const ens_hist_desc &h, double c, double Z,
+                          int mode, double q_sigma, const double *table, int table_len, double lam0, double dlam,
+                          double *out, hipStream_t s);
+
 hipError_t launch_mix_table(const MemberDev *const *members_host, const double *lambdas, int count,
                             const ens_hist_desc &h, double c, double Z, int mode, double q_sigma, const double *table,
                             int table_len, double lam0, double dlam, double *out, void *scratch, hipStream_t s) {
     if (count <= 0 || count > kMaxMix || !scratch) return hipErrorInvalidValue;
     if (mode == 4 && (!table || table_len < 2 || !(dlam > 0))) return hipErrorInvalidValue;
-    const HistGeom hg = make_hist_geom(h);
     std::vector<MixIn> tmp(count);
-    for (int i = 0; i < count; i++) {
-        tmp[i].counts = members_host[i]->counts;
-        tmp[i].moments = members_host[i]->moments;
-        tmp[i].lambda = lambdas[i];
-        tmp[i].ntot = 0.0; tmp[i].w = 0.0; tmp[i].order = 0; tmp[i].pad = 0;
-    }
-    MixIn *mi = reinterpret_cast<MixIn *>(scratch);
-    hipError_t e = hipMemcpyAsync(mi, tmp.data(), sizeof(MixIn) * count, hipMemcpyHostToDevice, s);
+    fill_mix_table(tmp.data(), members_host, lambdas, count);
+    return run_mix(tmp.data(), reinterpret_cast<MixIn *>(scratch), count, h, c, Z, mode, q_sigma, table, table_len,
+                   lam0, dlam, out, s);
+}
+
+// ------------------------------------------------ mixture without allocation
+// For callers that cannot allocate device memory: the device member table is
+// this file-scope array, one copy per GPU, held until the process ends.  In
+// host code `scratch` names a host-side stand-in, not the device array: its
+// device address is taken once per device with hipGetSymbolAddress (at
+// context creation, with that device current) and only that address is used.
+static __device__ __align__(256) unsigned char scratch[kMaxMix * sizeof(MixIn)];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_static_mu;                    // guards the two tables below
+static void *g_static_dev[kMaxDevices];           // device address of `scratch`, per device
+static MixIn g_static_host[kMaxMix];              // host staging of the member table
+
+hipError_t mix_static_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (g_static_dev[device]) return hipSuccess;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
     if (e != hipSuccess) return e;
-    e = hipStreamSynchronize(s);       // tmp is freed on return
+    g_static_dev[device] = p;
+    return hipSuccess;
+}
+
+size_t mix_static_bytes() { return sizeof(scratch); }
+
+hipError_t launch_mix_static(int device, const MemberDev *const *members_host, const double *lambdas, int count,
+                             const ens_hist_desc &h, double c, double Z, int mode, double q_sigma, double *out,
+                             hipStream_t s) {
+    if (count <= 0 || count > kMaxMix || device < 0 || device >= kMaxDevices) return hipErrorInvalidValue;
+    std::lock_guard<std::mutex> lk(g_static_mu);  // the host staging table is shared
+    MixIn *mi = reinterpret_cast<MixIn *>(g_static_dev[device]);
+    if (!mi) return hipErrorNotInitialized;
+    fill_mix_table(g_static_host, members_host, lambdas, count);
+    return run_mix(g_static_host, mi, count, h, c, Z, mode, q_sigma, nullptr, 0, 0.0, 0.0, out, s);
+}
+
+static hipError_t run_mix(const MixIn *tbl, MixIn *mi, int count, const ens_hist_desc &h, double c, double Z,
+                          int mode, double q_sigma, const double *table, int table_len, double lam0, double dlam,
+                          double *out, hipStream_t s) {
+    const HistGeom hg = make_hist_geom(h);
+    hipError_t e = hipMemcpyAsync(mi, tbl, sizeof(MixIn) * count, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(s);       // the host table may be reused on return
     if (e != hipSuccess) return e;
     k_mix_prep<<<count, 256, 0, s>>>(mi, hg.off_le);
     const double mu3 = (mode == 3 && Z > 0.0) ? truncated_mean(c, Z) : 0.0;

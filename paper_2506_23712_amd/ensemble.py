@@ -319,11 +319,15 @@ class Ensemble:
         ms = members if members is not None else self.members
         check(lib().ens_accumulate_stats(self.ctx, _ids(ms), len(ms), _stream_ptr()))
 
-    def mix(self, c: float, Z: float, mode: int = 0, q_sigma: float = 1.0, members=None) -> dict:
+    def mix(self, c: float, Z: float, mode: int = 0, q_sigma: float = 1.0, members=None,
+            noalloc: bool = False) -> dict:
+        """Gaussian mixture of the members' statistics; noalloc=True uses the
+        entry point whose member table is the library's static device array
+        (the output tensor is still allocated here, by the caller)."""
         ms = members if members is not None else self.members
         out = self._mix_out(len(ms))
-        check(lib().ens_mix(self.ctx, _ids(ms), len(ms), c, Z, mode, q_sigma, ctypes.c_void_p(out.data_ptr()),
-                            _stream_ptr()))
+        fn = lib().ens_mix_noalloc if noalloc else lib().ens_mix
+        check(fn(self.ctx, _ids(ms), len(ms), c, Z, mode, q_sigma, ctypes.c_void_p(out.data_ptr()), _stream_ptr()))
         return self._split_mix(out, len(ms))
 
     def mix_table(self, pdf: torch.Tensor, lam0: float, dlam: float, members=None) -> dict:

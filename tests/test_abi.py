@@ -51,6 +51,7 @@ def test_argument_validation_without_a_gpu(L):
     assert L.ens_spectrum(None, 0, 8, None, None) == _lib.ENS_E_INVALID
     assert L.ens_lambda_pdf_from_cf(None, 64, 0.0, 0.1, None, None) == _lib.ENS_E_INVALID
     assert L.ens_mix_table(None, None, 0, None, 64, 0.0, 0.1, None, None) == _lib.ENS_E_INVALID
+    assert L.ens_mix_noalloc(None, None, 0, 0.023, 1.0, 0, 1.0, None, None) == _lib.ENS_E_INVALID
     assert L.ens_scale_gap(None, None, 0, 100.0, None, None, None) == _lib.ENS_E_INVALID
     assert L.ens_member_refine(None, 0, 1, None) == _lib.ENS_E_INVALID
     assert L.ens_member_set_diag(None, 0, None, None) == _lib.ENS_E_INVALID
