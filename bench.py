@@ -236,6 +236,131 @@ def diagnostics(ens, torch, reps=20):
     return out
 
 
+def tail_probs(counts_log, lo, hi, nbins, n_samples, xs):
+    """P(X >= 10^b) from a log10 histogram (counts per bin, then under, over,
+    nan), at the bin edges nearest to log10 of each threshold in `xs`."""
+    import numpy as np
+    c = np.asarray(counts_log, dtype=np.float64)
+    w = (hi - lo) / nbins
+    out = {}
+    for x in xs:
+        b = int(round((math.log10(x) - lo) / w))
+        out[f"{x:g}"] = float((c[b:nbins].sum() + c[nbins + 1]) / n_samples)
+    return out
+
+
+def mixed_tail_probs(pdf_log, lo, hi, nbins, xs):
+    """The same from a mixed log10 PDF (density per log10 unit)."""
+    import numpy as np
+    p = np.asarray(pdf_log, dtype=np.float64)
+    w = (hi - lo) / nbins
+    return {f"{x:g}": float(p[int(round((math.log10(x) - lo) / w)):].sum() * w) for x in xs}
+
+
+def config5(ens, torch, args):
+    """Single member 1024^3 FP32, band |m| <= 2.5, nu set for R_lambda ~ 280,
+    500 steps with statistics every 10 into 512-bin log10 histograms of
+    eps/<eps> and omega^2/<omega^2>; beside it the 96-member FP32 set run to a
+    developed state and mixed (c = 0.023) at the scale gap Z whose reference
+    R_lambda is the 1024^3 member's.  nu is calibrated from the 96-member set:
+    R_lambda = A e^(lambda/6) fitted over lambda >= 0, R_lambda ~ nu^(-1/2) at
+    fixed injection and band, so nu = nu_96 (A / 280)^2."""
+    import numpy as np
+    xs = (3, 10, 30, 100, 300, 1000, 3000)
+    nu96 = 0.03395
+    t_start = time.perf_counter()
+    log = lambda msg: print(f"[config5 {time.perf_counter() - t_start:7.1f}s] {msg}", file=sys.stderr, flush=True)
+    h96 = hist_for(ens, nu96)
+    E96 = ens.Ensemble(hist=h96, graphs=True)
+    ms96 = [E96.add_member(sp) for sp in ens96_specs(ens)]
+    E96.autotune()
+    for k in range(args.c5_ens_transient // 500):
+        E96.step(500)
+        torch.cuda.synchronize()
+        log(f"ens96 transient {500 * (k + 1)} steps")
+    for m in ms96:
+        m.reset_stats()
+    for k in range(args.c5_ens_measure // 10):
+        E96.step(10)
+        E96.accumulate_stats()
+        if (k + 1) % 50 == 0:
+            torch.cuda.synchronize()
+            log(f"ens96 measured {10 * (k + 1)} steps")
+    gap = E96.scale_gap(280.0)
+    A = gap["prefactor"]
+    nu = nu96 * (A / 280.0) ** 2
+    log(f"ens96: R_lambda(0) fit A = {A:.2f}; 1024^3 nu = {nu:.4e}")
+    # The large scales develop over several integral times, which the 1024^3
+    # grid would spend minutes on: the member starts on 256^3 (the same nu,
+    # under-resolved), is refined onto 512^3 and then onto 1024^3 (spectral
+    # refinement keeps every mode), and each grid runs long enough for its
+    # new small scales to fill in.
+    E = ens.Ensemble(hist=hist_for(ens, nu), graphs=True)
+    chain = [(256, args.c5_coarse_steps), (512, args.c5_mid_steps), (1024, args.c5_transient)]
+    prev = None
+    for n, steps in chain:
+        spec = ens.MemberSpec(n=n, nu=nu, eps_ref=1.0, lam=0.0, kf_lo=0.0, kf_hi=2.5, dt=0.0, cfl=0.5,
+                              precision="fp32", seed=23712)
+        m = E.add_member(spec)
+        if prev is not None:
+            m.refine_from(prev)
+        for k in range(0, steps, 500):
+            E.step(min(500, steps - k), members=[m])
+            torch.cuda.synchronize()
+            d = m.diag()
+            log(f"{n}^3 transient {min(k + 500, steps)} steps: t {d['t']:.3f} E {d['E']:.4f} D {d['D']:.4f} "
+                f"R_lambda {d['rlambda']:.1f} kmax_eta {d['kmax_eta']:.3f}")
+            if d["diverged"]:
+                raise RuntimeError(f"config5: the {n}^3 stage diverged")
+        prev = m
+    E.autotune(members=[m])
+    log("1024^3 variants tuned")
+    m.reset_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.c5_steps):
+        E.step(1, members=[m])
+        if (i + 1) % 10 == 0:
+            E.accumulate_stats(members=[m])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    d = m.diag()
+    own = E.scale_gap(280.0, members=[m])["rlambda"][0]   # from the snapshot-averaged E and D
+    counts, mom, npts = m.stats()
+    h = E.hist
+    hg = {"qr": h.qr_bins ** 2 + 3, "le": h.log_bins + 3}
+    c = counts.numpy()
+    le = c[hg["qr"]:hg["qr"] + hg["le"]]
+    lw = c[hg["qr"] + hg["le"]:hg["qr"] + 2 * hg["le"]]
+    mean_eps, mean_ens = float(mom[12] / npts), float(mom[16] / npts)
+    # thresholds in units of each member's own mean (eps_ref = 1 = injection; Omega* = omega^2 nu / eps_ref)
+    member = {"eps": tail_probs(le, h.log10_lo, h.log10_hi, h.log_bins, npts, [x * mean_eps for x in xs]),
+              "enstrophy": tail_probs(lw, h.log10_lo, h.log10_hi, h.log_bins, npts, [x * mean_ens for x in xs])}
+    Z = E96.scale_gap(own)["Z"]
+    mix = E96.mix(0.023, Z, mode=0)
+    pred = {"eps": mixed_tail_probs(mix["log_eps"].numpy(), h96.log10_lo, h96.log10_hi, h96.log_bins, xs),
+            "enstrophy": mixed_tail_probs(mix["log_ens"].numpy(), h96.log10_lo, h96.log10_hi, h96.log_bins, xs)}
+    pts = 1024 ** 3
+    out = {"metric": "grid-pt RK steps/s (single 1024^3 FP32 member)", "value": round(pts * args.c5_steps / (t1 - t0), 1),
+           "unit": "grid-pt RK steps/s", "n_gpus": 1, "steps": args.c5_steps, "warmup": args.c5_transient,
+           "ms_per_step": round(1e3 * (t1 - t0) / args.c5_steps, 3), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic (seeded random solenoidal field developed on "
+           f"256^3 for {args.c5_coarse_steps} steps, refined to 512^3 for {args.c5_mid_steps} and to 1024^3 for "
+           f"{args.c5_transient} steps before timing)",
+           "config": {"workload": "single1024_fp32", "members": 1, "grid_points_per_step": pts, "stats_every": 10,
+                      "nu": nu, "band": "|m| <= 2.5", "cfl": 0.5},
+           "member": {"t_end": d["t"], "rlambda_snapshot_mean": own, "rlambda_last": d["rlambda"],
+                      "kmax_eta_last": d["kmax_eta"], "snapshots": int(mom[28]), "samples": int(npts),
+                      "mean_eps": mean_eps, "mean_enstrophy_nu": mean_ens, "tail_P(X>=x<X>)": member},
+           "ens96_mixture": {"transient_steps": args.c5_ens_transient, "measured_steps": args.c5_ens_measure,
+                             "rlambda_fit_A": A, "Z": Z, "c": 0.023, "weights": "Gaussian, open end bins",
+                             "tail_P(X>=x)": pred, "mean_eps": mix["mean_eps"], "mean_enstrophy_nu": mix["mean_ens"]},
+           "wall_s": round(time.perf_counter() - t_start, 1)}
+    E.close()
+    E96.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -244,9 +369,22 @@ def main():
     ap.add_argument("--stats-every", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--only", choices=["ens96_mixed_fp32", "single256_fp64", "ens48_128_fp64"], default=None,
-                    help="one workload; ens48_128_fp64 (the 48-member 128^3 FP64 set of the ensemble driver) "
-                         "runs only when named")
+    ap.add_argument("--only", choices=["ens96_mixed_fp32", "single256_fp64", "ens48_128_fp64", "single1024_fp32"],
+                    default=None,
+                    help="one workload; ens48_128_fp64 (the 48-member 128^3 FP64 set of the ensemble driver) and "
+                         "single1024_fp32 (one 1024^3 FP32 member at R_lambda ~ 280 with tail statistics, beside "
+                         "the developed 96-member set's mixture) run only when named")
+    ap.add_argument("--c5-coarse-steps", type=int, default=3000,
+                    help="single1024_fp32: steps of the member on 256^3 before refinement")
+    ap.add_argument("--c5-mid-steps", type=int, default=1000,
+                    help="single1024_fp32: steps on 512^3 before the second refinement")
+    ap.add_argument("--c5-transient", type=int, default=2500,
+                    help="single1024_fp32: steps on 1024^3 before the timed steps")
+    ap.add_argument("--c5-steps", type=int, default=500, help="single1024_fp32: timed steps (statistics every 10)")
+    ap.add_argument("--c5-ens-transient", type=int, default=2500,
+                    help="single1024_fp32: steps of the 96-member set before its statistics")
+    ap.add_argument("--c5-ens-measure", type=int, default=2500,
+                    help="single1024_fp32: steps of the 96-member set with statistics every 10")
     ap.add_argument("--develop", type=int, default=0, metavar="STEPS",
                     help="step the workload this many more steps before the timed statistics snapshot")
     ap.add_argument("--diagnostics", action="store_true",
@@ -273,6 +411,9 @@ def main():
         print(json.dumps({"diagnostics_256": diagnostics(ens, torch), "peak_GB/s": HBM_PEAK_GBS}))
         return
 
+    if args.only == "single1024_fp32":
+        print(json.dumps(config5(ens, torch, args)))
+        return
     res = {}
     if args.only in (None, "ens96_mixed_fp32"):
         res["ens"] = run_workload(ens, torch, "ens96_mixed_fp32", ens96_specs(ens), args.steps, args.warmup,

@@ -207,10 +207,21 @@ template <typename P> using LdsT = typename V2<P>::T;
 // write LDS directly (global_load_lds), which the pipelined passes keep in
 // flight across the transforms.
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
-// Barrier between transform stages: __syncthreads() (SB = false) or
-// lds_barrier() (SB = true, for passes that keep direct-to-LDS loads in flight).
-template <bool SB> __device__ __forceinline__ void stage_barrier() {
-    if constexpr (SB) lds_barrier();
+// Ordering of LDS accesses of one wave: the LDS executes a wave's operations
+// in issue order, so lanes of one wave exchanging values through LDS need no
+// hardware wait; this only keeps the compiler from moving LDS accesses
+// across the point (it emits no instruction).
+__device__ __forceinline__ void wave_fence() { asm volatile("" ::: "memory"); }
+// Wait until this wave's LDS reads have returned (before memory they read
+// is handed to a direct-to-LDS load, which is not ordered with them).
+__device__ __forceinline__ void lds_wait() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+// Barrier between transform stages: __syncthreads() (SB = 0), lds_barrier()
+// (SB = 1, for passes that keep direct-to-LDS loads in flight), or none but a
+// compiler fence (SB = 2, for transforms whose lines belong to one wave).
+template <int SB> __device__ __forceinline__ void stage_barrier() {
+    if constexpr (SB == 2) wave_fence();
+    else if constexpr (SB == 1) lds_barrier();
     else __syncthreads();
 }
 
@@ -229,6 +240,20 @@ template <typename P, int T> __device__ __forceinline__ int xslot(int p, int l) 
     else return p * T + l;
 }
 
+// Layouts of the exchanges: LDS slot of (position p, line l).
+// RowLay: [position][line] with T lines, lines fastest (xslot).
+template <typename P, int T> struct RowLay {
+    __device__ static __forceinline__ int slot(int p, int l) { return xslot<P, T>(p, l); }
+};
+// WaveLay: one row of N slots per line (the lines of a wave are its own), the
+// position XOR-ed within blocks of G = 128 bytes of complex values by its
+// block index: lanes of a line at positions G t + m (stride G) and at
+// positions t + G m (consecutive) both spread over all banks.
+template <typename P, int N> struct WaveLay {
+    static constexpr int G = 128 / (int)sizeof(LdsT<P>);
+    __device__ static __forceinline__ int slot(int p, int l) { return l * N + (p ^ ((p / G) % G)); }
+};
+
 template <typename P> __device__ __forceinline__ void lds_put(LdsT<P> *lds, int i, Cx<P> v) {
     LdsT<P> x; x.x = v.re; x.y = v.im; lds[i] = x;
 }
@@ -237,7 +262,7 @@ template <typename P> __device__ __forceinline__ Cx<P> lds_get(const LdsT<P> *ld
 }
 
 // One forward-flow stage s >= 1: gather from LDS, twiddle, butterfly.
-template <typename P, int N, int E, int T, int DIR, int s, class TW>
+template <typename P, int N, int E, int T, int DIR, int s, class LY, class TW>
 __device__ __forceinline__ void stage_gather(Cx<P> *v, const LdsT<P> *lds, int l, int t, const TW &tw) {
     constexpr int R = stage_radix(N, E, s), NS = stage_span(N, E, s), M = N / E;
 #pragma unroll
@@ -245,7 +270,7 @@ __device__ __forceinline__ void stage_gather(Cx<P> *v, const LdsT<P> *lds, int l
         const int j = t + M * b, k = j % NS;
 #pragma unroll
         for (int m = 0; m < R; m++) {
-            Cx<P> x = lds_get<P>(lds, xslot<P, T>(j + m * (N / R), l));
+            Cx<P> x = lds_get<P>(lds, LY::slot(j + m * (N / R), l));
             if (m > 0) x = cmul(x, tw_at<DIR, s>(tw, b, m, m * k * (N / (NS * R))));
             v[b * R + m] = x;
         }
@@ -254,35 +279,36 @@ __device__ __forceinline__ void stage_gather(Cx<P> *v, const LdsT<P> *lds, int l
 }
 
 // Scatter the outputs of stage s to LDS.
-template <typename P, int N, int E, int T, int s>
+template <typename P, int N, int E, int T, int s, class LY>
 __device__ __forceinline__ void stage_scatter(const Cx<P> *v, LdsT<P> *lds, int l, int t) {
     constexpr int R = stage_radix(N, E, s), NS = stage_span(N, E, s), M = N / E;
 #pragma unroll
     for (int b = 0; b < E / R; b++) {
         const int j = t + M * b, k = j % NS;
 #pragma unroll
-        for (int m = 0; m < R; m++) lds_put<P>(lds, xslot<P, T>((j / NS) * NS * R + k + m * NS, l), v[b * R + m]);
+        for (int m = 0; m < R; m++) lds_put<P>(lds, LY::slot((j / NS) * NS * R + k + m * NS, l), v[b * R + m]);
     }
 }
 
-template <typename P, int N, int E, int T, int DIR, int s, bool SB, class TW>
+template <typename P, int N, int E, int T, int DIR, int s, int SB, class LY, class TW>
 __device__ __forceinline__ void run_stages(Cx<P> *v, LdsT<P> *lds, int l, int t, const TW &tw) {
     if constexpr (s < num_stages(N, E)) {
         stage_barrier<SB>();
-        stage_scatter<P, N, E, T, s - 1>(v, lds, l, t);
+        stage_scatter<P, N, E, T, s - 1, LY>(v, lds, l, t);
         stage_barrier<SB>();
-        stage_gather<P, N, E, T, DIR, s>(v, lds, l, t, tw);
-        run_stages<P, N, E, T, DIR, s + 1, SB>(v, lds, l, t, tw);
+        stage_gather<P, N, E, T, DIR, s, LY>(v, lds, l, t, tw);
+        run_stages<P, N, E, T, DIR, s + 1, SB, LY>(v, lds, l, t, tw);
     }
 }
 
 // Forward-flow transform.  All threads of the workgroup must call it (it
-// contains barriers).  LDS: N*T elements of V2<P>.
-template <typename P, int N, int E, int T, int DIR, bool SB = false, class TW>
+// contains barriers; with SB = 2 all lanes of the wave).  LDS: N*T elements
+// of V2<P> (RowLay), or N per line of the wave (WaveLay).
+template <typename P, int N, int E, int T, int DIR, int SB = 0, class LY = RowLay<P, T>, class TW>
 __device__ __forceinline__ void line_fft(Cx<P> *v, LdsT<P> *lds, int l, int t, const TW &tw) {
     static_assert(N % E == 0 && N >= E, "line length must be a multiple of E");
     dft<E, DIR>(v);                       // stage 0: span 1, no twiddles
-    run_stages<P, N, E, T, DIR, 1, SB>(v, lds, l, t, tw);
+    run_stages<P, N, E, T, DIR, 1, SB, LY>(v, lds, l, t, tw);
 }
 
 // ---- transposed flow (stages in reverse order, twiddles after the butterflies)
@@ -300,43 +326,43 @@ __device__ __forceinline__ void stageT_compute(Cx<P> *v, int t, const TW &tw) {
     }
 }
 // after stage s (transposed) values belong at its input positions j + m N/R
-template <typename P, int N, int E, int T, int s>
+template <typename P, int N, int E, int T, int s, class LY>
 __device__ __forceinline__ void stageT_scatter(const Cx<P> *v, LdsT<P> *lds, int l, int t) {
     constexpr int R = stage_radix(N, E, s), M = N / E;
 #pragma unroll
     for (int b = 0; b < E / R; b++) {
         const int j = t + M * b;
 #pragma unroll
-        for (int m = 0; m < R; m++) lds_put<P>(lds, xslot<P, T>(j + m * (N / R), l), v[b * R + m]);
+        for (int m = 0; m < R; m++) lds_put<P>(lds, LY::slot(j + m * (N / R), l), v[b * R + m]);
     }
 }
 // stage s (transposed) reads from its output positions
-template <typename P, int N, int E, int T, int s>
+template <typename P, int N, int E, int T, int s, class LY>
 __device__ __forceinline__ void stageT_gather(Cx<P> *v, const LdsT<P> *lds, int l, int t) {
     constexpr int R = stage_radix(N, E, s), NS = stage_span(N, E, s), M = N / E;
 #pragma unroll
     for (int b = 0; b < E / R; b++) {
         const int j = t + M * b, k = j % NS;
 #pragma unroll
-        for (int m = 0; m < R; m++) v[b * R + m] = lds_get<P>(lds, xslot<P, T>((j / NS) * NS * R + k + m * NS, l));
+        for (int m = 0; m < R; m++) v[b * R + m] = lds_get<P>(lds, LY::slot((j / NS) * NS * R + k + m * NS, l));
     }
 }
 
-template <typename P, int N, int E, int T, int DIR, int s, bool SB, class TW>
+template <typename P, int N, int E, int T, int DIR, int s, int SB, class LY, class TW>
 __device__ __forceinline__ void run_stagesT(Cx<P> *v, LdsT<P> *lds, int l, int t, const TW &tw) {
     stageT_compute<P, N, E, T, DIR, s>(v, t, tw);
     if constexpr (s > 0) {
         stage_barrier<SB>();
-        stageT_scatter<P, N, E, T, s>(v, lds, l, t);
+        stageT_scatter<P, N, E, T, s, LY>(v, lds, l, t);
         stage_barrier<SB>();
-        stageT_gather<P, N, E, T, s - 1>(v, lds, l, t);
-        run_stagesT<P, N, E, T, DIR, s - 1, SB>(v, lds, l, t, tw);
+        stageT_gather<P, N, E, T, s - 1, LY>(v, lds, l, t);
+        run_stagesT<P, N, E, T, DIR, s - 1, SB, LY>(v, lds, l, t, tw);
     }
 }
 
-template <typename P, int N, int E, int T, int DIR, bool SB = false, class TW>
+template <typename P, int N, int E, int T, int DIR, int SB = 0, class LY = RowLay<P, T>, class TW>
 __device__ __forceinline__ void line_fft_T(Cx<P> *v, LdsT<P> *lds, int l, int t, const TW &tw) {
-    run_stagesT<P, N, E, T, DIR, num_stages(N, E) - 1, SB>(v, lds, l, t, tw);
+    run_stagesT<P, N, E, T, DIR, num_stages(N, E) - 1, SB, LY>(v, lds, l, t, tw);
 }
 
 }  // namespace ens

@@ -663,6 +663,221 @@ __global__ void __launch_bounds__((XCfg<P, N, EV>::NTH), (XCfg<P, N, EV>::MINB))
     }
 }
 
+// ------------------------------------------------------ wave-private x pass
+// The streamed x pass with every workgroup one wave: a tile is the R = 64 / M
+// rows whose transforms the wave's lanes hold (lane = row * M + thread), so
+// every exchange of the transforms stays inside the wave.  The LDS executes
+// one wave's operations in issue order, so no exchange needs an s_barrier or
+// an LDS wait, only a compiler fence (stage barrier kind 2); rows are XOR
+// swizzled per 128-byte block (WaveLay) so that the strided and the
+// consecutive exchange patterns both spread over all banks.  The wave copies
+// its own inputs (direct-to-LDS) and stores its own outputs, so the only
+// waits left are the exact vector-memory counts of the copies and an LDS wait
+// before a staging buffer is handed back to the copies.
+// Whether the wave-private x pass has a valid tile for (N, E, complex size):
+// a line within one wave, whole 16-byte vectors per output tile, at least one
+// wave-sized copy per field and a vector-memory count that fits its counter.
+constexpr bool xwave_ok(int N, int E, int CS) {
+    const int M = N / (E > N ? N : E), K = N / 3, CPV = 16 / CS;
+    if (M > 64 || 64 % M != 0) return false;
+    const int R = 64 / M, RQ = (K + 1 + CPV - 1) / CPV * CPV;
+    const int RV = R * (RQ / CPV), RWO = R * (K + 1);
+    if (RWO % CPV != 0 || RV < 64 || RWO / CPV < 64) return false;
+    const int D3 = 3 * ((RV + 63) / 64), S = 3 * ((RWO / CPV + 63) / 64);
+    return D3 + S < 64;
+}
+
+template <typename P, int N, int E_> struct XWCfg {
+    static constexpr int K = N / 3, E = E_ > N ? N : E_, M = N / E;
+    static constexpr int R = 64 / M;                           // rows per tile (one wave)
+    static constexpr int CS = (int)sizeof(Cx<P>), CPV = 16 / CS;
+    static constexpr int PX = kx_pitch(K, CS);
+    static constexpr int RQ = (K + 1 + CPV - 1) / CPV * CPV;   // staged row length (whole vectors)
+    static constexpr bool REGTW = sizeof(P) == 4;               // FP32: twiddles in registers
+    static constexpr int NTW = REGTW ? 1 : twiddle_span(N, E);
+    static constexpr int RW = R * RQ, RVR = RQ / CPV, RV = R * RVR;
+    static constexpr int RWO = R * (K + 1), RVO = RWO / CPV;
+    static constexpr int D3 = dma_tile3_ops<RV, 64>();          // copies per staging buffer
+    static constexpr int S = dma_tile3_ops<RVO, 64>();          // 16-byte stores per tile
+    static constexpr int XL = N * R > 3 * RWO ? N * R : 3 * RWO;
+    static constexpr int TILES = N * N / R;
+    static constexpr long long LDS_BYTES = (6LL * RW + XL + NTW) * CS + 64;
+    // waves per SIMD the register budget is cut for: what the LDS allows (one
+    // wave per workgroup, four SIMDs per compute unit), at most 4
+    static constexpr int WPS = (int)(163840 / ((LDS_BYTES + 511) / 512 * 512)) / 4;
+    static constexpr int MINW = WPS < 1 ? 1 : (WPS > 4 ? 4 : WPS);
+    static_assert(M <= 64 && 64 % M == 0, "a line must fit one wave");
+    static_assert(PX % CPV == 0 && RWO % CPV == 0 && RV >= 64 && RVO >= 64 && D3 + S < 64, "x-pass tile shape");
+};
+
+template <typename P, int N, int EV>
+__global__ void __launch_bounds__(64, (XWCfg<P, N, EV>::MINW)) k_xpass_wave(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw, int stage) {
+    using C = XWCfg<P, N, EV>;
+    using LY = WaveLay<P, N>;
+    constexpr int E = C::E, M = C::M, R = C::R, K = C::K, RW = C::RW, RQ = C::RQ;
+    constexpr int PX = C::PX, RWO = C::RWO, RVO = C::RVO;
+    constexpr long long FSB = (long long)N * N * PX * C::CS;         // bytes per input field
+    constexpr long long FSBO = (long long)N * N * (K + 1) * C::CS;   // bytes per output field
+    __shared__ __attribute__((aligned(16))) LdsT<P> slot0[3 * RW];
+    __shared__ __attribute__((aligned(16))) LdsT<P> slot1[3 * RW];
+    __shared__ __attribute__((aligned(16))) LdsT<P> lds[C::XL];
+    __shared__ Cx<P> twl[C::NTW];
+    unsigned chunk, mem_i;
+    xcd_tile(chunk, mem_i);
+    const MemberDev &md = mems[mem_i];
+    const int t0 = (int)((long long)chunk * C::TILES / gridDim.x);
+    const int t1 = (int)((long long)(chunk + 1) * C::TILES / gridDim.x);
+    if (t0 >= t1) return;                                     // uniform over the wave
+    const int t = (int)threadIdx.x % M, l = (int)threadIdx.x / M;
+    TwRegs<P, N, E> twr;
+    if constexpr (C::REGTW) twr.load(tw, t);
+    else for (int i = (int)threadIdx.x; i < C::NTW; i += 64) twl[i] = tw[i];
+    wave_fence();
+    const auto &twx = [&]() -> const auto & {
+        if constexpr (C::REGTW) return twr;
+        else return twl;
+    }();
+    const char *inb = (const char *)md.bufB;
+    char *outb = (char *)md.bufA;
+    auto request = [&](LdsT<P> *dst, int tile, int f0) {      // fields f0..f0+2 of the tile's R rows
+        dma_rows3<C::RVR, PX * C::CS, R, 64>(dst, inb + (long long)f0 * FSB + (long long)tile * R * PX * C::CS, FSB);
+    };
+    // packed two-for-one spectrum of fields (fa, fb), as in the streamed x pass
+    auto gather = [&](Cx<P> *v, const LdsT<P> *fa, const LdsT<P> *fb) {
+#pragma unroll
+        for (int m = 0; m < E; m++) {
+            const int n = t + M * m;
+            const int r = l * RQ;
+            if (M * m > K && M * m + M - 1 < N - K) {
+                v[m] = czero<P>();
+            } else if (m > 0 && M * m + M - 1 <= K) {
+                const Cx<P> A = lds_get<P>(fa, r + n), B = lds_get<P>(fb, r + n);
+                v[m] = {A.re - B.im, A.im + B.re};
+            } else if (M * m >= N - K) {
+                const Cx<P> A = lds_get<P>(fa, r + N - n), B = lds_get<P>(fb, r + N - n);
+                v[m] = {A.re + B.im, B.re - A.im};
+            } else {
+                const bool lo = n <= K, hi = n >= N - K;
+                const int kx = lo ? n : N - n;
+                Cx<P> A = czero<P>(), B = czero<P>();
+                if (lo || hi) { A = lds_get<P>(fa, r + kx); B = lds_get<P>(fb, r + kx); }
+                if (n == 0) v[m] = {A.re, B.re};
+                else if (lo) v[m] = {A.re - B.im, A.im + B.re};
+                else v[m] = {A.re + B.im, B.re - A.im};
+            }
+        }
+    };
+    P umx = P(0);
+    Cx<P> v[E];
+    typedef float F4 __attribute__((ext_vector_type(4)));
+    const unsigned lane16 = (threadIdx.x & 63u) * 16u;
+    // the tile's outputs staged in lds ([3][R][K+1], contiguous in the output)
+    // leave in wave-sized chunks of 64 vectors, the last chunk of a field moved
+    // back onto its end
+    auto store_tile = [&](int tile, bool zero) {
+        constexpr int NCF = (RVO + 63) / 64, NCH = 3 * NCF;
+#pragma unroll
+        for (int c = 0; c < NCH; c++) {
+            const int f = c / NCF, q = c - f * NCF;
+            const int st = q * 64 < RVO - 64 ? q * 64 : RVO - 64;
+            const F4 x = zero ? F4{0.f, 0.f, 0.f, 0.f} : *(const F4 *)((const char *)lds + (f * RVO + st) * 16 + lane16);
+            ENS_GLOBAL char *dst = (ENS_GLOBAL char *)outb + f * FSBO + (long long)tile * RWO * C::CS + st * 16;
+            *(ENS_GLOBAL F4 *)(dst + lane16) = x;
+        }
+    };
+    static_assert(C::S == 3 * ((RVO + 63) / 64), "store count");
+    // Wait accounting as in the streamed x pass (vector-memory operations
+    // complete in issue order; requests are unconditional, the prologue writes
+    // zeros to the first tile's output to reproduce the loop's order).
+    request(slot0, t0, 0);
+    request(slot1, t0, 3);
+    store_tile(t0, true);
+    wait_vm<C::D3 + C::S>();                                   // fields 0-2 of the first tile
+    wave_fence();
+    gather(v, slot0, slot0 + RW);
+    for (int tile = t0; tile < t1; tile++) {
+        const bool more = tile + 1 < t1;
+        P ph[6][E];
+        line_fft<P, N, E, R, +1, 2, LY>(v, lds, l, t, twx);
+#pragma unroll
+        for (int s = 0; s < E; s++) { ph[0][s] = v[s].re; ph[1][s] = v[s].im; }
+        wait_vm<C::S>();                                       // fields 3-5
+        wave_fence();
+        gather(v, slot0 + 2 * RW, slot1);
+        lds_wait();                                            // slot0 read
+        request(slot0, more ? tile + 1 : tile, 0);
+        line_fft<P, N, E, R, +1, 2, LY>(v, lds, l, t, twx);
+#pragma unroll
+        for (int s = 0; s < E; s++) { ph[2][s] = v[s].re; ph[3][s] = v[s].im; }
+        gather(v, slot1 + RW, slot1 + 2 * RW);
+        lds_wait();                                            // slot1 read
+        request(slot1, more ? tile + 1 : tile, 3);
+        line_fft<P, N, E, R, +1, 2, LY>(v, lds, l, t, twx);
+#pragma unroll
+        for (int s = 0; s < E; s++) { ph[4][s] = v[s].re; ph[5][s] = v[s].im; }
+        // ph: 0 u_x, 1 u_y, 2 u_z, 3 omega_x, 4 omega_y, 5 omega_z
+        if (stage == 0) {
+#pragma unroll
+            for (int s = 0; s < E; s++) {
+                const P a = fabs(ph[0][s]) + fabs(ph[1][s]) + fabs(ph[2][s]);
+                umx = a > umx ? a : umx;
+            }
+        }
+        Cx<P> d1[E], d2[E];
+#pragma unroll
+        for (int s = 0; s < E; s++) {
+            d1[s] = {ph[1][s] * ph[5][s] - ph[2][s] * ph[4][s], ph[2][s] * ph[3][s] - ph[0][s] * ph[5][s]};
+            d2[s] = {ph[0][s] * ph[4][s] - ph[1][s] * ph[3][s], P(0)};
+        }
+        line_fft_T<P, N, E, R, -1, 2, LY>(d1, lds, l, t, twx);        // d1[m] = D1[t + M m]
+        line_fft_T<P, N, E, R, -1, 2, LY>(d2, lds, l, t, twx);
+        wave_fence();
+#pragma unroll
+        for (int m = 0; m < E; m++) lds_put<P>(lds, LY::slot(t + M * m, l), d1[m]);
+        wave_fence();
+        // split D1 into the x-spectra of n_x and n_y
+        Cx<P> ox[E], oy[E];
+#pragma unroll
+        for (int m = 0; m < E; m++) {
+            const int k = t + M * m;
+            if (M * m <= K && (M * m + M - 1 <= K || k <= K)) {
+                const Cx<P> a = d1[m];
+                const Cx<P> b = lds_get<P>(lds, LY::slot((N - k) % N, l));
+                const P h = P(0.5);
+                ox[m] = {h * (a.re + b.re), h * (a.im - b.im)};
+                oy[m] = {h * (a.im + b.im), h * (b.re - a.re)};
+            }
+        }
+        wave_fence();
+#pragma unroll
+        for (int m = 0; m < E; m++) {
+            const int k = t + M * m;
+            if (M * m <= K && (M * m + M - 1 <= K || k <= K)) {
+                lds_put<P>(lds, l * (K + 1) + k, ox[m]);
+                lds_put<P>(lds, RWO + l * (K + 1) + k, oy[m]);
+                lds_put<P>(lds, 2 * RWO + l * (K + 1) + k, d2[m]);
+            }
+        }
+        wave_fence();
+        store_tile(tile, false);
+        if (more) {                                            // first pair of the next tile
+            wait_vm<C::D3 + C::S>();
+            wave_fence();
+            gather(v, slot0, slot0 + RW);
+        }
+    }
+    wait_vm<0>();                                              // no copy into LDS outlives the workgroup
+    if (stage == 0) {
+        double dm = (double)umx;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double o = __shfl_xor(dm, off, 64);
+            dm = o > dm ? o : dm;
+        }
+        if (threadIdx.x == 0) atomicMax(&md.st->umax_bits, (unsigned long long)__double_as_longlong(dm));
+    }
+}
+
 // ================================================================== yfwd
 // y-lines L = z PX + kx.  in bufA [3][N][N][K+1]; out bufB [3][N (z)][2K+1][PX]
 // (pad lines kx > K carry zeros)
@@ -902,6 +1117,26 @@ static hipError_t run_xpass_dma(const MemberDev *mem, int count, int stage, cons
     return hipGetLastError();
 }
 
+// Wave-private x pass: one-wave workgroups, as many as stay resident,
+// split evenly over the members.
+template <typename P, int N, int EV>
+static hipError_t run_xpass_wave(const MemberDev *mem, int count, int stage, const Cx<P> *tw, hipStream_t s) {
+    using C = XWCfg<P, N, EV>;
+    static int resident = 0;
+    if (resident == 0) {
+        int dev = 0, cus = 0, occ = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_xpass_wave<P, N, EV>, 64, 0);
+        if (e != hipSuccess) return e;
+        resident = (cus > 0 ? cus : 1) * (occ > 0 ? occ : 1);
+    }
+    int per = resident / (count > 0 ? count : 1);
+    per = per < 1 ? 1 : (per > C::TILES ? C::TILES : per);
+    k_xpass_wave<P, N, EV><<<dim3((unsigned)per, count), 64, 0, s>>>(mem, tw, stage);
+    return hipGetLastError();
+}
+
 template <typename P, int N>
 static hipError_t run_pass(int pass, int variant, const MemberDev *mem, int count, int stage, const void *tw, hipStream_t s) {
     using C = Cfg<P, N, 8>;
@@ -911,6 +1146,18 @@ static hipError_t run_pass(int pass, int variant, const MemberDev *mem, int coun
         if (pass == P_XPASS && variant == 2) {
             if constexpr (N >= 64) return run_xpass_dma<P, N, 8>(mem, count, stage, twp, s);
             else return run_pencil<P, N, 8>(pass, mem, count, stage, twp, s);   // lines too short to stream
+        }
+        if (pass == P_XPASS && (variant == 4 || variant == 5)) {
+            // wave-private: 16 (FP32) / 8 (FP64) values per thread, or half that
+            // (where that tile shape is invalid: the streamed x pass, variant 2)
+            constexpr int EA = sizeof(P) == 4 ? 16 : 8, EB = EA / 2, CS = (int)sizeof(Cx<P>);
+            if constexpr (N >= 64) {
+                if constexpr (xwave_ok(N, EA, CS))
+                    if (variant == 4) return run_xpass_wave<P, N, EA>(mem, count, stage, twp, s);
+                if constexpr (xwave_ok(N, EB, CS))
+                    if (variant == 5) return run_xpass_wave<P, N, EB>(mem, count, stage, twp, s);
+                return run_xpass_dma<P, N, 8>(mem, count, stage, twp, s);
+            } else return run_pencil<P, N, 8>(pass, mem, count, stage, twp, s);
         }
         if (pass == P_XPASS && variant == 3) {
             // streamed, 16 values per thread (one LDS exchange per 256-point
@@ -960,7 +1207,7 @@ hipError_t launch_pass(int pass, int variant, int n, int prec, const MemberDev *
 }
 
 int pass_variants(int pass) {
-    if (pass == P_XPASS) return 4;
+    if (pass == P_XPASS) return 6;
     return (pass == P_ZINV || pass == P_YINV || pass == P_YFWD) ? 2 : 1;
 }
 

@@ -36,15 +36,28 @@ import time
 LAMBDA_STEP = math.log(2) / 3
 
 
-def ens128_specs(ens, n: int = 128, precision: str = "fp64", i_lo: int = -22, i_hi: int = 25,
-                 kmeta: float = 3.0, cfl: float = 0.2, seed0: int = 23712, box: float = 2 * math.pi):
-    """Member specs: lambda_i = i ln2/3, eps = e^lambda, nu from k_M eta of the
-    central member (k_M = K dk, dk = 2 pi / box, eps = 1:
-    nu = (kmeta / (K dk))^(4/3)).  The ens256 set of Table I is n = 256 in a
-    box of 4 pi (dk = 1/2), the band still [1.4, 2.3] dk."""
-    K = n // 3
+def max_resolved_wavenumber(n: int, box: float = 2 * math.pi, convention: str = "cubic") -> float:
+    """k_M of an n^3 grid.  The paper calls it the maximum resolved wavenumber
+    without a formula.  "cubic": the largest retained |m_i| of the cubic 2/3
+    truncation, K dk with K = floor(n/3); "sqrt2": sqrt(2) n/3 dk, the radius of
+    the spherical truncation that phase-shift dealiased codes keep (a reading
+    that reproduces Table I's R_lambda, see the design notes)."""
     dk = 2 * math.pi / box
-    nu = (kmeta / (K * dk)) ** (4.0 / 3.0)
+    if convention == "cubic":
+        return (n // 3) * dk
+    if convention == "sqrt2":
+        return math.sqrt(2.0) * n / 3.0 * dk
+    raise ValueError(f"unknown k_M convention {convention!r}")
+
+
+def ens128_specs(ens, n: int = 128, precision: str = "fp64", i_lo: int = -22, i_hi: int = 25,
+                 kmeta: float = 3.0, cfl: float = 0.2, seed0: int = 23712, box: float = 2 * math.pi,
+                 km: str = "cubic"):
+    """Member specs: lambda_i = i ln2/3, eps = e^lambda, nu from k_M eta of the
+    central member (eps = 1: nu = (kmeta / k_M)^(4/3), k_M from
+    max_resolved_wavenumber).  The ens256 set of Table I is n = 256 in a box
+    of 4 pi (dk = 1/2), the band still [1.4, 2.3] dk."""
+    nu = (kmeta / max_resolved_wavenumber(n, box, km)) ** (4.0 / 3.0)
     return [ens.MemberSpec(n=n, nu=nu, eps_ref=1.0, lam=i * LAMBDA_STEP, kf_lo=1.4, kf_hi=2.3, dt=0.0, cfl=cfl,
                            precision=precision, seed=seed0 + (i - i_lo), box=box) for i in range(i_lo, i_hi + 1)]
 
@@ -221,7 +234,7 @@ def run(E, members, transient: float, measure: float, snaps_per_T: float, chunk:
 
 
 RUN_KEYS = ("n", "precision", "i_lo", "i_hi", "box_scale", "transient", "measure", "snaps_per_T", "chunk",
-            "refine_lambda", "refine_transient")
+            "refine_lambda", "refine_transient", "km_convention")
 
 
 def main(argv=None):
@@ -231,6 +244,8 @@ def main(argv=None):
     ap.add_argument("--i-lo", type=int, default=-22)
     ap.add_argument("--i-hi", type=int, default=25)
     ap.add_argument("--box-scale", type=float, default=1.0, help="box = box_scale * 2 pi (2 for the ens256 set)")
+    ap.add_argument("--km-convention", choices=["cubic", "sqrt2"], default="cubic",
+                    help="k_M in k_M eta = 3 (sets nu): K dk of the cubic truncation, or sqrt(2) n/3 dk")
     ap.add_argument("--transient", type=float, default=5.0, help="integral times before measuring")
     ap.add_argument("--measure", type=float, default=18.0, help="integral times measured")
     ap.add_argument("--snaps-per-T", type=float, default=10.0)
@@ -255,10 +270,11 @@ def main(argv=None):
         extra = ens.Ensemble.read_checkpoint_extra(a.resume)
         state, cfg = extra["driver"], extra["run"]
         for k in RUN_KEYS:
-            setattr(a, k, cfg[k])
+            setattr(a, k, cfg.get(k, getattr(a, k)))
         E, members = ens.Ensemble.load_checkpoint(a.resume)
     else:
-        specs = ens128_specs(ens, a.n, a.precision, a.i_lo, a.i_hi, box=a.box_scale * 2 * math.pi)
+        specs = ens128_specs(ens, a.n, a.precision, a.i_lo, a.i_hi, box=a.box_scale * 2 * math.pi,
+                             km=a.km_convention)
         E = ens.Ensemble(hist=hist_spec(ens, specs[0].nu), graphs=True)
         members = [E.add_member(s) for s in specs]
         E.autotune()
@@ -281,7 +297,8 @@ def main(argv=None):
                           + res["state"].get("m_steps", 0), "checkpoint": a.checkpoint}), flush=True)
         return 0
     specs = [m.spec for m in members]
-    res["config"] = {"n": a.n, "precision": a.precision, "members": len(specs), "nu": specs[0].nu,
+    res["config"] = {"n": a.n, "precision": a.precision, "km_convention": a.km_convention, "members": len(specs),
+                     "nu": specs[0].nu,
                      "box": specs[0].box, "lambda": [s.lam for s in specs], "band": [1.4, 2.3], "cfl": 0.2}
     diverged = [m.id for m in E.members if m.diag()["diverged"]]
     res["diverged"] = diverged
