@@ -9,6 +9,7 @@
 #include <vector>
 
 #include <mutex>
+#include <type_traits>
 
 #include "ens_internal.h"
 #include "ens_lambda.h"
@@ -203,9 +204,9 @@ constexpr size_t kHotBytes = (4 * (size_t)kHotBins1 * kHotCopies1 + (size_t)kHot
 // in a fixed order to one partial per workgroup.  The register budget is
 // capped at 256 so that two workgroups share a compute unit (one leaves each
 // SIMD a single wave, which stalls on every dependent FP64 operation).
-template <typename P, int N>
+template <typename P, int N, int EX>
 __global__ void __launch_bounds__(256, 2) k_gxstats(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ twg, HistArgs h) {
-    constexpr int E = 4, M = N / E, T = 256 / M, K = N / 3;
+    constexpr int E = EX, M = N / E, T = 256 / M, K = N / 3;
     constexpr int PX = kx_pitch(K, (int)sizeof(Cx<P>));
     constexpr long long FS = (long long)N * N * PX;
     extern __shared__ double dyn[];                         // log edges, 1-D histograms, QR window
@@ -230,7 +231,14 @@ __global__ void __launch_bounds__(256, 2) k_gxstats(const MemberDev *__restrict_
     // global atomics on one address serialise)
     __shared__ unsigned int qspec[3];
     const MemberDev &md = mems[blockIdx.y];
-    const int l = threadIdx.x % T, t = threadIdx.x / T;
+    // Where a row's M threads fit one wave (N <= 256), the threads of a row are
+    // consecutive lanes and the transforms exchange through wave-private LDS
+    // rows (WaveLay) with no workgroup barrier; longer rows span waves and use
+    // the [position][row] layout with barriers.
+    constexpr bool WP = M <= 64 && 64 % M == 0;
+    using LY = typename std::conditional<WP, WaveLay<P, N>, RowLay<P, T>>::type;
+    const int l = WP ? (int)threadIdx.x / M : (int)threadIdx.x % T;
+    const int t = WP ? (int)threadIdx.x % M : (int)threadIdx.x / T;
     const int grp = threadIdx.x & (NC - 1), grq = threadIdx.x & (NQ - 1);
     const P dk = (P)md.dk;
     const int n1d = 2 * (h.lb + 3) + 2 * (h.ab + 3);
@@ -335,7 +343,7 @@ __global__ void __launch_bounds__(256, 2) k_gxstats(const MemberDev *__restrict_
                     v[m] = {A.re - B.im, A.im + B.re};
                 }
             }
-            line_fft<P, N, E, T, +1>(v, lds, l, t, tw);
+            line_fft<P, N, E, T, +1, WP ? 2 : 0, LY>(v, lds, l, t, tw);
 #pragma unroll
             for (int s = 0; s < E; s++) { g[fa][s] = v[s].re; if (fb < 9) g[fb][s] = v[s].im; }
         }
@@ -491,6 +499,11 @@ static int xstats_grid(int n, int count) {
 }
 
 // ---------------------------------------------------------------- launchers
+// values per thread of the statistics x pass: 4 (with 8 the nine gradient
+// rows, the FP64 point values and the 26 FP64 moment sums spill hundreds of
+// bytes per lane at the two-workgroup register budget)
+template <typename P, int N> constexpr int xstats_e() { return 4; }
+
 template <typename P, int N>
 static hipError_t stats_pass(int pass, const MemberDev *mem, int count, const ens_hist_desc *hd, const double *ledge,
                              const void *tw, hipStream_t s) {
@@ -520,9 +533,9 @@ static hipError_t stats_pass(int pass, const MemberDev *mem, int count, const en
         h.l2s = (float)(0.30102999566398119521 * h.l_scale);
         h.loff = (float)(h.l_lo * h.l_scale);
         // LDS: transform tile + reduction (static) + log edges, 1-D histograms, QR window (dynamic) <= 64 KiB
-        constexpr int T = 256 / (N / 4);
+        constexpr int EX = xstats_e<P, N>(), T = 256 / (N / EX);
         const size_t stat = (size_t)N * T * sizeof(LdsT<P>) + 4 * 32 * sizeof(double) + kHotBytes + 16 +
-                            (size_t)twiddle_span(N, 4) * sizeof(Cx<P>);
+                            (size_t)twiddle_span(N, EX) * sizeof(Cx<P>);
         const size_t n1d = 2 * (size_t)(h.lb + 3) + 2 * (size_t)(h.ab + 3);
         const size_t budget = 65536 - stat - 512;
         const size_t fixed = n1d * 4 + (size_t)(h.lb + 1) * 8;
@@ -533,7 +546,7 @@ static hipError_t stats_pass(int pass, const MemberDev *mem, int count, const en
         h.win0 = (h.qb - win) / 2;
         const size_t dyn = (size_t)(h.lb + 1) * 8 + (n1d + (size_t)win * win) * 4;
         const int per = xstats_grid(N, count);
-        k_gxstats<P, N><<<dim3(per, count), 256, dyn, s>>>(mem, twp, h);
+        k_gxstats<P, N, EX><<<dim3(per, count), 256, dyn, s>>>(mem, twp, h);
     } else {
         k_stats_reduce<<<count, 256, 0, s>>>(mem, (long long)xstats_grid(N, count));
     }
