@@ -28,6 +28,7 @@ range of five repeats, without statistics snapshots or the mixture).
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import math
 import os
@@ -197,7 +198,14 @@ def cpu_baseline(specs, steps=3):
     oracle.run(m, u, steps)
     d1 = time.perf_counter() - s0
     oracle.set_threads(threads)
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), model)
+    except OSError:
+        pass
     return {"value": round(pts / dt, 1), "unit": "grid-pt RK steps/s", "cores": threads, "kind": "oracle",
+            "host_cpu": model,
             "sample": f"{steps} FP64 RK3 steps of one member at each of {sizes} (oracle, {threads} OpenMP threads), "
                       f"{dt:.1f} s",
             "one_thread": {"value": round(m.n ** 3 * steps / d1, 1), "sample": f"{steps} steps at {m.n}^3, {d1:.1f} s"}}
@@ -361,6 +369,99 @@ def config5(ens, torch, args):
     return out
 
 
+def member_moments(E, m):
+    """A member's moment sums (FP64 tensor), without copying its histograms."""
+    import ctypes
+    import torch
+    from paper_2506_23712_amd import _lib
+    mom = torch.zeros(_lib.ENS_NMOM, dtype=torch.float64)
+    _lib.check(_lib.lib().ens_get_stats(E.ctx, m.id, None, ctypes.cast(mom.data_ptr(), ctypes.POINTER(ctypes.c_double)),
+                                        None))
+    return mom.numpy()
+
+
+def precision_report(ens, torch, args):
+    """FP32 against FP64 on the 96-member benchmark set: both runs start from
+    the same seeded fields, decorrelate by chaos after the transient, and are
+    compared statistically over non-overlapping windows of `window` steps
+    (statistics every 10 steps; about one to two integral times of most
+    members): each member's mean dissipation over its injection, and the
+    Gaussian mixture (c = 0.023, Z = ln 8) -- skewness, flatness and
+    hyper-flatness of the gradient components, mean dissipation, and every
+    QR-PDF bin holding at least 5e-4 of the mass -- with two-sample BCa
+    bootstrap intervals of the FP32 - FP64 difference of the window means."""
+    import numpy as np
+    from scipy import stats as sps
+    t_start = time.perf_counter()
+    log = lambda msg: print(f"[precision {time.perf_counter() - t_start:7.1f}s] {msg}", file=sys.stderr, flush=True)
+    nu = 0.03395
+    h = hist_for(ens, nu)
+    runs = {}
+    for prec in ("fp32", "fp64"):
+        specs = [dataclasses.replace(sp, precision=prec) for sp in ens96_specs(ens)]
+        E = ens.Ensemble(hist=h, graphs=True)
+        ms = [E.add_member(sp) for sp in specs]
+        E.autotune()
+        runs[prec] = (E, ms, specs)
+    for k in range(args.pr_transient // 500):
+        for prec, (E, ms, _) in runs.items():
+            E.step(500)
+        torch.cuda.synchronize()
+        log(f"transient {500 * (k + 1)} steps")
+    win = {p: {"eps": [], "mix": [], "qr": []} for p in runs}
+    area = ((h.q_hi - h.q_lo) / h.qr_bins) * ((h.r_hi - h.r_lo) / h.qr_bins)
+    for w in range(args.pr_windows):
+        for prec, (E, ms, specs) in runs.items():
+            for m in ms:
+                m.reset_stats()
+            for _ in range(args.pr_window // 10):
+                E.step(10)
+                E.accumulate_stats()
+            eps = []
+            for m, sp in zip(ms, specs):
+                mom = member_moments(E, m)
+                eps.append(mom[12] / (mom[28] * sp.n ** 3) / math.exp(sp.lam))   # <eps>/injection (eps_ref = 1)
+            win[prec]["eps"].append(eps)
+            mx = E.mix(0.023, math.log(8), mode=0)
+            win[prec]["mix"].append([mx["S_long"], mx["F_long"], mx["H_long"], mx["F_trans"], mx["H_trans"],
+                                     mx["mean_eps"]])
+            win[prec]["qr"].append((mx["qr"].numpy() * area).ravel())
+        log(f"window {w + 1}/{args.pr_windows}")
+    diverged = {p: [m.id for m in ms if m.diag()["diverged"]] for p, (E, ms, _) in runs.items()}
+    for E, _, _ in runs.values():
+        E.close()
+    rng = np.random.default_rng(0)
+    boot = lambda a, b, cl: sps.bootstrap((a, b), lambda x, y: np.mean(x) - np.mean(y), method="BCa",
+                                          confidence_level=cl, random_state=rng).confidence_interval
+    e32, e64 = np.array(win["fp32"]["eps"]), np.array(win["fp64"]["eps"])     # [window][member]
+    specs = runs["fp32"][2]
+    members, inside = [], 0
+    for i, sp in enumerate(specs):
+        ci = boot(e32[:, i], e64[:, i], 0.95)
+        ok = bool(ci.low <= 0.0 <= ci.high)
+        inside += ok
+        members.append({"lambda": round(sp.lam, 4), "n": sp.n, "eps_over_inj_fp32": float(e32[:, i].mean()),
+                        "eps_over_inj_fp64": float(e64[:, i].mean()), "ci95_diff": [float(ci.low), float(ci.high)],
+                        "zero_inside": ok})
+    names = ("S_long", "F_long", "H_long", "F_trans", "H_trans", "mean_eps")
+    m32, m64 = np.array(win["fp32"]["mix"]), np.array(win["fp64"]["mix"])
+    mix = {}
+    for j, nm in enumerate(names):
+        ci = boot(m32[:, j], m64[:, j], 0.95)
+        mix[nm] = {"fp32": float(m32[:, j].mean()), "fp64": float(m64[:, j].mean()),
+                   "ci95_diff": [float(ci.low), float(ci.high)], "zero_inside": bool(ci.low <= 0.0 <= ci.high)}
+    q32, q64 = np.array(win["fp32"]["qr"]), np.array(win["fp64"]["qr"])
+    mean_q = 0.5 * (q32.mean(0) + q64.mean(0))
+    bins = np.flatnonzero(mean_q >= 5e-4)
+    qin = sum(bool(ci.low <= 0.0 <= ci.high) for ci in (boot(q32[:, b], q64[:, b], 0.99) for b in bins))
+    return {"report": "fp32_vs_fp64_ens96", "windows": args.pr_windows, "window_steps": args.pr_window,
+            "transient_steps": args.pr_transient, "stats_every": 10,
+            "member_mean_dissipation": {"members": len(specs), "zero_inside_ci95": inside, "per_member": members},
+            "mixture_Z_ln8_c0.023": mix,
+            "mixed_qr_pdf": {"bins_tested": int(len(bins)), "zero_inside_ci99": int(qin)},
+            "diverged": diverged, "wall_s": round(time.perf_counter() - t_start, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -369,11 +470,16 @@ def main():
     ap.add_argument("--stats-every", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--only", choices=["ens96_mixed_fp32", "single256_fp64", "ens48_128_fp64", "single1024_fp32"],
+    ap.add_argument("--only", choices=["ens96_mixed_fp32", "single256_fp64", "ens48_128_fp64", "single1024_fp32",
+                                       "ens96_fp32_vs_fp64"],
                     default=None,
                     help="one workload; ens48_128_fp64 (the 48-member 128^3 FP64 set of the ensemble driver) and "
                          "single1024_fp32 (one 1024^3 FP32 member at R_lambda ~ 280 with tail statistics, beside "
                          "the developed 96-member set's mixture) run only when named")
+    ap.add_argument("--pr-transient", type=int, default=2000,
+                    help="ens96_fp32_vs_fp64: steps of both runs before the windows")
+    ap.add_argument("--pr-windows", type=int, default=16, help="ens96_fp32_vs_fp64: number of windows")
+    ap.add_argument("--pr-window", type=int, default=150, help="ens96_fp32_vs_fp64: steps per window")
     ap.add_argument("--c5-coarse-steps", type=int, default=3000,
                     help="single1024_fp32: steps of the member on 256^3 before refinement")
     ap.add_argument("--c5-mid-steps", type=int, default=1000,
@@ -413,6 +519,9 @@ def main():
 
     if args.only == "single1024_fp32":
         print(json.dumps(config5(ens, torch, args)))
+        return
+    if args.only == "ens96_fp32_vs_fp64":
+        print(json.dumps(precision_report(ens, torch, args)))
         return
     res = {}
     if args.only in (None, "ens96_mixed_fp32"):
