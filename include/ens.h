@@ -192,7 +192,9 @@ ens_status ens_get_diag(ens_ctx *ctx, int32_t m, ens_diag *out);
  * variant 3 = the same with 16 values per thread for FP32 and 128 <= n <= 512,
  * else variant 2; variants 4 and 5 = the streamed pass with one wave per
  * workgroup and every transform exchange inside the wave, 16 or 8 (FP32) /
- * 8 or 4 (FP64) values per thread, n >= 64, else variant 2)
+ * 8 or 4 (FP64) values per thread, n >= 64, else variant 2; variant 6 =
+ * variant 4 with its inputs staged pairwise through two buffers, less LDS
+ * per wave)
  * on the grid sizes and precisions of `members`, and keep the fastest
  * per (pass, n, precision) for later steps.  Only scratch buffers are written:
  * member state is unchanged.  `cache_path` (may be NULL) names a text file of

@@ -110,6 +110,30 @@ __device__ __forceinline__ void dma_rows3(void *dst, const char *b0, long long f
     }
 }
 
+// The same for F fields (F >= 1), copied densely into `dst` laid out [F][T][RVR].
+template <int F, int RVR, int ROWB, int T, int NTH>
+__device__ __forceinline__ void dma_rows(void *dst, const char *b0, long long fstride) {
+    constexpr int RV = T * RVR, NCF = (RV + 63) / 64, NCH = F * NCF, NW = NTH / 64;
+    static_assert(RV >= 64 && NTH % 64 == 0 && ROWB >= RVR * 16, "tile too small for wave-wide copies");
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const unsigned lane = threadIdx.x & 63u;
+#pragma unroll
+    for (int j = 0; j < (NCH + NW - 1) / NW; j++) {
+        int c = j * NW + wave;
+        c = c < NCH ? c : NCH - 1;
+        const int f = c / NCF, q = c - f * NCF;
+        const int st = q * 64 < RV - 64 ? q * 64 : RV - 64;
+        const unsigned v = (unsigned)st + lane, r = v / (unsigned)RVR, col = v - r * (unsigned)RVR;
+        const ENS_GLOBAL char *src = (const ENS_GLOBAL char *)b0 + f * fstride;
+        __builtin_amdgcn_global_load_lds((const ENS_GLOBAL void *)(src + (r * (unsigned)ROWB + col * 16u)),
+                                         (__attribute__((address_space(3))) void *)((char *)dst + (f * RV + st) * 16), 16, 0, 0);
+    }
+}
+// copies per wave of dma_rows<F, ...> for RV vectors per field
+template <int F, int RV, int NTH> constexpr int dma_rows_ops() {
+    return (F * ((RV + 63) / 64) + NTH / 64 - 1) / (NTH / 64);
+}
+
 template <int RV, int NTH> constexpr int dma_tile3_ops() {
     return (3 * ((RV + 63) / 64) + NTH / 64 - 1) / (NTH / 64);
 }

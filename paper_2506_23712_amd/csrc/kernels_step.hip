@@ -878,6 +878,197 @@ __global__ void __launch_bounds__(64, (XWCfg<P, N, EV>::MINW)) k_xpass_wave(cons
     }
 }
 
+// Wave-private x pass with the six input fields staged as three pairs through
+// two buffers of two fields each (instead of two buffers of three): pair q of
+// the wave's sequence (3 per tile) goes to buffer q mod 2 and is requested as
+// soon as pair q - 2 has been read from it, so two pairs are resident or in
+// flight at any time.  A third less staging LDS per wave than k_xpass_wave
+// (19.5 against 24.8 KB for 256-point FP32 rows), so that eight one-wave
+// workgroups share a compute unit, two per SIMD, where six leave two SIMDs
+// with a single wave.
+template <typename P, int N, int E_> struct XW2Cfg {
+    using B = XWCfg<P, N, E_>;
+    static constexpr int D2 = dma_rows_ops<2, B::RV, 64>();    // copies per pair
+    static constexpr long long LDS_BYTES = (4LL * B::RW + B::XL + B::NTW) * B::CS + 64;
+    static constexpr int WPS = (int)(163840 / ((LDS_BYTES + 511) / 512 * 512)) / 4;
+    static constexpr int MINW = WPS < 1 ? 1 : (WPS > 4 ? 4 : WPS);
+    static_assert(D2 + B::S < 64, "vector-memory count of the x-pass tile");
+};
+
+template <typename P, int N, int EV>
+__global__ void __launch_bounds__(64, (XW2Cfg<P, N, EV>::MINW)) k_xpass_wave2(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw, int stage) {
+    using C = XWCfg<P, N, EV>;
+    using C2 = XW2Cfg<P, N, EV>;
+    using LY = WaveLay<P, N>;
+    constexpr int E = C::E, M = C::M, R = C::R, K = C::K, RW = C::RW, RQ = C::RQ;
+    constexpr int PX = C::PX, RWO = C::RWO, RVO = C::RVO, D2 = C2::D2, S = C::S;
+    constexpr long long FSB = (long long)N * N * PX * C::CS;         // bytes per input field
+    constexpr long long FSBO = (long long)N * N * (K + 1) * C::CS;   // bytes per output field
+    __shared__ __attribute__((aligned(16))) LdsT<P> slotA[2 * RW];
+    __shared__ __attribute__((aligned(16))) LdsT<P> slotB[2 * RW];
+    __shared__ __attribute__((aligned(16))) LdsT<P> lds[C::XL];
+    __shared__ Cx<P> twl[C::NTW];
+    unsigned chunk, mem_i;
+    xcd_tile(chunk, mem_i);
+    const MemberDev &md = mems[mem_i];
+    const int t0 = (int)((long long)chunk * C::TILES / gridDim.x);
+    const int t1 = (int)((long long)(chunk + 1) * C::TILES / gridDim.x);
+    if (t0 >= t1) return;                                     // uniform over the wave
+    const int t = (int)threadIdx.x % M, l = (int)threadIdx.x / M;
+    TwRegs<P, N, E> twr;
+    if constexpr (C::REGTW) twr.load(tw, t);
+    else for (int i = (int)threadIdx.x; i < C::NTW; i += 64) twl[i] = tw[i];
+    wave_fence();
+    const auto &twx = [&]() -> const auto & {
+        if constexpr (C::REGTW) return twr;
+        else return twl;
+    }();
+    const char *inb = (const char *)md.bufB;
+    char *outb = (char *)md.bufA;
+    auto slot = [&](int i) -> LdsT<P> * { return i ? slotB : slotA; };
+    auto request = [&](LdsT<P> *dst, int tile, int pair) {    // fields 2 pair, 2 pair + 1 of the tile's R rows
+        dma_rows<2, C::RVR, PX * C::CS, R, 64>(dst, inb + (long long)(2 * pair) * FSB + (long long)tile * R * PX * C::CS, FSB);
+    };
+    auto gather = [&](Cx<P> *v, const LdsT<P> *fa, const LdsT<P> *fb) {
+#pragma unroll
+        for (int m = 0; m < E; m++) {
+            const int n = t + M * m;
+            const int r = l * RQ;
+            if (M * m > K && M * m + M - 1 < N - K) {
+                v[m] = czero<P>();
+            } else if (m > 0 && M * m + M - 1 <= K) {
+                const Cx<P> A = lds_get<P>(fa, r + n), B = lds_get<P>(fb, r + n);
+                v[m] = {A.re - B.im, A.im + B.re};
+            } else if (M * m >= N - K) {
+                const Cx<P> A = lds_get<P>(fa, r + N - n), B = lds_get<P>(fb, r + N - n);
+                v[m] = {A.re + B.im, B.re - A.im};
+            } else {
+                const bool lo = n <= K, hi = n >= N - K;
+                const int kx = lo ? n : N - n;
+                Cx<P> A = czero<P>(), B = czero<P>();
+                if (lo || hi) { A = lds_get<P>(fa, r + kx); B = lds_get<P>(fb, r + kx); }
+                if (n == 0) v[m] = {A.re, B.re};
+                else if (lo) v[m] = {A.re - B.im, A.im + B.re};
+                else v[m] = {A.re + B.im, B.re - A.im};
+            }
+        }
+    };
+    P umx = P(0);
+    Cx<P> v[E];
+    typedef float F4 __attribute__((ext_vector_type(4)));
+    const unsigned lane16 = (threadIdx.x & 63u) * 16u;
+    auto store_tile = [&](int tile, bool zero) {
+        constexpr int NCF = (RVO + 63) / 64, NCH = 3 * NCF;
+#pragma unroll
+        for (int c = 0; c < NCH; c++) {
+            const int f = c / NCF, q = c - f * NCF;
+            const int st = q * 64 < RVO - 64 ? q * 64 : RVO - 64;
+            const F4 x = zero ? F4{0.f, 0.f, 0.f, 0.f} : *(const F4 *)((const char *)lds + (f * RVO + st) * 16 + lane16);
+            ENS_GLOBAL char *dst = (ENS_GLOBAL char *)outb + f * FSBO + (long long)tile * RWO * C::CS + st * 16;
+            *(ENS_GLOBAL F4 *)(dst + lane16) = x;
+        }
+    };
+    // Wait accounting (vector-memory operations complete in issue order).  The
+    // wave's pair requests R(q), q = 3 (tile - t0) + j, and its tile stores
+    // S(tile) are issued in the order ... R(3u+1) S(u-1) R(3u+2) R(3u+3) R(3u+4)
+    // S(u) ..., so before reading pair 0 of tile u at most D2 + S operations
+    // issued after it may be outstanding, before pair 1 S + D2, before pair 2
+    // D2.  The prologue writes zeros to the first tile's output to reproduce
+    // that order; requests past the last tile repeat the last tile's pairs.
+    request(slot(0), t0, 0);
+    request(slot(1), t0, 1);
+    store_tile(t0, true);
+    wait_vm<D2 + S>();                                         // pair 0 of the first tile
+    wave_fence();
+    gather(v, slot(0), slot(0) + RW);
+    for (int tile = t0; tile < t1; tile++) {
+        const int u = (tile - t0) & 1;                         // pairs 0, 1, 2 of this tile in slots u, 1 - u, u
+        const bool more = tile + 1 < t1;
+        const int nxt = more ? tile + 1 : tile;
+        P ph[6][E];
+        lds_wait();                                            // pair 0 read
+        request(slot(u), tile, 2);
+        line_fft<P, N, E, R, +1, 2, LY>(v, lds, l, t, twx);
+#pragma unroll
+        for (int s = 0; s < E; s++) { ph[0][s] = v[s].re; ph[1][s] = v[s].im; }
+        wait_vm<S + D2>();                                     // pair 1
+        wave_fence();
+        gather(v, slot(1 - u), slot(1 - u) + RW);
+        lds_wait();                                            // pair 1 read
+        request(slot(1 - u), nxt, 0);
+        line_fft<P, N, E, R, +1, 2, LY>(v, lds, l, t, twx);
+#pragma unroll
+        for (int s = 0; s < E; s++) { ph[2][s] = v[s].re; ph[3][s] = v[s].im; }
+        wait_vm<D2>();                                         // pair 2
+        wave_fence();
+        gather(v, slot(u), slot(u) + RW);
+        lds_wait();                                            // pair 2 read
+        request(slot(u), nxt, 1);
+        line_fft<P, N, E, R, +1, 2, LY>(v, lds, l, t, twx);
+#pragma unroll
+        for (int s = 0; s < E; s++) { ph[4][s] = v[s].re; ph[5][s] = v[s].im; }
+        // ph: 0 u_x, 1 u_y, 2 u_z, 3 omega_x, 4 omega_y, 5 omega_z
+        if (stage == 0) {
+#pragma unroll
+            for (int s = 0; s < E; s++) {
+                const P a = fabs(ph[0][s]) + fabs(ph[1][s]) + fabs(ph[2][s]);
+                umx = a > umx ? a : umx;
+            }
+        }
+        Cx<P> d1[E], d2[E];
+#pragma unroll
+        for (int s = 0; s < E; s++) {
+            d1[s] = {ph[1][s] * ph[5][s] - ph[2][s] * ph[4][s], ph[2][s] * ph[3][s] - ph[0][s] * ph[5][s]};
+            d2[s] = {ph[0][s] * ph[4][s] - ph[1][s] * ph[3][s], P(0)};
+        }
+        line_fft_T<P, N, E, R, -1, 2, LY>(d1, lds, l, t, twx);        // d1[m] = D1[t + M m]
+        line_fft_T<P, N, E, R, -1, 2, LY>(d2, lds, l, t, twx);
+        wave_fence();
+#pragma unroll
+        for (int m = 0; m < E; m++) lds_put<P>(lds, LY::slot(t + M * m, l), d1[m]);
+        wave_fence();
+        Cx<P> ox[E], oy[E];
+#pragma unroll
+        for (int m = 0; m < E; m++) {
+            const int k = t + M * m;
+            if (M * m <= K && (M * m + M - 1 <= K || k <= K)) {
+                const Cx<P> a = d1[m];
+                const Cx<P> b = lds_get<P>(lds, LY::slot((N - k) % N, l));
+                const P h = P(0.5);
+                ox[m] = {h * (a.re + b.re), h * (a.im - b.im)};
+                oy[m] = {h * (a.im + b.im), h * (b.re - a.re)};
+            }
+        }
+        wave_fence();
+#pragma unroll
+        for (int m = 0; m < E; m++) {
+            const int k = t + M * m;
+            if (M * m <= K && (M * m + M - 1 <= K || k <= K)) {
+                lds_put<P>(lds, l * (K + 1) + k, ox[m]);
+                lds_put<P>(lds, RWO + l * (K + 1) + k, oy[m]);
+                lds_put<P>(lds, 2 * RWO + l * (K + 1) + k, d2[m]);
+            }
+        }
+        wave_fence();
+        store_tile(tile, false);
+        if (more) {                                            // pair 0 of the next tile, in slot 1 - u
+            wait_vm<D2 + S>();
+            wave_fence();
+            gather(v, slot(1 - u), slot(1 - u) + RW);
+        }
+    }
+    wait_vm<0>();                                              // no copy into LDS outlives the workgroup
+    if (stage == 0) {
+        double dm = (double)umx;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double o = __shfl_xor(dm, off, 64);
+            dm = o > dm ? o : dm;
+        }
+        if (threadIdx.x == 0) atomicMax(&md.st->umax_bits, (unsigned long long)__double_as_longlong(dm));
+    }
+}
+
 // ================================================================== yfwd
 // y-lines L = z PX + kx.  in bufA [3][N][N][K+1]; out bufB [3][N (z)][2K+1][PX]
 // (pad lines kx > K carry zeros)
@@ -1137,6 +1328,24 @@ static hipError_t run_xpass_wave(const MemberDev *mem, int count, int stage, con
     return hipGetLastError();
 }
 
+template <typename P, int N, int EV>
+static hipError_t run_xpass_wave2(const MemberDev *mem, int count, int stage, const Cx<P> *tw, hipStream_t s) {
+    using C = XWCfg<P, N, EV>;
+    static int resident = 0;
+    if (resident == 0) {
+        int dev = 0, cus = 0, occ = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_xpass_wave2<P, N, EV>, 64, 0);
+        if (e != hipSuccess) return e;
+        resident = (cus > 0 ? cus : 1) * (occ > 0 ? occ : 1);
+    }
+    int per = resident / (count > 0 ? count : 1);
+    per = per < 1 ? 1 : (per > C::TILES ? C::TILES : per);
+    k_xpass_wave2<P, N, EV><<<dim3((unsigned)per, count), 64, 0, s>>>(mem, tw, stage);
+    return hipGetLastError();
+}
+
 template <typename P, int N>
 static hipError_t run_pass(int pass, int variant, const MemberDev *mem, int count, int stage, const void *tw, hipStream_t s) {
     using C = Cfg<P, N, 8>;
@@ -1146,6 +1355,13 @@ static hipError_t run_pass(int pass, int variant, const MemberDev *mem, int coun
         if (pass == P_XPASS && variant == 2) {
             if constexpr (N >= 64) return run_xpass_dma<P, N, 8>(mem, count, stage, twp, s);
             else return run_pencil<P, N, 8>(pass, mem, count, stage, twp, s);   // lines too short to stream
+        }
+        if (pass == P_XPASS && variant == 6) {
+            // wave-private, pairs staged through two buffers: 16 (FP32) / 8 (FP64) values per thread
+            constexpr int EA = sizeof(P) == 4 ? 16 : 8, CS = (int)sizeof(Cx<P>);
+            if constexpr (N >= 64 && xwave_ok(N, EA, CS)) return run_xpass_wave2<P, N, EA>(mem, count, stage, twp, s);
+            else if constexpr (N >= 64) return run_xpass_dma<P, N, 8>(mem, count, stage, twp, s);
+            else return run_pencil<P, N, 8>(pass, mem, count, stage, twp, s);
         }
         if (pass == P_XPASS && (variant == 4 || variant == 5)) {
             // wave-private: 16 (FP32) / 8 (FP64) values per thread, or half that
@@ -1207,7 +1423,7 @@ hipError_t launch_pass(int pass, int variant, int n, int prec, const MemberDev *
 }
 
 int pass_variants(int pass) {
-    if (pass == P_XPASS) return 6;
+    if (pass == P_XPASS) return 7;
     return (pass == P_ZINV || pass == P_YINV || pass == P_YFWD) ? 2 : 1;
 }
 

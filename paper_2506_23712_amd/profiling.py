@@ -67,6 +67,11 @@ def kernel_name(pass_name: str, n: int, prec: str, variant) -> str:
     p = "float" if prec == "fp32" else "double"
     if pass_name == "zfwd_update":
         return f"ens::k_zfwd_update<{p}, {n}>"
+    ea = 16 if prec == "fp32" else 8
+    if pass_name == "xpass" and variant == 6 and n >= 64:
+        return f"ens::k_xpass_wave2<{p}, {n}, {ea}>"
+    if pass_name == "xpass" and variant in (4, 5) and n >= 64:
+        return f"ens::k_xpass_wave<{p}, {n}, {ea if variant == 4 else ea // 2}>"
     if pass_name == "xpass" and variant == 3 and 128 <= n <= 512 and prec == "fp32":
         return f"ens::k_xpass_dma<{p}, {n}, 16>"
     if pass_name == "xpass" and variant in (2, 3) and n >= 64:

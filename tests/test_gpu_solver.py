@@ -229,13 +229,13 @@ def test_streamed_xpass_agrees_with_classic(n, prec, count):
     (batches of the benchmark's shapes) against the classic 8-value kernel:
     variant 2 (8 values per thread), 3 (FP32: 16), and the wave-private
     variants 4 (16 FP32 / 8 FP64 values) and 5 (8 / 4), whose exchanges never
-    leave a wave.  All perform the same operations; the compiler may fuse
+    leave a wave, and 6 (as 4, inputs staged pairwise through two buffers).  All perform the same operations; the compiler may fuse
     multiply-adds differently, so agreement is to rounding: a tile staged
     wrongly, read before its copy landed or exchanged without ordering would
     differ at O(1)."""
     ens = ens_mod()
     finals = []
-    variants = ((0, 2, 3) if prec == "fp32" and 128 <= n <= 512 else (0, 2)) + (4, 5)
+    variants = ((0, 2, 3) if prec == "fp32" and 128 <= n <= 512 else (0, 2)) + (4, 5, 6)
     for variant in variants:
         E = ens.Ensemble()
         ms = [E.add_member(ens.MemberSpec(n=n, nu=0.03395, eps_ref=1.0, lam=0.3 * i - 1.0, kf_hi=2.5, dt=0.0, cfl=0.5,
@@ -261,7 +261,7 @@ def test_autotune_keeps_state_and_writes_cache(tmp_path):
     cache = tmp_path / "variants.txt"
     table = E.autotune(cache_path=str(cache))
     assert np.array_equal(m.state().cpu().numpy(), before)
-    assert set(table.values()) <= {0, 1, 2, 3, 4, 5} and len(table) == 4
+    assert set(table.values()) <= {0, 1, 2, 3, 4, 5, 6} and len(table) == 4
     text = cache.read_text()
     assert "zinv:32:fp64" in text
     E.close()
