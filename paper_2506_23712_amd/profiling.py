@@ -180,7 +180,8 @@ def write_summary(n: int, counts, out: str, trace: str | None = None, workloads=
         for k in ("zinv", "yinv", "xpass", "yfwd", "zfwd_update"):
             for name, v in sorted(t["kernels"].items()):
                 short = name.replace("ens::", "")
-                if not (short.startswith(f"k_{k}<") or (k == "xpass" and short.startswith("k_xpass_dma<"))):
+                if not (short.startswith(f"k_{k}<") or (k == "xpass" and short.startswith(("k_xpass_dma<", "k_xpass_wave<",
+                                                                                          "k_xpass_wave2<")))):
                     continue
                 if f", {n}" not in short or ("float" in short) != (prec == "fp32"):
                     continue
