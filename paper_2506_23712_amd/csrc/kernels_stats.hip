@@ -265,10 +265,14 @@ __global__ void __launch_bounds__(256, 2) k_gxstats(const MemberDev *__restrict_
     if (!(md.eps_m > 0.0) || !(md.nu > 0.0)) { c0[0] = -1; c0[1] = -1; }
     const int q0 = c0_of((0.0 - h.q_lo) * h.q_scale, h.qb, CQ), r0 = c0_of((0.0 - h.r_lo) * h.r_scale, h.qb, CQ);
     unsigned int *single[4] = {h_le, h_lw, h_al, h_at};
+    // one LDS atomic per sample on the selected counter (a replicated hot bin
+    // or the plain bin): lanes of one wave that differ in the choice do not
+    // split into two atomic instructions
     auto add1 = [&](int hist, int slot) {
         const int rel = slot - c0[hist];
-        if (c0[hist] >= 0 && rel >= 0 && rel < CW) atomicAdd(&cen1[hist][rel][grp], 1u);
-        else atomicAdd(&single[hist][slot], 1u);
+        const bool hot = c0[hist] >= 0 && rel >= 0 && rel < CW;
+        unsigned int *p = hot ? &cen1[hist][hot ? rel : 0][grp] : &single[hist][slot];
+        atomicAdd(p, 1u);
     };
     double mom[26];
 #pragma unroll
@@ -374,22 +378,25 @@ __global__ void __launch_bounds__(256, 2) k_gxstats(const MemberDev *__restrict_
             const double ens = w0 * w0 + w1 * w1 + w2 * w2;
             const double qs = q * h.inv_trs, rs = r * h.inv_trs15;
             const double es = 2.0 * nu * ss * h.inv_eps_ref, ws = ens * h.om_scale;
-            {   // QR: replicated centre, then the LDS window, elsewhere global
-                int gidx = -1, widx = -1, cidx = -1, sidx = -1;
-                if (qs != qs || rs != rs) sidx = 2;
-                else {
-                    const int bq = bin_of(qs, h.q_lo, h.q_scale, h.qb), br = bin_of(rs, h.r_lo, h.r_scale, h.qb);
-                    if (bq < 0 || br < 0) sidx = 0;
-                    else if (q0 >= 0 && r0 >= 0 && bq >= q0 && bq < q0 + CQ && br >= r0 && br < r0 + CQ)
-                        cidx = (bq - q0) * CQ + (br - r0);
-                    else if (bq >= h.win0 && bq < h.win0 + h.win && br >= h.win0 && br < h.win0 + h.win)
-                        widx = (bq - h.win0) * h.win + (br - h.win0);
-                    else gidx = bq * h.qb + br;
+            {   // QR: replicated centre, the LDS window, the LDS outside/NaN
+                // counters (one LDS atomic on the selected counter), else global
+                const bool nan = qs != qs || rs != rs;
+                const int bq = nan ? -1 : bin_of(qs, h.q_lo, h.q_scale, h.qb);
+                const int br = nan ? -1 : bin_of(rs, h.r_lo, h.r_scale, h.qb);
+                const bool out = !nan && (bq < 0 || br < 0);
+                const bool cen = !nan && !out && q0 >= 0 && r0 >= 0 && bq >= q0 && bq < q0 + CQ && br >= r0 &&
+                                 br < r0 + CQ;
+                const bool win = !nan && !out && !cen && bq >= h.win0 && bq < h.win0 + h.win && br >= h.win0 &&
+                                 br < h.win0 + h.win;
+                if (nan || out || cen || win) {
+                    unsigned int *p = nan ? &qspec[2]
+                                    : out ? &qspec[0]
+                                    : cen ? &cenq[(bq - q0) * CQ + (br - r0)][grq]
+                                          : &h_qr[(bq - h.win0) * h.win + (br - h.win0)];
+                    atomicAdd(p, 1u);
+                } else {
+                    atomicAdd(&G[bq * h.qb + br], 1ull);
                 }
-                if (cidx >= 0) atomicAdd(&cenq[cidx][grq], 1u);
-                else if (widx >= 0) atomicAdd(&h_qr[widx], 1u);
-                else if (sidx >= 0) atomicAdd(&qspec[sidx], 1u);
-                else atomicAdd(&G[gidx], 1ull);
             }
             add1(0, slot_1d(es > 0.0 ? log_bin(es, ledge, h.lb, h.l2s, h.loff) : (es != es ? -3 : -1), h.lb));
             add1(1, slot_1d(ws > 0.0 ? log_bin(ws, ledge, h.lb, h.l2s, h.loff) : (ws != ws ? -3 : -1), h.lb));
