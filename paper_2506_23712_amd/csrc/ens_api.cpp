@@ -108,9 +108,12 @@ Layout member_layout(const ens_member_desc &d, const HistGeom *hg) {
     L.off_st = o; o += align256(sizeof(DevState));
     L.off_uh = o; o += align256(3 * (size_t)g.S * cs);
     L.off_q = o; o += align256(3 * (size_t)g.S * cs);
-    const size_t a_elems = std::max((size_t)6 * n * g.nzl, (size_t)3 * n * n * (g.K + 1));
+    // bufA: statistics z-inverse out, z-inverse out, x-pass out;
+    // bufB: statistics y-inverse out, y-inverse out, y-forward out
+    const size_t a_elems = std::max({(size_t)6 * n * g.nzl, (size_t)5 * n * g.zp, (size_t)3 * n * g.nyl});
+    const size_t b_elems = std::max({(size_t)9 * n * n * g.px, (size_t)6 * n * g.nyl, (size_t)3 * (2 * g.K + 1) * g.nyl});
     L.off_a = o; o += align256(a_elems * cs);
-    L.off_b = o; o += align256((size_t)9 * n * n * g.px * cs);
+    L.off_b = o; o += align256(b_elems * cs);
     const size_t nparts = std::max({(size_t)(2 * zfwd_blocks(d.n, d.precision)), (size_t)init_blocks(d.n),
                                     (size_t)(ENS_NMOM * xstats_blocks(d.n)), (size_t)scales_partials(g.K),
                                     (size_t)spectrum_partials(g.K)});

@@ -28,18 +28,22 @@ struct DevState {
     double pad[4];
 };
 
-// Pitch of the x-mode (fastest) index of the pencil buffers that a pass
-// writes in runs of one 128-byte line per position (the z- and y-inverse
-// outputs and the y-forward output): K + 1 rounded up to whole lines (16 FP32
-// / 8 FP64 complex values), the pad entries written as zeros, so that every
-// store covers whole lines.  A line shared by two workgroups, each writing
-// part of it, is written back twice at far lower bandwidth.  `cbytes` is the
-// size of one complex value.  Where the padding would exceed 1/8 of a row
-// (short rows: n <= 64 FP32, n <= 32 FP64) the rows are left unpadded.
+// Pitch of the x-mode (fastest) index of the statistics pass's pencil
+// buffers, which its z/y inverses write in runs of one 128-byte line per
+// position: K + 1 rounded up to whole lines (16 FP32 / 8 FP64 complex
+// values), the pad entries written as zeros, so that every store covers whole
+// lines.  A line shared by two workgroups, each writing part of it, is
+// written back twice at far lower bandwidth.  `cbytes` is the size of one
+// complex value.  Where the padding would exceed 1/8 of a row (short rows:
+// n <= 64 FP32, n <= 32 FP64) the rows are left unpadded.  (The time-step
+// passes need no pad: their lines are numbered so that every run they store
+// is a whole number of lines; see MemberDev.)
 __host__ __device__ constexpr int kx_pitch(int K, int cbytes) {
     const int per = 128 / cbytes, px = (K + 1 + per - 1) / per * per;
     return 8 * (px - (K + 1)) <= K + 1 ? px : K + 1;
 }
+
+__host__ __device__ constexpr int gcd_int(int a, int b) { return b == 0 ? a : gcd_int(b, a % b); }
 
 // Plane pitch of the state arrays (u_hat and the RK register, [3][2K+1 (kz)]
 // [ZP]): the (2K+1)(K+1) modes of one kz plane rounded up to whole 128-byte
@@ -53,29 +57,38 @@ __host__ __device__ constexpr int state_pitch(int K, int cbytes) {
 
 // Everything a kernel needs to know about one member (lives in a device
 // table owned by the library; pointers refer to the caller's workspace).
-// PX = kx_pitch(K, complex size).  Layouts (x-mode index fastest):
+// KX = K + 1 x-modes, NZLS = (2K+1) KX modes per z plane, ZP = state_pitch,
+// NYL = n KX; the y-pencil buffers hold blocks of ZB consecutive z rows,
+// BL = ZB KX values per position, ZB the fewest rows that fill whole 128-byte
+// lines (8 FP32 / 4 FP64 at n = 256).  Layouts of a time step (x-mode index
+// fastest, no row pad): every y/z pass numbers its lines so that a
+// workgroup's consecutive lines are consecutive in the buffer it writes, and
+// a run of 16 (FP32) / 8 (FP64) lines per position is one whole 128-byte line.
 struct MemberDev {
     void *uh;          // velocity  [3][2K+1 (kz)][ZP: 2K+1 (ky) x K+1 (kx), then pad] complex
     void *q;           // RK register, same layout
-    void *bufA;        // [F][n (z)][2K+1][PX] (z-inverse out) / [3][n][n][K+1] (x-pass out, linear stores)
-    void *bufB;        // [F][n (z)][n (y)][PX] (y-inverse out) / [3][n][2K+1][PX] (y-forward out)
+    void *bufA;        // z-inverse out [5][n (z)][ZP] (planes as in uh, pad zeroed) /
+                       // x-pass out [3][n / ZB][n (y)][ZB (z)][KX] (the rows of its input)
+    void *bufB;        // y-inverse out [6][n / ZB][n (y)][BL = ZB (z) x KX] /
+                       // y-forward out [3][n / ZB][2K+1 (ky)][BL]
+                       // (statistics: [6][n][2K+1][PX] and [9][n][n][PX], PX = kx_pitch)
     DevState *st;      // diag.E: energy at the end of the last step (or of the field as set)
     double *partials;  // per-workgroup FP64 partial sums
     unsigned long long *counts;   // statistics counters
     double *moments;              // ENS_NMOM sums
     double nu, eps_m, kf_lo2, kf_hi2, dt_fixed, cfl, box, dk;
     int n, K, prec, visc_mode;
-    int px;            // x-mode pitch PX
+    int px;            // x-mode pitch PX of the statistics pass's buffers
     int zp;            // state plane pitch ZP = state_pitch(K, complex size)
 };
 
 // Host-visible geometry of one member.
 struct Geom {
     int n, K, px;
-    long long nzl;     // z-lines of the pencil buffers = (2K+1) PX (pad lines included)
+    long long nzl;     // z-lines of the statistics pass's buffers = (2K+1) PX (pad lines included)
     long long zp;      // state plane pitch ZP
     long long S;       // state elements per component = (2K+1) ZP (pad entries included)
-    long long nyl;     // y-lines of the pencil buffers = n PX
+    long long nyl;     // y-lines of the time-step buffers = n (K+1)
 };
 
 inline Geom make_geom(int n, int prec) {
@@ -85,7 +98,7 @@ inline Geom make_geom(int n, int prec) {
     g.nzl = (long long)(2 * g.K + 1) * g.px;
     g.zp = state_pitch(g.K, prec == ENS_FP32 ? 8 : 16);
     g.S = (long long)(2 * g.K + 1) * g.zp;
-    g.nyl = (long long)n * g.px;
+    g.nyl = (long long)n * (g.K + 1);
     return g;
 }
 

@@ -9,9 +9,12 @@
 //   yfwd   : forward along y, keep |m_y| <= K                         3 fields
 //   zfwd   : forward along z, keep |m_z| <= K, project, force, RK update
 //   end    : FP64 reduction of E and D partials, diagnostics, time
-// Pencils of the y/z passes are lines of one (x-mode, other-coordinate) pair;
-// the x-mode index is the fastest in memory, so consecutive lanes of a
-// workgroup read consecutive complex words.  Every buffer is addressed as a
+// Pencils of the y/z passes are lines of one (x-mode, other-coordinate) pair,
+// numbered with the x-mode fastest and in the order of the buffer the pass
+// writes, so that a workgroup's consecutive lines are consecutive complex
+// words at every position and its stores cover whole 128-byte lines with no
+// row padding (its loads may straddle lines: the neighbouring workgroups, on
+// the same XCD, read the rest of them).  Every buffer is addressed as a
 // workgroup-uniform base pointer per field plus a 32-bit per-lane offset, and
 // the loads of the next transform are issued before the current one is
 // computed, so that HBM latency overlaps the butterflies.
@@ -43,18 +46,27 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
 // E are compiled for the pencil passes and the x pass; the host picks one per
 // (pass, N, precision) from its tuning table.
 template <typename P, int N, int E_> struct Cfg {
-    static constexpr int K = N / 3;
-    static constexpr int PX = kx_pitch(K, (int)sizeof(Cx<P>));  // x-mode pitch of the pencil buffers
-    static constexpr int NZL = (2 * K + 1) * PX;                // z-lines of a pencil buffer (pad lines included)
-    static constexpr int NZLS = (2 * K + 1) * (K + 1);          // z-lines of the state
-    static constexpr int ZP = state_pitch(K, (int)sizeof(Cx<P>));  // state plane pitch
+    static constexpr int K = N / 3, KX = K + 1;                 // x-modes kept
+    static constexpr int NZLS = (2 * K + 1) * KX;               // z-lines: modes of a z plane
+    static constexpr int ZP = state_pitch(K, (int)sizeof(Cx<P>));  // plane pitch (whole 128-byte lines)
     static constexpr int S = (2 * K + 1) * ZP;                  // state elements per component
-    static constexpr int NYL = N * PX;                          // y-lines
+    static constexpr int NYL = N * KX;                          // y-lines
+    // y-pencil buffers are blocked by z: ZB consecutive z rows (BL = ZB (K+1)
+    // lines, the fewest that fill whole 128-byte lines) are stored together,
+    // position by position, so that a pass's position stride is BL values
+    // (5.5 KB at N = 256) instead of the whole y-line count
+    static constexpr int TLB = 128 / (int)sizeof(Cx<P>);
+    static constexpr int ZB = TLB / gcd_int(KX, TLB), BL = ZB * KX;
+    // element of line L at position p of a y-pencil buffer with NP positions
+    __device__ static constexpr uint32_t yel(int L, int p, int NP) {
+        return (uint32_t)(L / BL) * (uint32_t)(NP * BL) + (uint32_t)p * BL + (uint32_t)(L % BL);
+    }
     static constexpr int E = E_ > N ? N : E_;
     static constexpr int M = N / E;
     // Lines per workgroup of the y/z pencil passes: at least 256 threads and
     // at least one 128-byte line per position (16 FP32 / 8 FP64 consecutive
-    // lines), so that every store covers whole lines; at most 1024 threads (512
+    // lines, a multiple of which is where every tile starts), so that every
+    // store covers whole lines; at most 1024 threads (512
     // with 16 values per thread, so that a wave may use 256 VGPRs); gfx950
     // gives a workgroup up to 160 KiB of LDS.
     static constexpr int TL = 128 / (int)sizeof(Cx<P>);
@@ -161,13 +173,14 @@ __device__ __forceinline__ void load_trunc(Cx<P> *v, const Fld<P> &f, uint32_t b
 }
 
 // ================================================================== zinv
-// z-lines L = iy PX + kx of the output (m_y, m_x) pairs; pad lines (kx > K)
-// carry zeros.  in u_hat [3][2K+1][ZP]; out (bufA) [5][N (z)][NZL]:
+// z-lines L = iy (K+1) + kx, the (m_y, m_x) pairs numbered as in a state
+// plane; lines NZLS..ZP-1 (a plane's pad) carry zeros.  in u_hat
+// [3][2K+1][ZP]; out (bufA) [5][N (z)][ZP]:
 // U_x, U_y, U_z, W_x = Z^-1[i k_z u_x], W_y = Z^-1[i k_z u_y]
 template <typename P, int N, int EV>
 __global__ void __launch_bounds__((Cfg<P, N, EV>::NT), (Cfg<P, N, EV>::PMINW)) k_zinv(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ twg) {
     using C = Cfg<P, N, EV>;
-    constexpr int E = C::E, M = C::M, T = C::T, NZL = C::NZL;
+    constexpr int E = C::E, M = C::M, T = C::T, ZP = C::ZP;
     __shared__ LdsT<P> lds[N * T];
     __shared__ Cx<P> tw[twiddle_span(N, E)];               // twiddles in LDS: no global load inside the transforms
     for (int i = (int)threadIdx.x; i < twiddle_span(N, E); i += (int)blockDim.x) tw[i] = twg[i];
@@ -176,17 +189,16 @@ __global__ void __launch_bounds__((Cfg<P, N, EV>::NT), (Cfg<P, N, EV>::PMINW)) k
     const MemberDev &md = mems[mem_i];
     const int l = threadIdx.x % T, t = threadIdx.x / T;
     const int L = tile * T + l;
-    const bool inb = L < NZL;                                   // output line (written)
-    const int kx = L % C::PX, iy = L / C::PX;
-    const bool valid = inb && kx <= C::K;                       // retained line (read)
-    const uint32_t Ls = valid ? (uint32_t)(iy * (C::K + 1) + kx) : 0u;   // the line in the state
+    const bool inb = L < ZP;                                    // output line (written)
+    const bool valid = L < C::NZLS;                             // retained line (read)
+    const uint32_t Ls = valid ? (uint32_t)L : 0u;               // the line in the state
     const P dk = (P)md.dk;
     auto kz = [&](int m) { return dk * (P)mode_of(t + M * m, N); };
     auto store = [&](const Cx<P> *v, int f) {
         if (inb) {
-            const Fld<P> o(md.bufA, (long long)f * N * NZL);
+            const Fld<P> o(md.bufA, (long long)f * N * ZP);
 #pragma unroll
-            for (int s = 0; s < E; s++) o.st((uint32_t)Plan<N, E>::out_pos(t, s) * NZL + L, v[s]);
+            for (int s = 0; s < E; s++) o.st((uint32_t)Plan<N, E>::out_pos(t, s) * ZP + L, v[s]);
         }
     };
     Cx<P> a[E], b[E], p[E];
@@ -212,12 +224,13 @@ __global__ void __launch_bounds__((Cfg<P, N, EV>::NT), (Cfg<P, N, EV>::PMINW)) k
 }
 
 // ================================================================== yinv
-// y-lines L = z PX + kx.  in bufA [5][N][NZL]; out bufB [6][N (z)][N (y)][PX]:
-// u_x, u_y, u_z, omega_x, omega_y, omega_z (pad lines kx > K carry zeros)
+// y-lines L = z (K+1) + kx.  in bufA [5][N (z)][ZP] (line L at iy (K+1) of
+// plane z); out bufB [6][N / ZB][N (y)][BL] (Cfg::yel):
+// u_x, u_y, u_z, omega_x, omega_y, omega_z
 template <typename P, int N, int EV>
 __global__ void __launch_bounds__((Cfg<P, N, EV>::NT)) k_yinv(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ twg) {
     using C = Cfg<P, N, EV>;
-    constexpr int E = C::E, M = C::M, T = C::T, K = C::K, NZL = C::NZL;
+    constexpr int E = C::E, M = C::M, T = C::T, KX = C::KX, ZP = C::ZP, NYL = C::NYL;
     __shared__ LdsT<P> lds[N * T];
     __shared__ Cx<P> tw[twiddle_span(N, E)];               // twiddles in LDS: no global load inside the transforms
     for (int i = (int)threadIdx.x; i < twiddle_span(N, E); i += (int)blockDim.x) tw[i] = twg[i];
@@ -226,24 +239,23 @@ __global__ void __launch_bounds__((Cfg<P, N, EV>::NT)) k_yinv(const MemberDev *_
     const MemberDev &md = mems[mem_i];
     const int l = threadIdx.x % T, t = threadIdx.x / T;
     const int L = tile * T + l;
-    constexpr int PX = C::PX;
-    const bool inb = L < C::NYL;
-    const int z = inb ? L / PX : 0;
-    const int kx = inb ? L % PX : 0;
-    const bool valid = inb && kx <= K;
+    const bool inb = L < NYL;
+    const int z = inb ? L / KX : 0;
+    const int kx = inb ? L % KX : 0;
+    const bool valid = inb;
     const P dk = (P)md.dk;
     const P kxv = dk * (P)kx;
-    const uint32_t in_base = (uint32_t)z * NZL + kx;             // + iy PX
-    const uint32_t out_base = (uint32_t)z * N * PX + kx;         // + y PX
+    const uint32_t in_base = (uint32_t)z * ZP + kx;              // + iy (K+1)
+    const uint32_t out_base = C::yel(inb ? L : 0, 0, N);          // + y BL
     auto ky = [&](int m) { return dk * (P)mode_of(t + M * m, N); };
     auto load = [&](Cx<P> *v, int f) {
-        load_trunc<P, N, E>(v, Fld<P>(md.bufA, (long long)f * N * NZL), in_base, PX, t, valid);
+        load_trunc<P, N, E>(v, Fld<P>(md.bufA, (long long)f * N * ZP), in_base, KX, t, valid);
     };
     auto store = [&](const Cx<P> *v, int f) {
         if (inb) {
-            const Fld<P> o(md.bufB, (long long)f * N * N * PX);
+            const Fld<P> o(md.bufB, (long long)f * N * NYL);
 #pragma unroll
-            for (int s = 0; s < E; s++) o.st(out_base + (uint32_t)Plan<N, E>::out_pos(t, s) * PX, v[s]);
+            for (int s = 0; s < E; s++) o.st(out_base + (uint32_t)Plan<N, E>::out_pos(t, s) * C::BL, v[s]);
         }
     };
     Cx<P> a[E], b[E], p[E];
@@ -282,8 +294,9 @@ __global__ void __launch_bounds__((Cfg<P, N, EV>::NT)) k_yinv(const MemberDev *_
 }
 
 // ================================================================== xpass
-// Rows R = z N + y.  in bufB [6][N][N][PX]; out bufA [3][N][N][K+1] = x-transform
-// (unnormalised) of n = u x omega, truncated to m_x <= K.
+// Rows R = y N + z of K+1 x-modes.  in bufB [6][N][N][K+1]; out bufA
+// [3][N][N][K+1] = x-transform (unnormalised) of n = u x omega, truncated to
+// m_x <= K.
 // The T rows of a workgroup are contiguous in every field, so inputs are
 // copied into LDS (and outputs out of it) with linear, fully coalesced
 // accesses; the next field pair is fetched into registers while the current
@@ -291,14 +304,14 @@ __global__ void __launch_bounds__((Cfg<P, N, EV>::NT)) k_yinv(const MemberDev *_
 template <typename P, int N, int EV>
 __global__ void __launch_bounds__(256) k_xpass(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ twg, int stage) {
     using C = Cfg<P, N, EV>;
-    constexpr int E = C::E, M = C::M, T = C::TX, K = C::K, PX = C::PX;
-    constexpr long long FS = (long long)N * N * PX;           // elements per input field
-    constexpr long long FSO = (long long)N * N * (K + 1);     // elements per output field
-    constexpr int RW = T * PX;                                 // elements of the tile per input field
-    constexpr int RWO = T * (K + 1);                           // elements of the tile per output field
-    // staged rows are PX + 1 apart in LDS when PX is a multiple of 16, so that
-    // the rows of a wave fall in different banks
-    constexpr int LP = PX % 16 == 0 ? PX + 1 : PX, RWL = T * LP;
+    constexpr int E = C::E, M = C::M, T = C::TX, K = C::K, KX = C::KX;
+    constexpr long long FS = (long long)N * N * KX;           // elements per input field
+    constexpr long long FSO = (long long)N * N * KX;          // elements per output field
+    constexpr int RW = T * KX;                                 // elements of the tile per input field
+    constexpr int RWO = T * KX;                                // elements of the tile per output field
+    // staged rows are K + 2 apart in LDS when K + 1 is a multiple of 16, so
+    // that the rows of a wave fall in different banks
+    constexpr int LP = KX % 16 == 0 ? KX + 1 : KX, RWL = T * LP;
     constexpr int PER = (RW + 255) / 256;                      // staged elements per thread per field
     __shared__ LdsT<P> lds[N * T];
     __shared__ Cx<P> tw[twiddle_span(N, E)];               // twiddles in LDS: no global load inside the transforms
@@ -328,7 +341,7 @@ __global__ void __launch_bounds__(256) k_xpass(const MemberDev *__restrict__ mem
 #pragma unroll
             for (int i = 0; i < PER; i++) {
                 const int e = threadIdx.x + 256 * i;
-                if (e < RW) lds_put<P>(sb, h * RWL + e + (LP - PX) * (e / PX), st[h][i]);
+                if (e < RW) lds_put<P>(sb, h * RWL + e + (LP - KX) * (e / KX), st[h][i]);
             }
     };
     // packed two-for-one spectrum of the staged pair: C = A + i B, Hermitian fill
@@ -449,8 +462,7 @@ __global__ void __launch_bounds__(256) k_xpass(const MemberDev *__restrict__ mem
 template <typename P, int N, int E_> struct XCfg {
     static constexpr int K = N / 3, E = E_ > N ? N : E_, M = N / E;
     static constexpr int CS = (int)sizeof(Cx<P>), CPV = 16 / CS;
-    static constexpr int PX = kx_pitch(K, CS);                 // row pitch in HBM
-    static constexpr int RQ = (K + 1 + CPV - 1) / CPV * CPV;   // row length staged in LDS (whole vectors)
+    static constexpr int RQ = K + 1;                           // row pitch in HBM and in the LDS staging
     // FP32: each thread keeps its twiddles in registers; FP64: a table in LDS
     // (registers would cost the second wave per SIMD)
     static constexpr bool REGTW = sizeof(P) == 4;
@@ -468,9 +480,8 @@ template <typename P, int N, int E_> struct XCfg {
         return t < 1 ? 1 : t;
     }
     static constexpr int T = pick_t(), NTH = M * T;
-    static constexpr int RW = T * RQ;                      // staged elements of a tile per field
-    static constexpr int RVR = RQ / CPV;                   // 16-byte vectors read per row
-    static constexpr int RV = T * RVR;                     // vectors read per field tile
+    static constexpr int RW = T * RQ;                      // elements of a tile per field (contiguous in HBM)
+    static constexpr int RV = RW / CPV;                    // 16-byte vectors read per field tile
     static constexpr int RWO = T * (K + 1);                // elements written per field tile (rows of K + 1)
     static constexpr int RVO = RWO / CPV;
     static constexpr int D3 = dma_tile3_ops<RV, NTH>();     // copies per wave per staging buffer
@@ -484,7 +495,7 @@ template <typename P, int N, int E_> struct XCfg {
     static constexpr int W_LDS = WG_LDS * (NTH / 64) / 4;
     static constexpr int W_MAX = sizeof(P) == 4 ? 3 : 2;
     static constexpr int MINB = W_LDS < 1 ? 1 : (W_LDS < W_MAX ? W_LDS : W_MAX);
-    static_assert(PX % CPV == 0 && RWO % CPV == 0 && NTH % 64 == 0 && RV >= 64 && RVO >= 64 && D3 + S < 64,
+    static_assert(RW % CPV == 0 && RWO % CPV == 0 && NTH % 64 == 0 && RV >= 64 && RVO >= 64 && D3 + S < 64,
                   "x-pass tile shape");
 };
 
@@ -492,8 +503,8 @@ template <typename P, int N, int EV>
 __global__ void __launch_bounds__((XCfg<P, N, EV>::NTH), (XCfg<P, N, EV>::MINB)) k_xpass_dma(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ tw, int stage) {
     using C = XCfg<P, N, EV>;
     constexpr int E = C::E, M = C::M, T = C::T, K = C::K, NTH = C::NTH, RW = C::RW, RQ = C::RQ;
-    constexpr int PX = C::PX, RWO = C::RWO, RVO = C::RVO;
-    constexpr long long FSB = (long long)N * N * PX * C::CS;         // bytes per input field
+    constexpr int RWO = C::RWO, RVO = C::RVO;
+    constexpr long long FSB = (long long)N * N * RQ * C::CS;         // bytes per input field
     constexpr long long FSBO = (long long)N * N * (K + 1) * C::CS;   // bytes per output field
     __shared__ __attribute__((aligned(16))) LdsT<P> slot0[3 * RW];
     __shared__ __attribute__((aligned(16))) LdsT<P> slot1[3 * RW];
@@ -515,8 +526,8 @@ __global__ void __launch_bounds__((XCfg<P, N, EV>::NTH), (XCfg<P, N, EV>::MINB))
     }();
     const char *inb = (const char *)md.bufB;
     char *outb = (char *)md.bufA;
-    auto request = [&](LdsT<P> *dst, int tile, int f0) {      // fields f0..f0+2 of `tile`, rows without the pad
-        dma_rows3<C::RVR, PX * C::CS, T, NTH>(dst, inb + (long long)f0 * FSB + (long long)tile * T * PX * C::CS, FSB);
+    auto request = [&](LdsT<P> *dst, int tile, int f0) {      // fields f0..f0+2 of `tile`
+        dma_tile3<C::RV, NTH>(dst, inb + (long long)f0 * FSB + (long long)tile * RW * C::CS, FSB);
     };
     // packed two-for-one spectrum of fields (fa, fb): C = A + i B, Hermitian
     // fill.  Position n = t + M m; whole segments [M m, M m + M) below K, above
@@ -680,9 +691,8 @@ __global__ void __launch_bounds__((XCfg<P, N, EV>::NTH), (XCfg<P, N, EV>::MINB))
 constexpr bool xwave_ok(int N, int E, int CS) {
     const int M = N / (E > N ? N : E), K = N / 3, CPV = 16 / CS;
     if (M > 64 || 64 % M != 0) return false;
-    const int R = 64 / M, RQ = (K + 1 + CPV - 1) / CPV * CPV;
-    const int RV = R * (RQ / CPV), RWO = R * (K + 1);
-    if (RWO % CPV != 0 || RV < 64 || RWO / CPV < 64) return false;
+    const int R = 64 / M, RWO = R * (K + 1), RV = RWO / CPV;
+    if (RWO % CPV != 0 || RV < 64) return false;
     const int D3 = 3 * ((RV + 63) / 64), S = 3 * ((RWO / CPV + 63) / 64);
     return D3 + S < 64;
 }
@@ -691,11 +701,10 @@ template <typename P, int N, int E_> struct XWCfg {
     static constexpr int K = N / 3, E = E_ > N ? N : E_, M = N / E;
     static constexpr int R = 64 / M;                           // rows per tile (one wave)
     static constexpr int CS = (int)sizeof(Cx<P>), CPV = 16 / CS;
-    static constexpr int PX = kx_pitch(K, CS);
-    static constexpr int RQ = (K + 1 + CPV - 1) / CPV * CPV;   // staged row length (whole vectors)
+    static constexpr int RQ = K + 1;                           // row pitch in HBM and in the LDS staging
     static constexpr bool REGTW = sizeof(P) == 4;               // FP32: twiddles in registers
     static constexpr int NTW = REGTW ? 1 : twiddle_span(N, E);
-    static constexpr int RW = R * RQ, RVR = RQ / CPV, RV = R * RVR;
+    static constexpr int RW = R * RQ, RV = RW / CPV;            // a tile's elements / 16-byte vectors per field
     static constexpr int RWO = R * (K + 1), RVO = RWO / CPV;
     static constexpr int D3 = dma_tile3_ops<RV, 64>();          // copies per staging buffer
     static constexpr int S = dma_tile3_ops<RVO, 64>();          // 16-byte stores per tile
@@ -707,7 +716,7 @@ template <typename P, int N, int E_> struct XWCfg {
     static constexpr int WPS = (int)(163840 / ((LDS_BYTES + 511) / 512 * 512)) / 4;
     static constexpr int MINW = WPS < 1 ? 1 : (WPS > 4 ? 4 : WPS);
     static_assert(M <= 64 && 64 % M == 0, "a line must fit one wave");
-    static_assert(PX % CPV == 0 && RWO % CPV == 0 && RV >= 64 && RVO >= 64 && D3 + S < 64, "x-pass tile shape");
+    static_assert(RW % CPV == 0 && RWO % CPV == 0 && RV >= 64 && RVO >= 64 && D3 + S < 64, "x-pass tile shape");
 };
 
 template <typename P, int N, int EV>
@@ -715,8 +724,8 @@ __global__ void __launch_bounds__(64, (XWCfg<P, N, EV>::MINW)) k_xpass_wave(cons
     using C = XWCfg<P, N, EV>;
     using LY = WaveLay<P, N>;
     constexpr int E = C::E, M = C::M, R = C::R, K = C::K, RW = C::RW, RQ = C::RQ;
-    constexpr int PX = C::PX, RWO = C::RWO, RVO = C::RVO;
-    constexpr long long FSB = (long long)N * N * PX * C::CS;         // bytes per input field
+    constexpr int RWO = C::RWO, RVO = C::RVO;
+    constexpr long long FSB = (long long)N * N * RQ * C::CS;         // bytes per input field
     constexpr long long FSBO = (long long)N * N * (K + 1) * C::CS;   // bytes per output field
     __shared__ __attribute__((aligned(16))) LdsT<P> slot0[3 * RW];
     __shared__ __attribute__((aligned(16))) LdsT<P> slot1[3 * RW];
@@ -740,7 +749,7 @@ __global__ void __launch_bounds__(64, (XWCfg<P, N, EV>::MINW)) k_xpass_wave(cons
     const char *inb = (const char *)md.bufB;
     char *outb = (char *)md.bufA;
     auto request = [&](LdsT<P> *dst, int tile, int f0) {      // fields f0..f0+2 of the tile's R rows
-        dma_rows3<C::RVR, PX * C::CS, R, 64>(dst, inb + (long long)f0 * FSB + (long long)tile * R * PX * C::CS, FSB);
+        dma_tile3<C::RV, 64>(dst, inb + (long long)f0 * FSB + (long long)tile * RW * C::CS, FSB);
     };
     // packed two-for-one spectrum of fields (fa, fb), as in the streamed x pass
     auto gather = [&](Cx<P> *v, const LdsT<P> *fa, const LdsT<P> *fb) {
@@ -901,8 +910,8 @@ __global__ void __launch_bounds__(64, (XW2Cfg<P, N, EV>::MINW)) k_xpass_wave2(co
     using C2 = XW2Cfg<P, N, EV>;
     using LY = WaveLay<P, N>;
     constexpr int E = C::E, M = C::M, R = C::R, K = C::K, RW = C::RW, RQ = C::RQ;
-    constexpr int PX = C::PX, RWO = C::RWO, RVO = C::RVO, D2 = C2::D2, S = C::S;
-    constexpr long long FSB = (long long)N * N * PX * C::CS;         // bytes per input field
+    constexpr int RWO = C::RWO, RVO = C::RVO, D2 = C2::D2, S = C::S;
+    constexpr long long FSB = (long long)N * N * RQ * C::CS;         // bytes per input field
     constexpr long long FSBO = (long long)N * N * (K + 1) * C::CS;   // bytes per output field
     __shared__ __attribute__((aligned(16))) LdsT<P> slotA[2 * RW];
     __shared__ __attribute__((aligned(16))) LdsT<P> slotB[2 * RW];
@@ -927,7 +936,7 @@ __global__ void __launch_bounds__(64, (XW2Cfg<P, N, EV>::MINW)) k_xpass_wave2(co
     char *outb = (char *)md.bufA;
     auto slot = [&](int i) -> LdsT<P> * { return i ? slotB : slotA; };
     auto request = [&](LdsT<P> *dst, int tile, int pair) {    // fields 2 pair, 2 pair + 1 of the tile's R rows
-        dma_rows<2, C::RVR, PX * C::CS, R, 64>(dst, inb + (long long)(2 * pair) * FSB + (long long)tile * R * PX * C::CS, FSB);
+        dma_rows<2, C::RV, C::RV * 16, 1, 64>(dst, inb + (long long)(2 * pair) * FSB + (long long)tile * RW * C::CS, FSB);
     };
     auto gather = [&](Cx<P> *v, const LdsT<P> *fa, const LdsT<P> *fb) {
 #pragma unroll
@@ -1070,13 +1079,13 @@ __global__ void __launch_bounds__(64, (XW2Cfg<P, N, EV>::MINW)) k_xpass_wave2(co
 }
 
 // ================================================================== yfwd
-// y-lines L = z PX + kx.  in bufA [3][N][N][K+1]; out bufB [3][N (z)][2K+1][PX]
-// (pad lines kx > K carry zeros)
+// y-lines L = z (K+1) + kx.  in bufA [3][N / ZB][N (y)][BL] (the x-pass
+// rows); out bufB [3][N / ZB][2K+1 (m_y)][BL]
 template <typename P, int N, int EV>
 __global__ void __launch_bounds__((Cfg<P, N, EV>::NT)) k_yfwd(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ twg) {
     using C = Cfg<P, N, EV>;
-    constexpr int E = C::E, M = C::M, T = C::T, K = C::K, NZL = C::NZL, PX = C::PX;
-    constexpr long long FS = (long long)N * N * (K + 1);
+    constexpr int E = C::E, M = C::M, T = C::T, K = C::K, NYL = C::NYL;
+    constexpr long long FS = (long long)N * NYL;
     __shared__ LdsT<P> lds[N * T];
     __shared__ Cx<P> tw[twiddle_span(N, E)];               // twiddles in LDS: no global load inside the transforms
     for (int i = (int)threadIdx.x; i < twiddle_span(N, E); i += (int)blockDim.x) tw[i] = twg[i];
@@ -1085,16 +1094,14 @@ __global__ void __launch_bounds__((Cfg<P, N, EV>::NT)) k_yfwd(const MemberDev *_
     const MemberDev &md = mems[mem_i];
     const int l = threadIdx.x % T, t = threadIdx.x / T;
     const int L = tile * T + l;
-    const bool inb = L < C::NYL;
-    const int z = inb ? L / PX : 0;
-    const int kx = inb ? L % PX : 0;
-    const bool valid = inb && kx <= K;
-    const uint32_t in_base = (uint32_t)z * N * (K + 1) + kx;
-    const uint32_t out_base = (uint32_t)z * NZL + kx;
+    const bool inb = L < NYL;
+    const bool valid = inb;
+    const uint32_t in_base = C::yel(inb ? L : 0, 0, N);           // + y BL
+    const uint32_t out_base = C::yel(inb ? L : 0, 0, 2 * K + 1);  // + m_y BL
     auto load = [&](Cx<P> *v, int f) {
         const Fld<P> in(md.bufA, f * FS);
 #pragma unroll
-        for (int m = 0; m < E; m++) v[m] = valid ? in.ld(in_base + (uint32_t)(t + M * m) * (K + 1)) : czero<P>();
+        for (int m = 0; m < E; m++) v[m] = valid ? in.ld(in_base + (uint32_t)(t + M * m) * C::BL) : czero<P>();
     };
     Cx<P> a[E], p[E];
     load(a, 0);
@@ -1103,11 +1110,11 @@ __global__ void __launch_bounds__((Cfg<P, N, EV>::NT)) k_yfwd(const MemberDev *_
         if (f < 2) load(p, f + 1);
         line_fft<P, N, E, T, -1>(a, lds, l, t, tw);
         if (inb) {
-            const Fld<P> o(md.bufB, (long long)f * N * NZL);
+            const Fld<P> o(md.bufB, (long long)f * (2 * K + 1) * NYL);
 #pragma unroll
             for (int s = 0; s < E; s++) {
                 const int my = mode_of(Plan<N, E>::out_pos(t, s), N);
-                if (my >= -K && my <= K) o.st(out_base + (uint32_t)(my >= 0 ? my : my + 2 * K + 1) * PX, a[s]);
+                if (my >= -K && my <= K) o.st(out_base + (uint32_t)(my >= 0 ? my : my + 2 * K + 1) * C::BL, a[s]);
             }
         }
         if (f < 2) {
@@ -1118,13 +1125,15 @@ __global__ void __launch_bounds__((Cfg<P, N, EV>::NT)) k_yfwd(const MemberDev *_
 }
 
 // ================================================================== zfwd + update
-// z-lines L = iy (K+1) + kx of the state (line iy PX + kx of bufB [3][N][NZL]).
+// z-lines L = iy (K+1) + kx of the state; in bufB [3][N / ZB][2K+1][BL]
+// line L's position z is at block z / ZB, row iy, entry (z mod ZB)(K+1) + kx.
 // Forward along z, keep |m_z| <= K, normalise by N^-3, project, add band
 // forcing, RK stage update.
 template <typename P, int N>
 __global__ void __launch_bounds__((Cfg<P, N, 8>::NTZ), (Cfg<P, N, 8>::ZMINB)) k_zfwd_update(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ twg, int stage) {
     using C = Cfg<P, N, 8>;
-    constexpr int E = C::EZ, M = C::MZ, T = C::TZ, K = C::K, NZL = C::NZL, S = C::S;   // NZL: bufB lines
+    constexpr int E = C::EZ, M = C::MZ, T = C::TZ, K = C::K, KX = C::KX, NYL = C::NYL, S = C::S;
+    constexpr int ZB = C::ZB, BL = C::BL;
     constexpr int NT = C::NTZ;
     static_assert(NT * sizeof(double) <= N * T * sizeof(LdsT<P>), "reduction scratch reuses the FFT LDS");
     __shared__ LdsT<P> lds[N * T];
@@ -1139,14 +1148,18 @@ __global__ void __launch_bounds__((Cfg<P, N, 8>::NTZ), (Cfg<P, N, 8>::ZMINB)) k_
     const bool valid = L < C::NZLS;
     const int iy = valid ? L / (K + 1) : 0;
     const int kx = valid ? L % (K + 1) : 0;
-    const uint32_t Lz = (uint32_t)(iy * C::PX + kx);           // the line in bufB
+    const uint32_t Lz = (uint32_t)iy * BL + (uint32_t)kx;      // position 0 of the line in bufB
     const int my = iy <= K ? iy : iy - (2 * K + 1);
     Cx<P> a[3][E];
 #pragma unroll
     for (int f = 0; f < 3; f++) {
-        const Fld<P> in(md.bufB, (long long)f * N * NZL);
+        const Fld<P> in(md.bufB, (long long)f * (2 * K + 1) * NYL);
 #pragma unroll
-        for (int m = 0; m < E; m++) a[f][m] = valid ? in.ld((uint32_t)(t + M * m) * NZL + Lz) : czero<P>();
+        for (int m = 0; m < E; m++) {
+            const int z = t + M * m;
+            a[f][m] = valid ? in.ld((uint32_t)(z / ZB) * (uint32_t)((2 * K + 1) * BL) + (uint32_t)(z % ZB) * KX + Lz)
+                            : czero<P>();
+        }
     }
 #pragma unroll
     for (int f = 0; f < 3; f++) line_fft<P, N, E, T, -1>(a[f], lds, l, t, tw);
@@ -1279,7 +1292,7 @@ template <typename P, int N, int EV>
 static hipError_t run_pencil(int pass, const MemberDev *mem, int count, int stage, const Cx<P> *tw, hipStream_t s) {
     using C = Cfg<P, N, EV>;
     switch (pass) {
-    case P_ZINV: k_zinv<P, N, EV><<<dim3((C::NZL + C::T - 1) / C::T, count), C::NT, 0, s>>>(mem, tw); break;
+    case P_ZINV: k_zinv<P, N, EV><<<dim3((C::ZP + C::T - 1) / C::T, count), C::NT, 0, s>>>(mem, tw); break;
     case P_YINV: k_yinv<P, N, EV><<<dim3((C::NYL + C::T - 1) / C::T, count), C::NT, 0, s>>>(mem, tw); break;
     case P_XPASS: k_xpass<P, N, EV><<<dim3((unsigned)((long long)N * N / C::TX), count), 256, 0, s>>>(mem, tw, stage); break;
     case P_YFWD: k_yfwd<P, N, EV><<<dim3((C::NYL + C::T - 1) / C::T, count), C::NT, 0, s>>>(mem, tw); break;
