@@ -190,6 +190,13 @@ __device__ __forceinline__ int log_bin(double x, const double *edge, int nb, flo
     return c;
 }
 __device__ __forceinline__ int slot_1d(int b, int nb) { return b >= 0 ? b : (b == -1 ? nb : (b == -2 ? nb + 1 : nb + 2)); }
+// slot_1d(bin_of(x, lo, scale, nb), nb) with fewer operations: the same FP64
+// value (x - lo) scale decides the bin (truncation is floor on [0, nb))
+__device__ __forceinline__ int slot_of(double x, double lo, double scale, int nb) {
+    const double d = (x - lo) * scale;
+    const int b = d >= (double)nb ? nb + 1 : (int)d;
+    return x < lo ? nb : (d == d ? b : nb + 2);
+}
 
 // Replicated hot bins of the statistics pass: copies per bin and central bins
 // of each 1-D histogram; copies per bin and central bins per axis of the QR
@@ -264,13 +271,20 @@ __global__ void __launch_bounds__(256, 2) k_gxstats(const MemberDev *__restrict_
     c0[3] = c0[2];
     if (!(md.eps_m > 0.0) || !(md.nu > 0.0)) { c0[0] = -1; c0[1] = -1; }
     const int q0 = c0_of((0.0 - h.q_lo) * h.q_scale, h.qb, CQ), r0 = c0_of((0.0 - h.r_lo) * h.r_scale, h.qb, CQ);
+    // first bins of the replicated QR centre, far above every bin where there is none
+    const int cq0 = q0 >= 0 && r0 >= 0 ? q0 : (1 << 30), cr0 = q0 >= 0 && r0 >= 0 ? r0 : (1 << 30);
     unsigned int *single[4] = {h_le, h_lw, h_al, h_at};
     // one LDS atomic per sample on the selected counter (a replicated hot bin
     // or the plain bin): lanes of one wave that differ in the choice do not
     // split into two atomic instructions
+    // (a histogram without a replicated window gets a first bin far above
+    // every slot, so that one unsigned comparison decides)
+    int cw0[4];
+#pragma unroll
+    for (int i = 0; i < 4; i++) cw0[i] = c0[i] >= 0 ? c0[i] : (1 << 30);
     auto add1 = [&](int hist, int slot) {
-        const int rel = slot - c0[hist];
-        const bool hot = c0[hist] >= 0 && rel >= 0 && rel < CW;
+        const unsigned rel = (unsigned)(slot - cw0[hist]);
+        const bool hot = rel < (unsigned)CW;
         unsigned int *p = hot ? &cen1[hist][hot ? rel : 0][grp] : &single[hist][slot];
         atomicAdd(p, 1u);
     };
@@ -380,14 +394,15 @@ __global__ void __launch_bounds__(256, 2) k_gxstats(const MemberDev *__restrict_
             const double es = 2.0 * nu * ss * h.inv_eps_ref, ws = ens * h.om_scale;
             {   // QR: replicated centre, the LDS window, the LDS outside/NaN
                 // counters (one LDS atomic on the selected counter), else global
+                // the bins of bin_of: in range iff !(x < lo) and (x - lo) scale < nb
                 const bool nan = qs != qs || rs != rs;
-                const int bq = nan ? -1 : bin_of(qs, h.q_lo, h.q_scale, h.qb);
-                const int br = nan ? -1 : bin_of(rs, h.r_lo, h.r_scale, h.qb);
-                const bool out = !nan && (bq < 0 || br < 0);
-                const bool cen = !nan && !out && q0 >= 0 && r0 >= 0 && bq >= q0 && bq < q0 + CQ && br >= r0 &&
-                                 br < r0 + CQ;
-                const bool win = !nan && !out && !cen && bq >= h.win0 && bq < h.win0 + h.win && br >= h.win0 &&
-                                 br < h.win0 + h.win;
+                const double dq = (qs - h.q_lo) * h.q_scale, dr = (rs - h.r_lo) * h.r_scale;
+                const bool inq = !(qs < h.q_lo) && dq < (double)h.qb, inr = !(rs < h.r_lo) && dr < (double)h.qb;
+                const int bq = inq ? (int)dq : 0, br = inr ? (int)dr : 0;
+                const bool out = !nan && !(inq && inr);
+                const bool cen = !nan && !out && (unsigned)(bq - cq0) < (unsigned)CQ && (unsigned)(br - cr0) < (unsigned)CQ;
+                const bool win = !nan && !out && !cen && (unsigned)(bq - h.win0) < (unsigned)h.win &&
+                                 (unsigned)(br - h.win0) < (unsigned)h.win;
                 if (nan || out || cen || win) {
                     unsigned int *p = nan ? &qspec[2]
                                     : out ? &qspec[0]
@@ -405,14 +420,18 @@ __global__ void __launch_bounds__(256, 2) k_gxstats(const MemberDev *__restrict_
 #pragma unroll
                 for (int j = 0; j < 3; j++) {
                     const double x = a[i][j] * h.tau;
-                    add1(i == j ? 2 : 3, slot_1d(bin_of(x, h.a_lo, h.a_scale, h.ab), h.ab));
-                    double xp = 1.0;
-#pragma unroll
-                    for (int p = 0; p < 6; p++) { xp *= x; mom[(i == j ? 0 : 6) + p] += xp; }
+                    add1(i == j ? 2 : 3, slot_of(x, h.a_lo, h.a_scale, h.ab));
+                    // x .. x^6 from x^2 and x^4, the odd powers fused into the sums
+                    double *mo = mom + (i == j ? 0 : 6);
+                    const double x2 = x * x, x4 = x2 * x2;
+                    mo[0] += x; mo[1] += x2; mo[2] = fma(x2, x, mo[2]);
+                    mo[3] += x4; mo[4] = fma(x4, x, mo[4]); mo[5] = fma(x4, x2, mo[5]);
                 }
-            double ep = 1.0, wp = 1.0;
-#pragma unroll
-            for (int p = 0; p < 4; p++) { ep *= es; wp *= ws; mom[12 + p] += ep; mom[16 + p] += wp; }
+            {
+                const double e2 = es * es, w2 = ws * ws;
+                mom[12] += es; mom[13] += e2; mom[14] = fma(e2, es, mom[14]); mom[15] = fma(e2, e2, mom[15]);
+                mom[16] += ws; mom[17] += w2; mom[18] = fma(w2, ws, mom[18]); mom[19] = fma(w2, w2, mom[19]);
+            }
             mom[20] += qs; mom[21] += rs;
             mom[22] += ss * h.tau * h.tau;
             mom[23] += tr * tr * h.tau * h.tau;
