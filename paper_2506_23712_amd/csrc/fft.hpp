@@ -61,16 +61,37 @@ template <int DIR, typename P> __device__ __forceinline__ void dft2(Cx<P> &a, Cx
     Cx<P> t = a; a = t + b; b = t - b;
 }
 
-template <int DIR, typename P> __device__ __forceinline__ void dft4(Cx<P> &a0, Cx<P> &a1, Cx<P> &a2, Cx<P> &a3) {
-    Cx<P> t0 = a0 + a2, t1 = a0 - a2, t2 = a1 + a3, t3 = rot90<DIR>(a1 - a3);
+template <typename P> __device__ __forceinline__ Cx<P> cneg(Cx<P> a) { return {-a.re, -a.im}; }
+
+// a +- b where bit 0 of Z says a is known to be zero and bit 1 that b is
+// (known zeros are the truncated modes of an inverse transform's input; the
+// sums skip them)
+template <int Z, typename P> __device__ __forceinline__ Cx<P> zadd(Cx<P> a, Cx<P> b) {
+    if constexpr ((Z & 2) != 0) return a;
+    else if constexpr ((Z & 1) != 0) return b;
+    else return a + b;
+}
+template <int Z, typename P> __device__ __forceinline__ Cx<P> zsub(Cx<P> a, Cx<P> b) {
+    if constexpr ((Z & 2) != 0) return a;
+    else if constexpr ((Z & 1) != 0) return cneg(b);
+    else return a - b;
+}
+
+// ZM: bit i set = input a_i is known to be zero
+template <int DIR, unsigned ZM = 0u, typename P>
+__device__ __forceinline__ void dft4(Cx<P> &a0, Cx<P> &a1, Cx<P> &a2, Cx<P> &a3) {
+    constexpr int Z02 = (int)((ZM & 1u) | ((ZM >> 1) & 2u)), Z13 = (int)(((ZM >> 1) & 1u) | ((ZM >> 2) & 2u));
+    Cx<P> t0 = zadd<Z02>(a0, a2), t1 = zsub<Z02>(a0, a2), t2 = zadd<Z13>(a1, a3), t3 = rot90<DIR>(zsub<Z13>(a1, a3));
     a0 = t0 + t2; a2 = t0 - t2; a1 = t1 + t3; a3 = t1 - t3;
 }
 
-template <int DIR, typename P> __device__ __forceinline__ void dft8(Cx<P> *v) {
+template <int DIR, unsigned ZM = 0u, typename P> __device__ __forceinline__ void dft8(Cx<P> *v) {
     Cx<P> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
     Cx<P> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
-    dft4<DIR>(e0, e1, e2, e3);
-    dft4<DIR>(o0, o1, o2, o3);
+    constexpr unsigned ZE = (ZM & 1u) | ((ZM >> 1) & 2u) | ((ZM >> 2) & 4u) | ((ZM >> 3) & 8u);
+    constexpr unsigned ZO = ((ZM >> 1) & 1u) | ((ZM >> 2) & 2u) | ((ZM >> 3) & 4u) | ((ZM >> 4) & 8u);
+    dft4<DIR, ZE>(e0, e1, e2, e3);
+    dft4<DIR, ZO>(o0, o1, o2, o3);
     const P r = P(ENS_R2);
     o1 = rotc<DIR>(o1, r, r);
     o2 = rot90<DIR>(o2);
@@ -81,14 +102,22 @@ template <int DIR, typename P> __device__ __forceinline__ void dft8(Cx<P> *v) {
     v[3] = e3 + o3; v[7] = e3 - o3;
 }
 
-template <int DIR, typename P> __device__ __forceinline__ void dft16(Cx<P> *v) {
+// inputs n2, n2 + 4, n2 + 8, n2 + 12 of a 16-point mask
+template <int n2> constexpr unsigned sub4(unsigned zm) {
+    return ((zm >> n2) & 1u) | ((zm >> (n2 + 3)) & 2u) | ((zm >> (n2 + 6)) & 4u) | ((zm >> (n2 + 9)) & 8u);
+}
+
+template <int DIR, unsigned ZM = 0u, typename P> __device__ __forceinline__ void dft16(Cx<P> *v) {
     // 16 = 4 x 4: n = 4 n1 + n2, k = k1 + 4 k2
     Cx<P> y[4][4];
-#pragma unroll
-    for (int n2 = 0; n2 < 4; n2++) {
-        y[n2][0] = v[n2]; y[n2][1] = v[n2 + 4]; y[n2][2] = v[n2 + 8]; y[n2][3] = v[n2 + 12];
-        dft4<DIR>(y[n2][0], y[n2][1], y[n2][2], y[n2][3]);
-    }
+    y[0][0] = v[0]; y[0][1] = v[4]; y[0][2] = v[8]; y[0][3] = v[12];
+    y[1][0] = v[1]; y[1][1] = v[5]; y[1][2] = v[9]; y[1][3] = v[13];
+    y[2][0] = v[2]; y[2][1] = v[6]; y[2][2] = v[10]; y[2][3] = v[14];
+    y[3][0] = v[3]; y[3][1] = v[7]; y[3][2] = v[11]; y[3][3] = v[15];
+    dft4<DIR, sub4<0>(ZM)>(y[0][0], y[0][1], y[0][2], y[0][3]);
+    dft4<DIR, sub4<1>(ZM)>(y[1][0], y[1][1], y[1][2], y[1][3]);
+    dft4<DIR, sub4<2>(ZM)>(y[2][0], y[2][1], y[2][2], y[2][3]);
+    dft4<DIR, sub4<3>(ZM)>(y[3][0], y[3][1], y[3][2], y[3][3]);
     const P c = P(ENS_C8), s = P(ENS_S8), r = P(ENS_R2);
     // twiddles w16^(n2 k1)
     y[1][1] = rotc<DIR>(y[1][1], c, s);
@@ -108,12 +137,23 @@ template <int DIR, typename P> __device__ __forceinline__ void dft16(Cx<P> *v) {
     }
 }
 
-template <int R, int DIR, typename P> __device__ __forceinline__ void dft(Cx<P> *v) {
+template <int R, int DIR, unsigned ZM = 0u, typename P> __device__ __forceinline__ void dft(Cx<P> *v) {
     if constexpr (R == 2) dft2<DIR>(v[0], v[1]);
-    else if constexpr (R == 4) dft4<DIR>(v[0], v[1], v[2], v[3]);
-    else if constexpr (R == 8) dft8<DIR>(v);
-    else if constexpr (R == 16) dft16<DIR>(v);
+    else if constexpr (R == 4) dft4<DIR, ZM>(v[0], v[1], v[2], v[3]);
+    else if constexpr (R == 8) dft8<DIR, ZM>(v);
+    else if constexpr (R == 16) dft16<DIR, ZM>(v);
     else static_assert(R == 2, "unsupported radix");
+}
+
+// Input slots m of a thread whose positions t + M m (every t < M) all lie
+// strictly between K and N - K, i.e. hold truncated modes (zero) of an
+// inverse transform's input: bit m of the mask.
+__host__ __device__ constexpr unsigned truncated_slots(int N, int E, int K) {
+    const int M = N / E;
+    unsigned z = 0u;
+    for (int m = 0; m < E && m < 32; m++)
+        if (M * m > K && M * m + M - 1 < N - K) z |= 1u << m;
+    return z;
 }
 
 // ---------------------------------------------------------------- stage plan
@@ -303,11 +343,12 @@ __device__ __forceinline__ void run_stages(Cx<P> *v, LdsT<P> *lds, int l, int t,
 
 // Forward-flow transform.  All threads of the workgroup must call it (it
 // contains barriers; with SB = 2 all lanes of the wave).  LDS: N*T elements
-// of V2<P> (RowLay), or N per line of the wave (WaveLay).
-template <typename P, int N, int E, int T, int DIR, int SB = 0, class LY = RowLay<P, T>, class TW>
+// of V2<P> (RowLay), or N per line of the wave (WaveLay).  ZM: input slots
+// known to be zero (truncated_slots), skipped by the first stage's sums.
+template <typename P, int N, int E, int T, int DIR, int SB = 0, class LY = RowLay<P, T>, unsigned ZM = 0u, class TW>
 __device__ __forceinline__ void line_fft(Cx<P> *v, LdsT<P> *lds, int l, int t, const TW &tw) {
     static_assert(N % E == 0 && N >= E, "line length must be a multiple of E");
-    dft<E, DIR>(v);                       // stage 0: span 1, no twiddles
+    dft<E, DIR, ZM>(v);                   // stage 0: span 1, no twiddles
     run_stages<P, N, E, T, DIR, 1, SB, LY>(v, lds, l, t, tw);
 }
 

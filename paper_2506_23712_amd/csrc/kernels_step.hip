@@ -367,7 +367,7 @@ __global__ void __launch_bounds__(256) k_xpass(const MemberDev *__restrict__ mem
         __syncthreads();                                       // staged pair visible
         gather(v);
         if (pr < 2) fetch(2 * pr + 2);                         // next pair in flight during the transform
-        line_fft<P, N, E, T, +1>(v, lds, l, t, tw);
+        line_fft<P, N, E, T, +1, 0, RowLay<P, T>, truncated_slots(N, E, K)>(v, lds, l, t, tw);
 #pragma unroll
         for (int s = 0; s < E; s++) { ph[2 * pr][s] = v[s].re; ph[2 * pr + 1][s] = v[s].im; }
         if (pr < 2) {
@@ -404,7 +404,8 @@ __global__ void __launch_bounds__(256) k_xpass(const MemberDev *__restrict__ mem
     line_fft_T<P, N, E, T, -1>(d2, lds, l, t, tw);
     __syncthreads();
 #pragma unroll
-    for (int m = 0; m < E; m++) lds_put<P>(lds, (t + M * m) * T + l, d1[m]);
+    for (int m = 0; m < E; m++)          // the split reads only the partner positions 0 and >= N - K
+        if (m == 0 || M * m + M - 1 >= N - K) lds_put<P>(lds, (t + M * m) * T + l, d1[m]);
     __syncthreads();
     if (stage == 0 && threadIdx.x == 0) {
         double dm = redmax[0];
@@ -594,7 +595,7 @@ __global__ void __launch_bounds__((XCfg<P, N, EV>::NTH), (XCfg<P, N, EV>::MINB))
     for (int tile = t0; tile < t1; tile++) {
         const bool more = tile + 1 < t1;
         P ph[6][E];
-        line_fft<P, N, E, T, +1, true>(v, lds, l, t, twx);
+        line_fft<P, N, E, T, +1, 1, RowLay<P, T>, truncated_slots(N, E, K)>(v, lds, l, t, twx);
 #pragma unroll
         for (int s = 0; s < E; s++) { ph[0][s] = v[s].re; ph[1][s] = v[s].im; }
         wait_vm<C::S>();                                       // fields 3-5
@@ -602,13 +603,13 @@ __global__ void __launch_bounds__((XCfg<P, N, EV>::NTH), (XCfg<P, N, EV>::MINB))
         gather(v, slot0 + 2 * RW, slot1);
         lds_barrier();                                         // slot0 read by every wave
         request(slot0, more ? tile + 1 : tile, 0);
-        line_fft<P, N, E, T, +1, true>(v, lds, l, t, twx);
+        line_fft<P, N, E, T, +1, 1, RowLay<P, T>, truncated_slots(N, E, K)>(v, lds, l, t, twx);
 #pragma unroll
         for (int s = 0; s < E; s++) { ph[2][s] = v[s].re; ph[3][s] = v[s].im; }
         gather(v, slot1 + RW, slot1 + 2 * RW);
         lds_barrier();                                         // slot1 read by every wave
         request(slot1, more ? tile + 1 : tile, 3);
-        line_fft<P, N, E, T, +1, true>(v, lds, l, t, twx);
+        line_fft<P, N, E, T, +1, 1, RowLay<P, T>, truncated_slots(N, E, K)>(v, lds, l, t, twx);
 #pragma unroll
         for (int s = 0; s < E; s++) { ph[4][s] = v[s].re; ph[5][s] = v[s].im; }
         // ph: 0 u_x, 1 u_y, 2 u_z, 3 omega_x, 4 omega_y, 5 omega_z
@@ -629,7 +630,8 @@ __global__ void __launch_bounds__((XCfg<P, N, EV>::NTH), (XCfg<P, N, EV>::MINB))
         line_fft_T<P, N, E, T, -1, true>(d2, lds, l, t, twx);
         lds_barrier();
 #pragma unroll
-        for (int m = 0; m < E; m++) lds_put<P>(lds, (t + M * m) * T + l, d1[m]);
+        for (int m = 0; m < E; m++)          // the split reads only the partner positions 0 and >= N - K
+            if (m == 0 || M * m + M - 1 >= N - K) lds_put<P>(lds, (t + M * m) * T + l, d1[m]);
         lds_barrier();
         // split D1 into the x-spectra of n_x and n_y
         Cx<P> ox[E], oy[E];
@@ -807,7 +809,7 @@ __global__ void __launch_bounds__(64, (XWCfg<P, N, EV>::MINW)) k_xpass_wave(cons
     for (int tile = t0; tile < t1; tile++) {
         const bool more = tile + 1 < t1;
         P ph[6][E];
-        line_fft<P, N, E, R, +1, 2, LY>(v, lds, l, t, twx);
+        line_fft<P, N, E, R, +1, 2, LY, truncated_slots(N, E, K)>(v, lds, l, t, twx);
 #pragma unroll
         for (int s = 0; s < E; s++) { ph[0][s] = v[s].re; ph[1][s] = v[s].im; }
         wait_vm<C::S>();                                       // fields 3-5
@@ -815,13 +817,13 @@ __global__ void __launch_bounds__(64, (XWCfg<P, N, EV>::MINW)) k_xpass_wave(cons
         gather(v, slot0 + 2 * RW, slot1);
         lds_wait();                                            // slot0 read
         request(slot0, more ? tile + 1 : tile, 0);
-        line_fft<P, N, E, R, +1, 2, LY>(v, lds, l, t, twx);
+        line_fft<P, N, E, R, +1, 2, LY, truncated_slots(N, E, K)>(v, lds, l, t, twx);
 #pragma unroll
         for (int s = 0; s < E; s++) { ph[2][s] = v[s].re; ph[3][s] = v[s].im; }
         gather(v, slot1 + RW, slot1 + 2 * RW);
         lds_wait();                                            // slot1 read
         request(slot1, more ? tile + 1 : tile, 3);
-        line_fft<P, N, E, R, +1, 2, LY>(v, lds, l, t, twx);
+        line_fft<P, N, E, R, +1, 2, LY, truncated_slots(N, E, K)>(v, lds, l, t, twx);
 #pragma unroll
         for (int s = 0; s < E; s++) { ph[4][s] = v[s].re; ph[5][s] = v[s].im; }
         // ph: 0 u_x, 1 u_y, 2 u_z, 3 omega_x, 4 omega_y, 5 omega_z
@@ -842,7 +844,8 @@ __global__ void __launch_bounds__(64, (XWCfg<P, N, EV>::MINW)) k_xpass_wave(cons
         line_fft_T<P, N, E, R, -1, 2, LY>(d2, lds, l, t, twx);
         wave_fence();
 #pragma unroll
-        for (int m = 0; m < E; m++) lds_put<P>(lds, LY::slot(t + M * m, l), d1[m]);
+        for (int m = 0; m < E; m++)          // the split reads only the partner positions 0 and >= N - K
+            if (m == 0 || M * m + M - 1 >= N - K) lds_put<P>(lds, LY::slot(t + M * m, l), d1[m]);
         wave_fence();
         // split D1 into the x-spectra of n_x and n_y
         Cx<P> ox[E], oy[E];
@@ -997,7 +1000,7 @@ __global__ void __launch_bounds__(64, (XW2Cfg<P, N, EV>::MINW)) k_xpass_wave2(co
         P ph[6][E];
         lds_wait();                                            // pair 0 read
         request(slot(u), tile, 2);
-        line_fft<P, N, E, R, +1, 2, LY>(v, lds, l, t, twx);
+        line_fft<P, N, E, R, +1, 2, LY, truncated_slots(N, E, K)>(v, lds, l, t, twx);
 #pragma unroll
         for (int s = 0; s < E; s++) { ph[0][s] = v[s].re; ph[1][s] = v[s].im; }
         wait_vm<S + D2>();                                     // pair 1
@@ -1005,7 +1008,7 @@ __global__ void __launch_bounds__(64, (XW2Cfg<P, N, EV>::MINW)) k_xpass_wave2(co
         gather(v, slot(1 - u), slot(1 - u) + RW);
         lds_wait();                                            // pair 1 read
         request(slot(1 - u), nxt, 0);
-        line_fft<P, N, E, R, +1, 2, LY>(v, lds, l, t, twx);
+        line_fft<P, N, E, R, +1, 2, LY, truncated_slots(N, E, K)>(v, lds, l, t, twx);
 #pragma unroll
         for (int s = 0; s < E; s++) { ph[2][s] = v[s].re; ph[3][s] = v[s].im; }
         wait_vm<D2>();                                         // pair 2
@@ -1013,7 +1016,7 @@ __global__ void __launch_bounds__(64, (XW2Cfg<P, N, EV>::MINW)) k_xpass_wave2(co
         gather(v, slot(u), slot(u) + RW);
         lds_wait();                                            // pair 2 read
         request(slot(u), nxt, 1);
-        line_fft<P, N, E, R, +1, 2, LY>(v, lds, l, t, twx);
+        line_fft<P, N, E, R, +1, 2, LY, truncated_slots(N, E, K)>(v, lds, l, t, twx);
 #pragma unroll
         for (int s = 0; s < E; s++) { ph[4][s] = v[s].re; ph[5][s] = v[s].im; }
         // ph: 0 u_x, 1 u_y, 2 u_z, 3 omega_x, 4 omega_y, 5 omega_z
@@ -1034,7 +1037,8 @@ __global__ void __launch_bounds__(64, (XW2Cfg<P, N, EV>::MINW)) k_xpass_wave2(co
         line_fft_T<P, N, E, R, -1, 2, LY>(d2, lds, l, t, twx);
         wave_fence();
 #pragma unroll
-        for (int m = 0; m < E; m++) lds_put<P>(lds, LY::slot(t + M * m, l), d1[m]);
+        for (int m = 0; m < E; m++)          // the split reads only the partner positions 0 and >= N - K
+            if (m == 0 || M * m + M - 1 >= N - K) lds_put<P>(lds, LY::slot(t + M * m, l), d1[m]);
         wave_fence();
         Cx<P> ox[E], oy[E];
 #pragma unroll
