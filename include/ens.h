@@ -187,7 +187,10 @@ ens_status ens_get_diag(ens_ctx *ctx, int32_t m, ens_diag *out);
 
 /* Time the compiled variants of the transform passes (1 z inverse, 2 y
  * inverse, 3 x pass, 4 y forward; variant 0 = 8, 1 = 16 complex values per
- * thread; x pass variant 2 = persistent workgroups streaming their inputs by
+ * thread; z inverse, y inverse and y forward variants 2 and 3 = 8 and 16
+ * values per thread with twice the lines per workgroup (two 128-byte lines
+ * per position) where the thread budget allows, else as 0 and 1; x pass
+ * variant 2 = persistent workgroups streaming their inputs by
  * direct-to-LDS loads, 8 values per thread, the same as variant 0 for n < 64;
  * variant 3 = the same with 16 values per thread for FP32 and 128 <= n <= 512,
  * else variant 2; variants 4 and 5 = the streamed pass with one wave per

@@ -997,7 +997,7 @@ ENS_API ens_status ens_autotune(ens_ctx *ctx, const int32_t *members, int32_t co
     drop_graphs(ctx);
     if (cache_path) {
         std::ofstream f(cache_path);
-        f << "# libensdns kernel variants (pass:n:precision variant); 0 = 8, 1 = 16 values per thread, 2 and 3 = streamed x pass with 8 and 16, 4 to 6 = wave-private streamed x pass\n";
+        f << "# libensdns kernel variants (pass:n:precision variant); 0 = 8, 1 = 16 values per thread, 2 and 3 = the same with twice the lines per workgroup (y/z passes) or the streamed x pass with 8 and 16, 4 to 6 = wave-private streamed x pass\n";
         for (auto &kv : cache) f << kv.first << " " << kv.second << "\n";
     }
     return ENS_OK;

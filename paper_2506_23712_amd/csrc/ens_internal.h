@@ -127,9 +127,9 @@ enum Pass { P_BAND = 0, P_ZINV = 1, P_YINV = 2, P_XPASS = 3, P_YFWD = 4, P_ZFWD 
 // Launchers (defined in the .hip files).  `mem` points to a device array of
 // `count` MemberDev of one size n and precision; grids cover all of them.
 // `variant` selects a compiled kernel variant (0: 8 values per thread,
-// 1: 16 values per thread; x pass 2: persistent pipelined workgroups with
-// direct-to-LDS staging, 8 values per thread) for passes with
-// pass_variants(pass) > 1.
+// 1: 16 values per thread; y/z passes 2, 3: the same with twice the lines
+// per workgroup; x pass 2 to 6: the streamed and wave-private passes, see
+// ens_autotune in ens.h) for passes with pass_variants(pass) > 1.
 hipError_t launch_pass(int pass, int variant, int n, int prec, const MemberDev *mem, int count, int stage,
                        const void *tw, hipStream_t s);
 int pass_variants(int pass);

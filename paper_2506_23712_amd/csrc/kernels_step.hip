@@ -45,7 +45,7 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
 // E = complex values per thread (a line of N uses N/E threads).  Variants of
 // E are compiled for the pencil passes and the x pass; the host picks one per
 // (pass, N, precision) from its tuning table.
-template <typename P, int N, int E_> struct Cfg {
+template <typename P, int N, int E_, int TM = 1> struct Cfg {
     static constexpr int K = N / 3, KX = K + 1;                 // x-modes kept
     static constexpr int NZLS = (2 * K + 1) * KX;               // z-lines: modes of a z plane
     static constexpr int ZP = state_pitch(K, (int)sizeof(Cx<P>));  // plane pitch (whole 128-byte lines)
@@ -71,7 +71,11 @@ template <typename P, int N, int E_> struct Cfg {
     // gives a workgroup up to 160 KiB of LDS.
     static constexpr int TL = 128 / (int)sizeof(Cx<P>);
     static constexpr int MAXT = E >= 16 ? 512 : 1024;             // 16 values/thread: keep 256 VGPRs available
-    static constexpr int T = N <= 256 ? (256 / M > TL ? 256 / M : TL) : (TL * M <= MAXT ? TL : MAXT / M);
+    // TM > 1 (autotuner variants 2, 3 of the y/z passes): TM times as many
+    // lines, i.e. TM whole lines per position, where the thread budget above
+    // allows it (not for 16 FP64 values per thread, which would spill)
+    static constexpr int T1 = N <= 256 ? (256 / M > TL ? 256 / M : TL) : (TL * M <= MAXT ? TL : MAXT / M);
+    static constexpr int T = (T1 * TM * M <= MAXT && !(sizeof(P) == 8 && E >= 16)) ? T1 * TM : T1;
     static constexpr int NT = T * M;
     // z/y inverse passes: waves per SIMD the register budget is cut for
     static constexpr int PMINW = (sizeof(P) == 4 && E == 16 && NT == 256) ? 3 : 1;
@@ -177,9 +181,9 @@ __device__ __forceinline__ void load_trunc(Cx<P> *v, const Fld<P> &f, uint32_t b
 // plane; lines NZLS..ZP-1 (a plane's pad) carry zeros.  in u_hat
 // [3][2K+1][ZP]; out (bufA) [5][N (z)][ZP]:
 // U_x, U_y, U_z, W_x = Z^-1[i k_z u_x], W_y = Z^-1[i k_z u_y]
-template <typename P, int N, int EV>
-__global__ void __launch_bounds__((Cfg<P, N, EV>::NT), (Cfg<P, N, EV>::PMINW)) k_zinv(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ twg) {
-    using C = Cfg<P, N, EV>;
+template <typename P, int N, int EV, int TM = 1>
+__global__ void __launch_bounds__((Cfg<P, N, EV, TM>::NT), (Cfg<P, N, EV, TM>::PMINW)) k_zinv(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ twg) {
+    using C = Cfg<P, N, EV, TM>;
     constexpr int E = C::E, M = C::M, T = C::T, ZP = C::ZP;
     __shared__ LdsT<P> lds[N * T];
     __shared__ Cx<P> tw[twiddle_span(N, E)];               // twiddles in LDS: no global load inside the transforms
@@ -227,9 +231,9 @@ __global__ void __launch_bounds__((Cfg<P, N, EV>::NT), (Cfg<P, N, EV>::PMINW)) k
 // y-lines L = z (K+1) + kx.  in bufA [5][N (z)][ZP] (line L at iy (K+1) of
 // plane z); out bufB [6][N / ZB][N (y)][BL] (Cfg::yel):
 // u_x, u_y, u_z, omega_x, omega_y, omega_z
-template <typename P, int N, int EV>
-__global__ void __launch_bounds__((Cfg<P, N, EV>::NT)) k_yinv(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ twg) {
-    using C = Cfg<P, N, EV>;
+template <typename P, int N, int EV, int TM = 1>
+__global__ void __launch_bounds__((Cfg<P, N, EV, TM>::NT)) k_yinv(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ twg) {
+    using C = Cfg<P, N, EV, TM>;
     constexpr int E = C::E, M = C::M, T = C::T, KX = C::KX, ZP = C::ZP, NYL = C::NYL;
     __shared__ LdsT<P> lds[N * T];
     __shared__ Cx<P> tw[twiddle_span(N, E)];               // twiddles in LDS: no global load inside the transforms
@@ -1085,9 +1089,9 @@ __global__ void __launch_bounds__(64, (XW2Cfg<P, N, EV>::MINW)) k_xpass_wave2(co
 // ================================================================== yfwd
 // y-lines L = z (K+1) + kx.  in bufA [3][N / ZB][N (y)][BL] (the x-pass
 // rows); out bufB [3][N / ZB][2K+1 (m_y)][BL]
-template <typename P, int N, int EV>
-__global__ void __launch_bounds__((Cfg<P, N, EV>::NT)) k_yfwd(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ twg) {
-    using C = Cfg<P, N, EV>;
+template <typename P, int N, int EV, int TM = 1>
+__global__ void __launch_bounds__((Cfg<P, N, EV, TM>::NT)) k_yfwd(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ twg) {
+    using C = Cfg<P, N, EV, TM>;
     constexpr int E = C::E, M = C::M, T = C::T, K = C::K, NYL = C::NYL;
     constexpr long long FS = (long long)N * NYL;
     __shared__ LdsT<P> lds[N * T];
@@ -1292,14 +1296,14 @@ __global__ void __launch_bounds__(256) k_end_step(const MemberDev *__restrict__ 
 }
 
 // ================================================================== launchers
-template <typename P, int N, int EV>
+template <typename P, int N, int EV, int TM = 1>
 static hipError_t run_pencil(int pass, const MemberDev *mem, int count, int stage, const Cx<P> *tw, hipStream_t s) {
-    using C = Cfg<P, N, EV>;
+    using C = Cfg<P, N, EV, TM>;
     switch (pass) {
-    case P_ZINV: k_zinv<P, N, EV><<<dim3((C::ZP + C::T - 1) / C::T, count), C::NT, 0, s>>>(mem, tw); break;
-    case P_YINV: k_yinv<P, N, EV><<<dim3((C::NYL + C::T - 1) / C::T, count), C::NT, 0, s>>>(mem, tw); break;
+    case P_ZINV: k_zinv<P, N, EV, TM><<<dim3((C::ZP + C::T - 1) / C::T, count), C::NT, 0, s>>>(mem, tw); break;
+    case P_YINV: k_yinv<P, N, EV, TM><<<dim3((C::NYL + C::T - 1) / C::T, count), C::NT, 0, s>>>(mem, tw); break;
     case P_XPASS: k_xpass<P, N, EV><<<dim3((unsigned)((long long)N * N / C::TX), count), 256, 0, s>>>(mem, tw, stage); break;
-    case P_YFWD: k_yfwd<P, N, EV><<<dim3((C::NYL + C::T - 1) / C::T, count), C::NT, 0, s>>>(mem, tw); break;
+    case P_YFWD: k_yfwd<P, N, EV, TM><<<dim3((C::NYL + C::T - 1) / C::T, count), C::NT, 0, s>>>(mem, tw); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1399,6 +1403,8 @@ static hipError_t run_pass(int pass, int variant, const MemberDev *mem, int coun
             else if constexpr (N >= 64) return run_xpass_dma<P, N, 8>(mem, count, stage, twp, s);
             else return run_pencil<P, N, 8>(pass, mem, count, stage, twp, s);
         }
+        if (pass != P_XPASS && variant == 2) return run_pencil<P, N, 8, 2>(pass, mem, count, stage, twp, s);
+        if (pass != P_XPASS && variant == 3) return run_pencil<P, N, 16, 2>(pass, mem, count, stage, twp, s);
         return variant == 1 ? run_pencil<P, N, 16>(pass, mem, count, stage, twp, s)
                             : run_pencil<P, N, 8>(pass, mem, count, stage, twp, s);
     case P_ZFWD:
@@ -1441,7 +1447,7 @@ hipError_t launch_pass(int pass, int variant, int n, int prec, const MemberDev *
 
 int pass_variants(int pass) {
     if (pass == P_XPASS) return 7;
-    return (pass == P_ZINV || pass == P_YINV || pass == P_YFWD) ? 2 : 1;
+    return (pass == P_ZINV || pass == P_YINV || pass == P_YFWD) ? 4 : 1;
 }
 
 int default_variant(int pass, int n, int prec) {
