@@ -76,6 +76,8 @@ def kernel_name(pass_name: str, n: int, prec: str, variant) -> str:
         return f"ens::k_xpass_dma<{p}, {n}, 16>"
     if pass_name == "xpass" and variant in (2, 3) and n >= 64:
         return f"ens::k_xpass_dma<{p}, {n}, 8>"
+    if pass_name in ("zinv", "yinv", "yfwd"):                  # variants 2, 3: twice the lines per workgroup
+        return f"ens::k_{pass_name}<{p}, {n}, {16 if variant in (1, 3) else 8}, {2 if variant in (2, 3) else 1}>"
     return f"ens::k_{pass_name}<{p}, {n}, {16 if variant == 1 else 8}>"
 
 
@@ -147,14 +149,6 @@ def trace_averages(path: str) -> dict:
 PEAK_GBS = 8000.0
 
 
-def _pitch(n: int, cbytes: int) -> int:
-    """Row pitch of the pencil buffers (complex values): K + 1 rounded up to
-    whole 128-byte lines unless that pads more than 1/8 of the row."""
-    k1, per = n // 3 + 1, 128 // cbytes
-    px = (k1 + per - 1) // per * per
-    return px if 8 * (px - k1) <= k1 else k1
-
-
 DEFAULT_WORKLOADS = (("single256_fp64", "fp64", 1), ("ens96_mixed_fp32", "fp32", 25))
 
 
@@ -202,10 +196,10 @@ def write_summary(n: int, counts, out: str, trace: str | None = None, workloads=
                 + " (their commands are recorded inside).  Counters: FETCH_SIZE and WRITE_SIZE (rocprofv3 `--pmc`, one "
                   "counter per run), KiB per dispatch, scaled by what the same counter reads for a plain 1 GiB device "
                   "copy.  Algorithmic bytes: each pass's inputs read once and outputs written once, truncated storage "
-                  "without line padding (the `zfwd_update` read and write average the three RK stages).  The measured bytes "
-                  "include the zero pad entries that the z/y passes write so that every store covers whole 128-byte "
-                  f"lines (rows of {n // 3 + 1} complex values padded to {_pitch(n, 8)} in FP32, "
-                  f"{_pitch(n, 16)} in FP64).\n\n")
+                  "(the `zfwd_update` read and write average the three RK stages).  The pencil buffers hold no row "
+                  "padding; what the measured bytes add comes from loads that straddle 128-byte lines (the y inverse "
+                  "and the z forward read rows of K + 1 values that start anywhere in a line) and from the z planes' "
+                  "pad of at most one line.\n\n")
         if trace:
             f.write("Durations: kernel-trace averages from `" + os.path.relpath(trace, os.path.dirname(HERE)) +
                     "` (same kernel sources; averages include the autotuner's launches of each variant).  "

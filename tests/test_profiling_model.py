@@ -37,6 +37,11 @@ def test_kernel_names_exist_in_the_sources():
     assert p.kernel_name("xpass", 256, "fp32", 3).endswith(", 16>")
     assert p.kernel_name("xpass", 256, "fp64", 3).endswith(", 8>")   # FP64 falls back to 8 values per thread
     assert p.kernel_name("xpass", 32, "fp32", 2) == "ens::k_xpass<float, 32, 8>"
+    assert p.kernel_name("yinv", 256, "fp32", 1) == "ens::k_yinv<float, 256, 16, 1>"
+    assert p.kernel_name("zinv", 256, "fp32", 2) == "ens::k_zinv<float, 256, 8, 2>"
+    # every y/z name appears in the committed trace of the same sources
+    table = open(os.path.join(ROOT, "profiles", "ens96_mixed_fp32_and_single256_fp64_kernel_stats.md")).read()
+    assert "`" + p.kernel_name("yfwd", 256, "fp32", 3) + "`" in table
 
 
 
