@@ -199,7 +199,8 @@ ens_status ens_get_diag(ens_ctx *ctx, int32_t m, ens_diag *out);
  * variant 4 with its inputs staged pairwise through two buffers, less LDS
  * per wave)
  * on the grid sizes and precisions of `members`, and keep the fastest
- * per (pass, n, precision) for later steps.  Only scratch buffers are written:
+ * per (pass, n, precision) for later steps (the x pass timed in its place,
+ * each launch after the y inverse that writes its inputs).  Only scratch buffers are written:
  * member state is unchanged.  `cache_path` (may be NULL) names a text file of
  * "pass:n:precision variant" lines: entries found there are used without
  * timing, and the file is rewritten with the full table.  Synchronises. */

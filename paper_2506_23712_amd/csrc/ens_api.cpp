@@ -973,13 +973,23 @@ ENS_API ens_status ens_autotune(ens_ctx *ctx, const int32_t *members, int32_t co
             // each variant: warm-up, then three timed runs of five launches; the
             // fastest run counts (variants within a few per cent of each other
             // are otherwise decided by interference from the rest of the device)
+            // The x pass is timed in its place in the stage, each launch after
+            // the y inverse (already tuned) that writes its inputs: variants
+            // within a few per cent of each other in isolation rank differently
+            // there.
+            const int prev = pass == P_XPASS ? variant_of(ctx, P_YINV, g.n, g.prec) : -1;
+            auto launch = [&](int v) -> hipError_t {
+                if (prev >= 0)
+                    if (hipError_t e = launch_pass(P_YINV, prev, g.n, g.prec, g.dev, cnt, 1, g.tw, s)) return e;
+                return launch_pass(pass, v, g.n, g.prec, g.dev, cnt, 1, g.tw, s);
+            };
             for (int v = 0; v < pass_variants(pass); v++) {
-                for (int w = 0; w < 2; w++) HIPCK(ctx, launch_pass(pass, v, g.n, g.prec, g.dev, cnt, 1, g.tw, s));
+                for (int w = 0; w < 2; w++) HIPCK(ctx, launch(v));
                 float v_ms = 1e30f;
                 for (int trial = 0; trial < 3; trial++) {
                     HIPCK(ctx, hipEventRecord(a, s));
                     const int reps = 5;
-                    for (int r = 0; r < reps; r++) HIPCK(ctx, launch_pass(pass, v, g.n, g.prec, g.dev, cnt, 1, g.tw, s));
+                    for (int r = 0; r < reps; r++) HIPCK(ctx, launch(v));
                     HIPCK(ctx, hipEventRecord(b, s));
                     HIPCK(ctx, hipEventSynchronize(b));
                     float ms = 0.f;
