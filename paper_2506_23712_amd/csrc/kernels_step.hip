@@ -1137,8 +1137,9 @@ __global__ void __launch_bounds__((Cfg<P, N, EV, TM>::NT)) k_yfwd(const MemberDe
 // line L's position z is at block z / ZB, row iy, entry (z mod ZB)(K+1) + kx.
 // Forward along z, keep |m_z| <= K, normalise by N^-3, project, add band
 // forcing, RK stage update.
-template <typename P, int N>
-__global__ void __launch_bounds__((Cfg<P, N, 8>::NTZ), (Cfg<P, N, 8>::ZMINB)) k_zfwd_update(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ twg, int stage) {
+// The RK stage is a template parameter: no run-time branches on it.
+template <typename P, int N, int stage>
+__global__ void __launch_bounds__((Cfg<P, N, 8>::NTZ), (Cfg<P, N, 8>::ZMINB)) k_zfwd_update(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ twg) {
     using C = Cfg<P, N, 8>;
     constexpr int E = C::EZ, M = C::MZ, T = C::TZ, K = C::K, KX = C::KX, NYL = C::NYL, S = C::S;
     constexpr int ZB = C::ZB, BL = C::BL;
@@ -1146,6 +1147,7 @@ __global__ void __launch_bounds__((Cfg<P, N, 8>::NTZ), (Cfg<P, N, 8>::ZMINB)) k_
     static_assert(NT * sizeof(double) <= N * T * sizeof(LdsT<P>), "reduction scratch reuses the FFT LDS");
     __shared__ LdsT<P> lds[N * T];
     __shared__ Cx<P> tw[twiddle_span(N, E)];               // twiddles in LDS: no global load inside the transforms
+    __shared__ double ezt[N];                               // exp(-nh m_z^2) by position
     for (int i = (int)threadIdx.x; i < twiddle_span(N, E); i += (int)blockDim.x) tw[i] = twg[i];
     double *red = reinterpret_cast<double *>(lds);
     unsigned tile, mem_i;
@@ -1189,71 +1191,97 @@ __global__ void __launch_bounds__((Cfg<P, N, 8>::NTZ), (Cfg<P, N, 8>::ZMINB)) k_
     const double RKH[3] = {1.0 / 3.0, 5.0 / 12.0, 1.0 / 4.0};
     const P As = (P)RKA[stage], Bs = (P)RKB[stage], Pdt = (P)dt;
     const double nh = md.nu * RKH[stage] * dt * md.dk * md.dk;   // exponent per |m|^2
+    // integrating factor exp(-nh |m|^2) = exp(-nh (m_x^2 + m_y^2)) exp(-nh m_z^2):
+    // one exponential per line and a table of the m_z factors per workgroup
+    for (int i = (int)threadIdx.x; i < N; i += NT) {
+        const double mz = (double)mode_of(i, N);
+        ezt[i] = exp(-nh * mz * mz);
+    }
+    const double exy = exp(-nh * (double)(kx * kx + my * my));
+    __syncthreads();
     const P inv_n3 = (P)(1.0 / ((double)N * N * N));
     const P dk = (P)md.dk, nu = (P)md.nu;
+    const double kf_lo2 = md.kf_lo2, kf_hi2 = md.kf_hi2;
+    const bool explicit_visc = md.visc_mode == 1;
     const Fld<P> U[3] = {Fld<P>(md.uh, 0), Fld<P>(md.uh, S), Fld<P>(md.uh, 2 * S)};
     const Fld<P> Q[3] = {Fld<P>(md.q, 0), Fld<P>(md.q, S), Fld<P>(md.q, 2 * S)};
     double eacc = 0.0, dacc = 0.0;
     if (valid) {
+        // the outputs in pairs: the state and register loads of a pair are
+        // issued before its arithmetic (from a valid address for a mode that
+        // is not kept, whose value is then discarded), so that their
+        // latencies overlap
+        constexpr int HB = 2;
 #pragma unroll
-        for (int s = 0; s < E; s++) {
-            const int mz = mode_of(Plan<N, E>::out_pos(t, s), N);
-            if (mz < -K || mz > K) continue;
-            const int iz = mz >= 0 ? mz : mz + 2 * K + 1;
-            const uint32_t idx = (uint32_t)iz * C::ZP + L;
-            const int m2 = kx * kx + my * my + mz * mz;
-            const P kxv = dk * (P)kx, kyv = dk * (P)my, kzv = dk * (P)mz;
-            const P k2 = kxv * kxv + kyv * kyv + kzv * kzv;
-            Cx<P> u[3], g[3];
+        for (int s0 = 0; s0 < E; s0 += HB) {
+            Cx<P> ub[HB][3], qb[HB][3];
 #pragma unroll
-            for (int c = 0; c < 3; c++) u[c] = U[c].ld(idx);
-            if (m2 == 0) {
-                g[0] = g[1] = g[2] = czero<P>();
-            } else {
-                Cx<P> n0 = cscale(a[0][s], inv_n3), n1 = cscale(a[1][s], inv_n3), n2 = cscale(a[2][s], inv_n3);
-                // the band forcing joins the nonlinear term before the projection:
-                // unprojected, it would amplify the rounding-level divergent part
-                // of u in the band at the rate eps/(2 E_f) - nu k^2 > 0
-                if ((double)m2 >= md.kf_lo2 && (double)m2 <= md.kf_hi2) {
-                    n0 = n0 + cscale(u[0], ffac);
-                    n1 = n1 + cscale(u[1], ffac);
-                    n2 = n2 + cscale(u[2], ffac);
-                }
-                const P ik2 = P(1) / k2;
-                Cx<P> kn = cscale(n0, kxv) + cscale(n1, kyv) + cscale(n2, kzv);
-                g[0] = n0 - cscale(kn, kxv * ik2);
-                g[1] = n1 - cscale(kn, kyv * ik2);
-                g[2] = n2 - cscale(kn, kzv * ik2);
+            for (int j = 0; j < HB; j++) {
+                const int mz = mode_of(Plan<N, E>::out_pos(t, s0 + j), N);
+                const bool keep = mz >= -K && mz <= K;
+                const uint32_t idx = (uint32_t)(keep ? (mz >= 0 ? mz : mz + 2 * K + 1) : 0) * C::ZP + L;
+#pragma unroll
+                for (int c = 0; c < 3; c++) ub[j][c] = U[c].ld(idx);
+#pragma unroll
+                for (int c = 0; c < 3; c++) qb[j][c] = stage == 0 ? czero<P>() : Q[c].ld(idx);
             }
-            if (md.visc_mode == 1) {
 #pragma unroll
-                for (int c = 0; c < 3; c++) g[c] = g[c] - cscale(u[c], nu * k2);
-#pragma unroll
-                for (int c = 0; c < 3; c++) {
-                    Cx<P> q = stage == 0 ? czero<P>() : Q[c].ld(idx);
-                    q = cscale(q, As) + cscale(g[c], Pdt);
-                    u[c] = u[c] + cscale(q, Bs);
-                    if (stage < 2) Q[c].st(idx, q);       // the last stage's register is never read
-                    U[c].st(idx, u[c]);
+            for (int j = 0; j < HB; j++) {
+                const int s = s0 + j;
+                const int pz = Plan<N, E>::out_pos(t, s);
+                const int mz = mode_of(pz, N);
+                if (mz < -K || mz > K) continue;
+                const int iz = mz >= 0 ? mz : mz + 2 * K + 1;
+                const uint32_t idx = (uint32_t)iz * C::ZP + L;
+                const int m2 = kx * kx + my * my + mz * mz;
+                const P kxv = dk * (P)kx, kyv = dk * (P)my, kzv = dk * (P)mz;
+                const P k2 = kxv * kxv + kyv * kyv + kzv * kzv;
+                Cx<P> *u = ub[j], g[3];
+                {
+                    // the band forcing joins the nonlinear term before the projection:
+                    // unprojected, it would amplify the rounding-level divergent part
+                    // of u in the band at the rate eps/(2 E_f) - nu k^2 > 0
+                    const P fb = ((double)m2 >= kf_lo2 && (double)m2 <= kf_hi2) ? ffac : P(0);
+                    const Cx<P> n0 = cscale(a[0][s], inv_n3) + cscale(u[0], fb);
+                    const Cx<P> n1 = cscale(a[1][s], inv_n3) + cscale(u[1], fb);
+                    const Cx<P> n2 = cscale(a[2][s], inv_n3) + cscale(u[2], fb);
+                    const P ik2 = m2 == 0 ? P(0) : P(1) / k2;
+                    const Cx<P> kn = cscale(n0, kxv) + cscale(n1, kyv) + cscale(n2, kzv);
+                    g[0] = n0 - cscale(kn, kxv * ik2);
+                    g[1] = n1 - cscale(kn, kyv * ik2);
+                    g[2] = n2 - cscale(kn, kzv * ik2);
+                    if (m2 == 0) g[0] = g[1] = g[2] = czero<P>();
                 }
-            } else {
-                const P es = (P)exp(-nh * (double)m2);
+                if (explicit_visc) {
 #pragma unroll
-                for (int c = 0; c < 3; c++) {
-                    Cx<P> q = stage == 0 ? czero<P>() : Q[c].ld(idx);
-                    q = cscale(cscale(q, As) + cscale(g[c], Pdt), es);
-                    u[c] = cscale(u[c], es) + cscale(q, Bs);
-                    if (stage < 2) Q[c].st(idx, q);       // the last stage's register is never read
-                    U[c].st(idx, u[c]);
+                    for (int c = 0; c < 3; c++) g[c] = g[c] - cscale(u[c], nu * k2);
+#pragma unroll
+                    for (int c = 0; c < 3; c++) {
+                        Cx<P> q = qb[j][c];
+                        q = cscale(q, As) + cscale(g[c], Pdt);
+                        u[c] = u[c] + cscale(q, Bs);
+                        if (stage < 2) Q[c].st(idx, q);       // the last stage's register is never read
+                        U[c].st(idx, u[c]);
+                    }
+                } else {
+                    const P es = (P)(exy * ezt[pz]);
+#pragma unroll
+                    for (int c = 0; c < 3; c++) {
+                        Cx<P> q = qb[j][c];
+                        q = cscale(cscale(q, As) + cscale(g[c], Pdt), es);
+                        u[c] = cscale(u[c], es) + cscale(q, Bs);
+                        if (stage < 2) Q[c].st(idx, q);       // the last stage's register is never read
+                        U[c].st(idx, u[c]);
+                    }
                 }
-            }
-            if (stage == 2) {
-                const double w = kx > 0 ? 1.0 : 0.5;
-                double e2 = 0.0;
+                if (stage == 2) {
+                    const double w = kx > 0 ? 1.0 : 0.5;
+                    double e2 = 0.0;
 #pragma unroll
-                for (int c = 0; c < 3; c++) e2 += (double)u[c].re * (double)u[c].re + (double)u[c].im * (double)u[c].im;
-                eacc += w * e2;
-                dacc += w * e2 * (double)m2;
+                    for (int c = 0; c < 3; c++) e2 += (double)u[c].re * (double)u[c].re + (double)u[c].im * (double)u[c].im;
+                    eacc += w * e2;
+                    dacc += w * e2 * (double)m2;
+                }
             }
         }
     }
@@ -1407,9 +1435,13 @@ static hipError_t run_pass(int pass, int variant, const MemberDev *mem, int coun
         if (pass != P_XPASS && variant == 3) return run_pencil<P, N, 16, 2>(pass, mem, count, stage, twp, s);
         return variant == 1 ? run_pencil<P, N, 16>(pass, mem, count, stage, twp, s)
                             : run_pencil<P, N, 8>(pass, mem, count, stage, twp, s);
-    case P_ZFWD:
-        k_zfwd_update<P, N><<<dim3((C::NZLS + C::TZ - 1) / C::TZ, count), C::NTZ, 0, s>>>(mem, twp, stage);
+    case P_ZFWD: {
+        const dim3 grid((C::NZLS + C::TZ - 1) / C::TZ, count);
+        if (stage == 0) k_zfwd_update<P, N, 0><<<grid, C::NTZ, 0, s>>>(mem, twp);
+        else if (stage == 1) k_zfwd_update<P, N, 1><<<grid, C::NTZ, 0, s>>>(mem, twp);
+        else k_zfwd_update<P, N, 2><<<grid, C::NTZ, 0, s>>>(mem, twp);
         break;
+    }
     case P_END:
         k_end_step<N><<<count, 256, 0, s>>>(mem, (C::NZLS + C::TZ - 1) / C::TZ);
         break;
