@@ -1160,19 +1160,6 @@ __global__ void __launch_bounds__((Cfg<P, N, 8>::NTZ), (Cfg<P, N, 8>::ZMINB)) k_
     const int kx = valid ? L % (K + 1) : 0;
     const uint32_t Lz = (uint32_t)iy * BL + (uint32_t)kx;      // position 0 of the line in bufB
     const int my = iy <= K ? iy : iy - (2 * K + 1);
-    Cx<P> a[3][E];
-#pragma unroll
-    for (int f = 0; f < 3; f++) {
-        const Fld<P> in(md.bufB, (long long)f * (2 * K + 1) * NYL);
-#pragma unroll
-        for (int m = 0; m < E; m++) {
-            const int z = t + M * m;
-            a[f][m] = valid ? in.ld((uint32_t)(z / ZB) * (uint32_t)((2 * K + 1) * BL) + (uint32_t)(z % ZB) * KX + Lz)
-                            : czero<P>();
-        }
-    }
-#pragma unroll
-    for (int f = 0; f < 3; f++) line_fft<P, N, E, T, -1>(a[f], lds, l, t, tw);
     // time step of this RK step
     double dt;
     if (md.dt_fixed > 0.0) dt = md.dt_fixed;
@@ -1198,6 +1185,19 @@ __global__ void __launch_bounds__((Cfg<P, N, 8>::NTZ), (Cfg<P, N, 8>::ZMINB)) k_
         ezt[i] = exp(-nh * mz * mz);
     }
     const double exy = exp(-nh * (double)(kx * kx + my * my));
+    Cx<P> a[3][E];
+#pragma unroll
+    for (int f = 0; f < 3; f++) {
+        const Fld<P> in(md.bufB, (long long)f * (2 * K + 1) * NYL);
+#pragma unroll
+        for (int m = 0; m < E; m++) {
+            const int z = t + M * m;
+            a[f][m] = valid ? in.ld((uint32_t)(z / ZB) * (uint32_t)((2 * K + 1) * BL) + (uint32_t)(z % ZB) * KX + Lz)
+                            : czero<P>();
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < 3; f++) line_fft<P, N, E, T, -1>(a[f], lds, l, t, tw);
     __syncthreads();
     const P inv_n3 = (P)(1.0 / ((double)N * N * N));
     const P dk = (P)md.dk, nu = (P)md.nu;
@@ -1211,7 +1211,7 @@ __global__ void __launch_bounds__((Cfg<P, N, 8>::NTZ), (Cfg<P, N, 8>::ZMINB)) k_
         // issued before its arithmetic (from a valid address for a mode that
         // is not kept, whose value is then discarded), so that their
         // latencies overlap
-        constexpr int HB = 2;
+        constexpr int HB = stage == 0 ? 2 : 1;
 #pragma unroll
         for (int s0 = 0; s0 < E; s0 += HB) {
             Cx<P> ub[HB][3], qb[HB][3];
