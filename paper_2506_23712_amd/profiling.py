@@ -65,8 +65,8 @@ def pass_bytes(n: int, prec: str) -> dict:
 def kernel_name(pass_name: str, n: int, prec: str, variant) -> str:
     """Symbol (as rocprofv3 prints it, without arguments) of a pass's kernel."""
     p = "float" if prec == "fp32" else "double"
-    if pass_name == "zfwd_update":
-        return f"ens::k_zfwd_update<{p}, {n}>"
+    if pass_name == "zfwd_update":                             # the kernel of the middle RK stage
+        return f"ens::k_zfwd_update<{p}, {n}, 1>"
     ea = 16 if prec == "fp32" else 8
     if pass_name == "xpass" and variant == 6 and n >= 64:
         return f"ens::k_xpass_wave2<{p}, {n}, {ea}>"
@@ -180,6 +180,11 @@ def write_summary(n: int, counts, out: str, trace: str | None = None, workloads=
                 if f", {n}" not in short or ("float" in short) != (prec == "fp32"):
                     continue
                 ar, aw = rw[k][0] * cs * cnt, rw[k][1] * cs * cnt
+                st = re.match(r"k_zfwd_update<\w+, \d+, (\d)>", short)
+                if st:                                     # one RK stage: its own register traffic
+                    stage = int(st.group(1))
+                    ar = (3 * zl + 3 * S + (3 * S if stage > 0 else 0)) * cs * cnt
+                    aw = (3 * S + (3 * S if stage < 2 else 0)) * cs * cnt
                 us = avg.get(name)
                 rows.append((wl, short, ar / 1e9, aw / 1e9, v["fetch_bytes"] / 1e9, v["write_bytes"] / 1e9,
                              (v["fetch_bytes"] + v["write_bytes"]) / (ar + aw), t["source_hash"], us,
@@ -196,7 +201,8 @@ def write_summary(n: int, counts, out: str, trace: str | None = None, workloads=
                 + " (their commands are recorded inside).  Counters: FETCH_SIZE and WRITE_SIZE (rocprofv3 `--pmc`, one "
                   "counter per run), KiB per dispatch, scaled by what the same counter reads for a plain 1 GiB device "
                   "copy.  Algorithmic bytes: each pass's inputs read once and outputs written once, truncated storage "
-                  "(the `zfwd_update` read and write average the three RK stages).  The pencil buffers hold no row "
+                  "(a `zfwd_update` kernel of one RK stage: stage 0 does not read the RK register, stage 2 does not "
+                  "write it; the stage-averaged figure where the stage is not in the name).  The pencil buffers hold no row "
                   "padding; what the measured bytes add comes from loads that straddle 128-byte lines (the y inverse "
                   "and the z forward read rows of K + 1 values that start anywhere in a line) and from the z planes' "
                   "pad of at most one line.\n\n")
