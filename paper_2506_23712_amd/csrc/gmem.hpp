@@ -61,20 +61,20 @@ template <int n> __device__ __forceinline__ void wait_vm() {
     __builtin_amdgcn_s_waitcnt((n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
-// Direct-to-LDS copy of one tile of three fields into `dst` laid out
-// [3][RV] in 16-byte vectors.  Field f's tile starts at byte b0 + f fstride
-// (16-byte aligned).  Each field is cut into ceil(RV/64) wave-sized chunks,
-// the last one moved back to end at the field's last vector (re-copying a few
-// vectors with identical data), so that every global_load_lds moves 64
-// consecutive vectors of one field: its global and LDS bases are wave-uniform
-// (scalar registers) and the lane offset is lane * 16.  Every wave issues
-// exactly ceil(3 ceil(RV/64) / waves) copies (surplus waves repeat the last
-// chunk), so the vector-memory counter of every wave advances by the same
-// known amount.
-template <int RV, int NTH>
-__device__ __forceinline__ void dma_tile3(void *dst, const char *b0, long long fstride) {
-    constexpr int NCF = (RV + 63) / 64, NCH = 3 * NCF, NW = NTH / 64;
-    static_assert(RV >= 64 && NTH % 64 == 0, "tile too small for wave-wide copies");
+// Direct-to-LDS copy of one tile of F fields into `dst` laid out [F][RV] in
+// 16-byte vectors.  Field f's tile starts at byte b0 + f fstride (16-byte
+// aligned; the tile is contiguous in HBM).  Each field is cut into
+// ceil(RV/64) wave-sized chunks, the last one moved back to end at the
+// field's last vector (re-copying a few vectors with identical data), so that
+// every global_load_lds moves 64 consecutive vectors of one field: its global
+// and LDS bases are wave-uniform (scalar registers) and the lane offset is
+// lane * 16.  Every wave issues exactly dma_tile_ops<F, RV, NTH>() copies
+// (surplus waves repeat the last chunk), so the vector-memory counter of every
+// wave advances by the same known amount.
+template <int F, int RV, int NTH>
+__device__ __forceinline__ void dma_tile(void *dst, const char *b0, long long fstride) {
+    constexpr int NCF = (RV + 63) / 64, NCH = F * NCF, NW = NTH / 64;
+    static_assert(F >= 1 && RV >= 64 && NTH % 64 == 0, "tile too small for wave-wide copies");
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const unsigned lane16 = (threadIdx.x & 63u) * 16u;
 #pragma unroll
@@ -88,54 +88,9 @@ __device__ __forceinline__ void dma_tile3(void *dst, const char *b0, long long f
                                          (__attribute__((address_space(3))) void *)((char *)dst + (f * RV + st) * 16), 16, 0, 0);
     }
 }
-// The same for tiles whose rows are padded in HBM: T rows of RVR vectors, ROWB
-// bytes apart (the pad after each row is not read), copied densely into
-// `dst` laid out [3][T][RVR].  Lane offsets follow the row structure.
-template <int RVR, int ROWB, int T, int NTH>
-__device__ __forceinline__ void dma_rows3(void *dst, const char *b0, long long fstride) {
-    constexpr int RV = T * RVR, NCF = (RV + 63) / 64, NCH = 3 * NCF, NW = NTH / 64;
-    static_assert(RV >= 64 && NTH % 64 == 0 && ROWB >= RVR * 16, "tile too small for wave-wide copies");
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const unsigned lane = threadIdx.x & 63u;
-#pragma unroll
-    for (int j = 0; j < (NCH + NW - 1) / NW; j++) {
-        int c = j * NW + wave;
-        c = c < NCH ? c : NCH - 1;
-        const int f = c / NCF, q = c - f * NCF;
-        const int st = q * 64 < RV - 64 ? q * 64 : RV - 64;
-        const unsigned v = (unsigned)st + lane, r = v / (unsigned)RVR, col = v - r * (unsigned)RVR;
-        const ENS_GLOBAL char *src = (const ENS_GLOBAL char *)b0 + f * fstride;
-        __builtin_amdgcn_global_load_lds((const ENS_GLOBAL void *)(src + (r * (unsigned)ROWB + col * 16u)),
-                                         (__attribute__((address_space(3))) void *)((char *)dst + (f * RV + st) * 16), 16, 0, 0);
-    }
-}
-
-// The same for F fields (F >= 1), copied densely into `dst` laid out [F][T][RVR].
-template <int F, int RVR, int ROWB, int T, int NTH>
-__device__ __forceinline__ void dma_rows(void *dst, const char *b0, long long fstride) {
-    constexpr int RV = T * RVR, NCF = (RV + 63) / 64, NCH = F * NCF, NW = NTH / 64;
-    static_assert(RV >= 64 && NTH % 64 == 0 && ROWB >= RVR * 16, "tile too small for wave-wide copies");
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const unsigned lane = threadIdx.x & 63u;
-#pragma unroll
-    for (int j = 0; j < (NCH + NW - 1) / NW; j++) {
-        int c = j * NW + wave;
-        c = c < NCH ? c : NCH - 1;
-        const int f = c / NCF, q = c - f * NCF;
-        const int st = q * 64 < RV - 64 ? q * 64 : RV - 64;
-        const unsigned v = (unsigned)st + lane, r = v / (unsigned)RVR, col = v - r * (unsigned)RVR;
-        const ENS_GLOBAL char *src = (const ENS_GLOBAL char *)b0 + f * fstride;
-        __builtin_amdgcn_global_load_lds((const ENS_GLOBAL void *)(src + (r * (unsigned)ROWB + col * 16u)),
-                                         (__attribute__((address_space(3))) void *)((char *)dst + (f * RV + st) * 16), 16, 0, 0);
-    }
-}
-// copies per wave of dma_rows<F, ...> for RV vectors per field
-template <int F, int RV, int NTH> constexpr int dma_rows_ops() {
+// copies (or 16-byte stores in the same chunking) per wave for F fields of RV vectors
+template <int F, int RV, int NTH> constexpr int dma_tile_ops() {
     return (F * ((RV + 63) / 64) + NTH / 64 - 1) / (NTH / 64);
-}
-
-template <int RV, int NTH> constexpr int dma_tile3_ops() {
-    return (3 * ((RV + 63) / 64) + NTH / 64 - 1) / (NTH / 64);
 }
 
 }  // namespace ens

@@ -489,8 +489,8 @@ template <typename P, int N, int E_> struct XCfg {
     static constexpr int RV = RW / CPV;                    // 16-byte vectors read per field tile
     static constexpr int RWO = T * (K + 1);                // elements written per field tile (rows of K + 1)
     static constexpr int RVO = RWO / CPV;
-    static constexpr int D3 = dma_tile3_ops<RV, NTH>();     // copies per wave per staging buffer
-    static constexpr int S = dma_tile3_ops<RVO, NTH>();     // 16-byte stores per wave per tile
+    static constexpr int D3 = dma_tile_ops<3, RV, NTH>();     // copies per wave per staging buffer
+    static constexpr int S = dma_tile_ops<3, RVO, NTH>();     // 16-byte stores per wave per tile
     static constexpr int XL = N * T > 3 * RWO ? N * T : 3 * RWO;
     static constexpr int TILES = N * N / T;
     // waves per SIMD the register budget is cut for: what the LDS allows
@@ -532,7 +532,7 @@ __global__ void __launch_bounds__((XCfg<P, N, EV>::NTH), (XCfg<P, N, EV>::MINB))
     const char *inb = (const char *)md.bufB;
     char *outb = (char *)md.bufA;
     auto request = [&](LdsT<P> *dst, int tile, int f0) {      // fields f0..f0+2 of `tile`
-        dma_tile3<C::RV, NTH>(dst, inb + (long long)f0 * FSB + (long long)tile * RW * C::CS, FSB);
+        dma_tile<3, C::RV, NTH>(dst, inb + (long long)f0 * FSB + (long long)tile * RW * C::CS, FSB);
     };
     // packed two-for-one spectrum of fields (fa, fb): C = A + i B, Hermitian
     // fill.  Position n = t + M m; whole segments [M m, M m + M) below K, above
@@ -712,8 +712,8 @@ template <typename P, int N, int E_> struct XWCfg {
     static constexpr int NTW = REGTW ? 1 : twiddle_span(N, E);
     static constexpr int RW = R * RQ, RV = RW / CPV;            // a tile's elements / 16-byte vectors per field
     static constexpr int RWO = R * (K + 1), RVO = RWO / CPV;
-    static constexpr int D3 = dma_tile3_ops<RV, 64>();          // copies per staging buffer
-    static constexpr int S = dma_tile3_ops<RVO, 64>();          // 16-byte stores per tile
+    static constexpr int D3 = dma_tile_ops<3, RV, 64>();          // copies per staging buffer
+    static constexpr int S = dma_tile_ops<3, RVO, 64>();          // 16-byte stores per tile
     static constexpr int XL = N * R > 3 * RWO ? N * R : 3 * RWO;
     static constexpr int TILES = N * N / R;
     static constexpr long long LDS_BYTES = (6LL * RW + XL + NTW) * CS + 64;
@@ -755,7 +755,7 @@ __global__ void __launch_bounds__(64, (XWCfg<P, N, EV>::MINW)) k_xpass_wave(cons
     const char *inb = (const char *)md.bufB;
     char *outb = (char *)md.bufA;
     auto request = [&](LdsT<P> *dst, int tile, int f0) {      // fields f0..f0+2 of the tile's R rows
-        dma_tile3<C::RV, 64>(dst, inb + (long long)f0 * FSB + (long long)tile * RW * C::CS, FSB);
+        dma_tile<3, C::RV, 64>(dst, inb + (long long)f0 * FSB + (long long)tile * RW * C::CS, FSB);
     };
     // packed two-for-one spectrum of fields (fa, fb), as in the streamed x pass
     auto gather = [&](Cx<P> *v, const LdsT<P> *fa, const LdsT<P> *fb) {
@@ -904,7 +904,7 @@ __global__ void __launch_bounds__(64, (XWCfg<P, N, EV>::MINW)) k_xpass_wave(cons
 // with a single wave.
 template <typename P, int N, int E_> struct XW2Cfg {
     using B = XWCfg<P, N, E_>;
-    static constexpr int D2 = dma_rows_ops<2, B::RV, 64>();    // copies per pair
+    static constexpr int D2 = dma_tile_ops<2, B::RV, 64>();    // copies per pair
     static constexpr long long LDS_BYTES = (4LL * B::RW + B::XL + B::NTW) * B::CS + 64;
     static constexpr int WPS = (int)(163840 / ((LDS_BYTES + 511) / 512 * 512)) / 4;
     static constexpr int MINW = WPS < 1 ? 1 : (WPS > 4 ? 4 : WPS);
@@ -943,7 +943,7 @@ __global__ void __launch_bounds__(64, (XW2Cfg<P, N, EV>::MINW)) k_xpass_wave2(co
     char *outb = (char *)md.bufA;
     auto slot = [&](int i) -> LdsT<P> * { return i ? slotB : slotA; };
     auto request = [&](LdsT<P> *dst, int tile, int pair) {    // fields 2 pair, 2 pair + 1 of the tile's R rows
-        dma_rows<2, C::RV, C::RV * 16, 1, 64>(dst, inb + (long long)(2 * pair) * FSB + (long long)tile * RW * C::CS, FSB);
+        dma_tile<2, C::RV, 64>(dst, inb + (long long)(2 * pair) * FSB + (long long)tile * RW * C::CS, FSB);
     };
     auto gather = [&](Cx<P> *v, const LdsT<P> *fa, const LdsT<P> *fb) {
 #pragma unroll
