@@ -1207,10 +1207,11 @@ __global__ void __launch_bounds__((Cfg<P, N, 8>::NTZ), (Cfg<P, N, 8>::ZMINB)) k_
     const Fld<P> Q[3] = {Fld<P>(md.q, 0), Fld<P>(md.q, S), Fld<P>(md.q, 2 * S)};
     double eacc = 0.0, dacc = 0.0;
     if (valid) {
-        // the outputs in pairs: the state and register loads of a pair are
-        // issued before its arithmetic (from a valid address for a mode that
-        // is not kept, whose value is then discarded), so that their
-        // latencies overlap
+        // stage 0 (no RK register to read) takes the outputs in pairs: the
+        // state loads of a pair are issued before its arithmetic (from a
+        // valid address for a mode that is not kept, whose value is then
+        // discarded), so that their latencies overlap; stages 1 and 2 take
+        // one output at a time (pairs with their register loads spill)
         constexpr int HB = stage == 0 ? 2 : 1;
 #pragma unroll
         for (int s0 = 0; s0 < E; s0 += HB) {
