@@ -59,3 +59,28 @@ def test_trace_averages_read_the_committed_kernel_table():
         name = cells[0].strip("`")
         assert avg[name] == float(cells[3])
         assert abs(float(cells[2]) - int(cells[1]) * float(cells[3])) <= 0.01 * float(cells[2]) + 1
+
+
+def test_summary_uses_each_rk_stage_own_bytes_for_the_z_forward():
+    """The z forward + update of RK stage 0 reads no RK register and that of
+    stage 2 writes none: the committed summary's algorithmic bytes of each
+    stage's kernel follow that, and average to the pass model's figure."""
+    from paper_2506_23712_amd import profiling as p
+    path = os.path.join(ROOT, "profiles", "traffic_summary_256.md")
+    n, K, cs, cnt = 256, 256 // 3, 8, 25
+    S, zl = (2 * K + 1) ** 2 * (K + 1), n * (2 * K + 1) * (K + 1)
+    want = {0: ((3 * zl + 3 * S) * cs * cnt, 6 * S * cs * cnt),
+            1: ((3 * zl + 6 * S) * cs * cnt, 6 * S * cs * cnt),
+            2: ((3 * zl + 6 * S) * cs * cnt, 3 * S * cs * cnt)}
+    got = {}
+    for l in open(path):
+        cells = [c.strip() for c in l.strip().strip("|").split("|")]
+        if len(cells) > 2 and cells[0] == "ens96_mixed_fp32" and cells[1].startswith("`k_zfwd_update<float, 256, "):
+            st = int(cells[1][-3])
+            r, w = (float(x) for x in cells[2].split("/"))
+            got[st] = (r, w)
+    assert sorted(got) == [0, 1, 2]
+    for st, (r, w) in want.items():
+        assert abs(got[st][0] - r / 1e9) < 1e-3 and abs(got[st][1] - w / 1e9) < 1e-3, (st, got[st])
+    avg = sum(r + w for r, w in want.values()) / 3
+    assert abs(avg - p.pass_bytes(n, "fp32")["zfwd_update"] * cnt) < 1e-6 * avg
