@@ -370,13 +370,13 @@ ENS_API ens_status ens_create(ens_ctx **out, int device, const ens_hist_desc *h)
         ctx->dev_allocs.push_back(ctx->ledge);
         e = hipMemcpy(ctx->ledge, edges.data(), edges.size() * sizeof(double), hipMemcpyHostToDevice);
         if (e != hipSuccess) {
-            hipFree(ctx->ledge);
+            (void)hipFree(ctx->ledge);
             return fail(ENS_E_HIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
         }
     }
     e = hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking);
     if (e != hipSuccess) {
-        if (ctx->ledge) hipFree(ctx->ledge);
+        if (ctx->ledge) (void)hipFree(ctx->ledge);
         return fail(ENS_E_HIP, std::string("hipStreamCreate: ") + hipGetErrorString(e));
     }
     *out = ctx.release();
@@ -385,19 +385,21 @@ ENS_API ens_status ens_create(ens_ctx **out, int device, const ens_hist_desc *h)
 
 ENS_API ens_status ens_destroy(ens_ctx *ctx) {
     if (!ctx) return fail(ENS_E_INVALID, "null context");
-    hipSetDevice(ctx->device);
-    hipDeviceSynchronize();
+    // Teardown is best effort: every handle is released even if an earlier
+    // release (or a sticky error of the device) fails.
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
     for (auto &kv : ctx->plans) {
-        if (kv.second->exec) hipGraphExecDestroy(kv.second->exec);
-        if (kv.second->graph) hipGraphDestroy(kv.second->graph);
+        if (kv.second->exec) (void)hipGraphExecDestroy(kv.second->exec);
+        if (kv.second->graph) (void)hipGraphDestroy(kv.second->graph);
     }
     for (auto &m : ctx->members)
-        if (m && m->dev) hipFree(m->dev);
-    for (void *p : ctx->dev_allocs) hipFree(p);
-    if (ctx->mix_scratch) hipFree(ctx->mix_scratch);
-    if (ctx->cap) hipStreamDestroy(ctx->cap);
-    for (hipStream_t st : ctx->side) hipStreamDestroy(st);
-    for (hipEvent_t ev : ctx->fork) hipEventDestroy(ev);
+        if (m && m->dev) (void)hipFree(m->dev);
+    for (void *p : ctx->dev_allocs) (void)hipFree(p);
+    if (ctx->mix_scratch) (void)hipFree(ctx->mix_scratch);
+    if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
+    for (hipStream_t st : ctx->side) (void)hipStreamDestroy(st);
+    for (hipEvent_t ev : ctx->fork) (void)hipEventDestroy(ev);
     delete ctx;
     return ENS_OK;
 }
@@ -569,7 +571,7 @@ ENS_API ens_status ens_profile_step(ens_ctx *ctx, const int32_t *members, int32_
         if (e == hipSuccess && e2 == hipSuccess && hipEventElapsedTime(&ms, prof.ev[2 * i], prof.ev[2 * i + 1]) == hipSuccess)
             ms_out[prof.pass[i]] += ms;
     }
-    for (hipEvent_t ev : prof.ev) hipEventDestroy(ev);
+    for (hipEvent_t ev : prof.ev) (void)hipEventDestroy(ev);
     HIPCK(ctx, e);
     HIPCK(ctx, e2);
     for (int id : ids) ctx->members[id]->last = s;

@@ -614,7 +614,7 @@ hipError_t launch_stats_reduce(int n, int prec, const MemberDev *mem, int count,
     return stats_dispatch(n, prec, 3, mem, count, nullptr, nullptr, nullptr, s);
 }
 // upper bound of workgroup partials per member (the grid depends on the batch)
-long long xstats_blocks(int n) { return 512; }
+long long xstats_blocks(int /*n*/) { return 512; }
 bool stats_hist_fits(const ens_hist_desc &h) {
     const size_t n1d = 2 * (size_t)(h.log_bins + 3) + 2 * (size_t)(h.a_bins + 3);
     return n1d * 4 + (size_t)(h.log_bins + 1) * 8 <= 65536 - kHotBytes - 4 * 32 * 8 - 16384 - 512 - 4096;
