@@ -70,6 +70,15 @@ def test_weights_sum_to_one_and_delta_limit():
     assert wsmall[lam.index(0.0)] > 1 - 1e-12
 
 
+def test_delta_limit_on_a_bin_edge_goes_to_the_upper_bin():
+    """P(lambda; 0) is a point mass at lambda = 0 and the bins are half-open,
+    [a, b): with 0 on the edge between two members the whole weight goes to
+    the member above the edge."""
+    for mode in (0, 1):
+        assert mx.weights([-1.0, 1.0], C, 0.0, mode=mode) == [0.0, 1.0]
+        assert mx.weights([1.0, -1.0, 3.0], C, 0.0, mode=mode) == [1.0, 0.0, 0.0]
+
+
 def test_tail_member_bin_mass_matches_paper():
     """Bin mass of the lambda = 3.93 member at R_lambda = 1300, c = 0.023.  Z from
     R_lambda ~ exp(2Z/3) through the 2048^3 reference (R = 261 at Z = log 8)."""

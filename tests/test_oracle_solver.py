@@ -43,6 +43,11 @@ def test_init_field_properties(orc, n):
     mask = orc.retained_mask(n)
     assert np.all(u[:, ~mask] == 0)
     assert np.all(u[:, 0, 0, 0] == 0)
+    # independent real and imaginary deviates: the phases of a mode's components
+    # are spread (one deviate used twice would put each at 45 or 225 degrees)
+    keep = mask & (np.sum(np.abs(u) ** 2, axis=0) > 0)
+    same = np.all(np.abs(u.real - u.imag) <= 1e-9 * np.abs(u), axis=0)
+    assert np.mean(same[keep]) < 0.01
     # Hermitian on the m_x = 0 plane: u(0, -m_y, -m_z) = conj(u(0, m_y, m_z))
     p = u[:, :, :, 0]
     mirrored = np.conj(p[:, (-np.arange(n)) % n][:, :, (-np.arange(n)) % n])
@@ -124,7 +129,7 @@ def test_single_fourier_mode_has_no_nonlinear_term(orc):
     assert np.max(np.abs(N)) <= 1e-15 * (a @ a) * np.sqrt(kv @ kv)
 
 
-@pytest.mark.parametrize("band", [(0.0, 2.0, 32), (0.0, 2.5, 80), (1.4, 2.3, 50)])
+@pytest.mark.parametrize("band", [(0.0, 2.0, 32), (0.0, 2.5, 80), (1.4, 2.3, 50), (1.0, 2.0, 32), (1.0, 1.0, 6)])
 def test_forcing_injects_exactly_eps(orc, band):
     lo, hi, count = band
     n = 16
@@ -189,6 +194,21 @@ def test_forcing_acts_on_the_hermitian_part_of_the_m_x_0_plane(orc):
     assert np.max(np.abs(gv - g)) <= 1e-15
     # the injection rate stays eps exactly
     assert abs(iv[1] - 0.5) <= 1e-14
+
+
+def test_band_excludes_the_mean_mode(orc):
+    """A band starting at 0 holds the modes 0 < |m| <= k_f,hi: a uniform flow
+    (the m = 0 mode) is neither counted in E_f nor forced."""
+    n = 16
+    u = _random_field(orc, n, 12)
+    m = orc.Member(n=n, nu=0.0, eps=0.4, kf_lo=0.0, kf_hi=2.0)
+    g, info = orc.rhs(m, u, terms=orc.T_FORCING)
+    v = u.copy()
+    v[:, 0, 0, 0] = (0.3, -0.2, 0.45)
+    gv, iv = orc.rhs(m, v, terms=orc.T_FORCING)
+    assert abs(iv[0] - info[0]) <= 1e-15 * info[0]
+    assert np.all(gv[:, 0, 0, 0] == 0)
+    assert np.max(np.abs(gv - g)) <= 1e-15
 
 
 def test_forcing_with_empty_band_energy_is_zero(orc):
@@ -324,6 +344,22 @@ def test_steps_stay_solenoidal_and_truncated(orc):
     E0 = orc.energy(u0)
     D0 = orc.dissipation(u0, 0.02)
     assert abs((diag[0, 2] - E0) / 0.01 - (0.1 - D0)) < 0.02
+    assert abs(diag[-1, 3] - orc.dissipation(u, 0.02)) <= 1e-14 * diag[-1, 3]
+
+
+def test_energy_budget_with_the_reported_dissipation(orc):
+    """dE/dt = eps - D (the nonlinear term conserves energy, the forcing injects
+    eps): over every step the reported energies and dissipations satisfy
+    E_n - E_(n-1) = dt (eps - (D_(n-1) + D_n) / 2) up to the trapezoid and
+    RK3 errors, O(dt^3) per step."""
+    n, nu, eps, dt = 16, 0.02, 0.1, 2e-3
+    u0 = _random_field(orc, n, 31)
+    m = orc.Member(n=n, nu=nu, eps=eps, kf_hi=2.0, dt=dt)
+    _, diag = orc.run(m, u0, 8)
+    E = np.concatenate([[orc.energy(u0)], diag[:, 2]])
+    D = np.concatenate([[orc.dissipation(u0, nu)], diag[:, 3]])
+    resid = (E[1:] - E[:-1]) / dt - (eps - 0.5 * (D[1:] + D[:-1]))
+    assert np.max(np.abs(resid)) <= 1e-4 * np.max(D), (resid, D)
 
 
 def test_cfl_time_step(orc):

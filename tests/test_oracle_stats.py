@@ -166,3 +166,110 @@ def test_gradient_tolerance_bounds_the_bin_changes_of_a_perturbed_field(orc):
         assert int(near[k]) >= int(near0[k])
         moved += diff > 2 * int(near0[k])
     assert moved >= 3                                     # the perturbation does move samples across edges
+
+
+def aliased_field(n, seed):
+    """A solenoidal field with every mode |m_i| < n/2 (no 2/3 truncation, Nyquist
+    planes zero), from a random real field by the library FFT: no symmetry of
+    the Taylor-Green kind, and its grid sum of R is not zero (triple products
+    of modes alias onto m = 0)."""
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal((3, n, n, n))
+    uh = np.stack([np.fft.rfftn(v[c]) / n ** 3 for c in range(3)])
+    m = np.fft.fftfreq(n, 1.0 / n)
+    mz, my, mx = m[:, None, None], m[None, :, None], np.arange(n // 2 + 1)[None, None, :]
+    k2 = mz * mz + my * my + mx * mx
+    kd = mx * uh[0] + my * uh[1] + mz * uh[2]
+    k = (mx, my, mz)
+    uh = np.stack([uh[c] - k[c] * kd / np.where(k2 > 0, k2, 1) for c in range(3)])
+    uh[:, 0, 0, 0] = 0
+    uh[:, n // 2], uh[:, :, n // 2], uh[..., n // 2] = 0, 0, 0
+    # physical gradients by the library inverse FFT: A[..., i, j] = d_j u_i
+    A = np.zeros((n, n, n, 3, 3))
+    for i in range(3):
+        for j in range(3):
+            A[..., i, j] = np.fft.irfftn(1j * k[j] * uh[i], s=(n, n, n), axes=(0, 1, 2)) * n ** 3
+    return uh, A
+
+
+def test_aliased_field_statistics_from_matrix_invariants(orc):
+    """Q and R as the coefficients of the characteristic polynomial of A
+    (eigenvalues, determinant; lambda^3 + Q lambda + R = 0 for Tr A = 0), and
+    eps = nu (|A|^2 - 2Q), omega^2 = |A|^2 + 2Q from A = S + W: the oracle's
+    counts (bins and under/overflow slots) and moment sums must agree.  The
+    field breaks every symmetry that would hide a wrong sign, a transposed
+    index or a swapped strain/rotation part."""
+    n, nu = 16, 0.05
+    uh, A = aliased_field(n, 11)
+    ev = np.linalg.eigvals(A)
+    Q = np.real(ev[..., 0] * ev[..., 1] + ev[..., 1] * ev[..., 2] + ev[..., 2] * ev[..., 0])
+    R = -np.linalg.det(A)
+    F2 = np.sum(A * A, axis=(-2, -1))
+    eps = nu * (F2 - 2 * Q)
+    ens = F2 + 2 * Q
+    eps_ref, nu_ref = 0.7, nu
+    tau, trs = np.sqrt(nu_ref / eps_ref), eps_ref / (2 * nu_ref)
+    qs, rs = (Q / trs).ravel(), (R / trs ** 1.5).ravel()
+    es, ws = (eps / eps_ref).ravel(), (ens * nu_ref / eps_ref).ravel()
+    diag = np.stack([A[..., i, i] for i in range(3)]).ravel() * tau
+    off = np.stack([A[..., i, j] for i in range(3) for j in range(3) if i != j]).ravel() * tau
+    # (sum Q vanishes on the grid for any solenoidal field with |m_i| < n/2; sum R does not)
+    assert abs(np.sum(rs)) > 1e-2 * np.sum(np.abs(rs))
+
+    def rng_of(v, lo_q, hi_q, nb):        # a range inside the data, off the grid of bin edges
+        lo, hi = np.quantile(v, [lo_q, hi_q])
+        return float(lo) - 0.123e-3 * (hi - lo), float(hi) + 0.0371e-3 * (hi - lo)
+
+    q_lo, q_hi = rng_of(qs, 0.08, 0.93, 12)
+    r_lo, r_hi = rng_of(rs, 0.06, 0.91, 12)
+    lg = np.log10(np.concatenate([es, ws]))
+    l_lo, l_hi = rng_of(lg, 0.05, 0.95, 40)
+    a_lo, a_hi = rng_of(np.concatenate([diag, off]), 0.04, 0.97, 30)
+    h = orc.Hist(qr_bins=12, q_lo=q_lo, q_hi=q_hi, r_lo=r_lo, r_hi=r_hi, log_bins=40, log10_lo=l_lo,
+                 log10_hi=l_hi, a_bins=30, a_lo=a_lo, a_hi=a_hi, eps_ref=eps_ref, nu_ref=nu_ref)
+    counts, mom, near, trmax = orc.stats(orc.Member(n=n, nu=nu, eps=0.1), h, uh)
+    assert np.all(near == 0)
+    got = h.split(counts)
+    # QR joint histogram and its outside slot
+    bq, br = bin_rule(qs, q_lo, q_hi, 12), bin_rule(rs, r_lo, r_hi, 12)
+    inside = (bq >= 0) & (br >= 0)
+    assert np.array_equal(got["qr"].ravel(), np.bincount(bq[inside] * 12 + br[inside], minlength=144))
+    assert got["qr_special"][0] == np.sum(~inside) > 0
+    # log histograms, under- and overflow
+    for name, v in (("log_eps", es), ("log_ens", ws)):
+        b = bin_rule(np.log10(v), l_lo, l_hi, 40)
+        assert np.array_equal(got[name], np.bincount(b[b >= 0], minlength=40)), name
+        assert got[name + "_special"][0] == np.sum(b == -1) > 0, name
+        assert got[name + "_special"][1] == np.sum(b == -2) > 0, name
+    # pooled components, under- and overflow
+    for name, v in (("a_long", diag), ("a_trans", off)):
+        b = bin_rule(v, a_lo, a_hi, 30)
+        assert np.array_equal(got[name], np.bincount(b[b >= 0], minlength=30)), name
+        assert got[name + "_special"][0] == np.sum(b == -1) > 0, name
+        assert got[name + "_special"][1] == np.sum(b == -2) > 0, name
+    # moment sums
+    close = lambda a, b, scale: abs(a - b) <= 1e-11 * scale
+    for p in range(1, 7):
+        assert close(mom[p - 1], np.sum(diag ** p), np.sum(np.abs(diag) ** p)), p
+        assert close(mom[5 + p], np.sum(off ** p), np.sum(np.abs(off) ** p)), p
+    for p in range(1, 5):
+        assert close(mom[11 + p], np.sum(es ** p), np.sum(es ** p)), p
+        assert close(mom[15 + p], np.sum(ws ** p), np.sum(ws ** p)), p
+    assert close(mom[20], np.sum(qs), np.sum(np.abs(qs)))
+    assert close(mom[21], np.sum(rs), np.sum(np.abs(rs)))
+    assert close(mom[22], np.sum(eps) / (2 * nu) * tau ** 2, np.sum(eps) / (2 * nu) * tau ** 2)
+    assert close(mom[24], np.sum(qs ** 2), np.sum(qs ** 2))
+    assert close(mom[25], np.sum(rs ** 2), np.sum(rs ** 2))
+    assert mom[23] <= 1e-24 * np.sum(F2) * tau ** 2 and trmax <= 1e-12 * np.sqrt(np.max(F2))
+
+
+def test_zero_gradient_sits_in_the_first_bin_of_a_range_starting_at_zero(orc):
+    """The bin rule takes x = lo into bin 0 (x < lo is underflow)."""
+    n = 16
+    u = np.zeros((3, n, n, n // 2 + 1), complex)
+    h = orc.Hist(qr_bins=8, q_lo=0.0, q_hi=1, r_lo=0.0, r_hi=1, log_bins=8, a_bins=8, a_lo=0.0, a_hi=1)
+    counts, _, _, _ = orc.stats(orc.Member(n=n, nu=0.01, eps=1.0), h, u)
+    got = h.split(counts)
+    assert got["qr"][0, 0] == n ** 3 and got["qr_special"][0] == 0
+    assert got["a_long"][0] == 3 * n ** 3 and got["a_long_special"][0] == 0
+    assert got["a_trans"][0] == 6 * n ** 3 and got["a_trans_special"][0] == 0
