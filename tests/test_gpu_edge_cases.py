@@ -166,6 +166,31 @@ def test_band_part_breaking_hermitian_symmetry_is_not_forced(orc, prec):
         assert np.max(np.abs(a - np.conj(b))) > 0.01
 
 
+def test_mean_flow_is_carried_but_neither_forced_nor_counted_in_the_band(orc):
+    """A uniform flow (the m = 0 mode) with a band starting at 0: it advects the
+    field and enters the CFL velocity, but it is not part of the band (E_f,
+    forcing), and it keeps its value.  Five steps against the oracle."""
+    import torch
+    ens = ens_mod()
+    n, nu, steps = 32, 0.02, 5
+    u = orc.init_field(n, 53)
+    u[:, 0, 0, 0] = (0.3, -0.2, 0.45)
+    E = ens.Ensemble()
+    m = E.add_member(ens.MemberSpec(n=n, nu=nu, eps_ref=0.1, kf_lo=0.0, kf_hi=2.0, dt=0.0, cfl=0.5,
+                                    precision="fp64", seed=53))
+    m.set_state(torch.from_numpy(u))
+    E.step(steps)
+    got = m.state().cpu().numpy()
+    d = m.diag()
+    E.close()
+    ref, rd = orc.run(orc.Member(n=n, nu=nu, eps=0.1, kf_lo=0.0, kf_hi=2.0, dt=0.0, cfl=0.5), u, steps)
+    assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
+    assert np.array_equal(got[:, 0, 0, 0], u[:, 0, 0, 0])
+    assert abs(d["E_f"] - rd[-1, 5]) <= 1e-12 * rd[-1, 5]
+    assert abs(d["umax"] - rd[-1, 6]) <= 1e-12 * rd[-1, 6]
+    assert abs(d["inj"] - 0.1) <= 1e-14
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_long_forced_run_keeps_the_invisible_parts_at_rounding(prec):
     """Regression test for the band forcing: 20 000 CFL steps of a forced 32^3

@@ -63,6 +63,7 @@ CASES = {
     "n16_cfl": (16, 0.05, 0.3, 0.0, 2.5, 0.0, 0.5),
     "n64_cfl_band_paper": (64, 0.01, 1.0, 1.4, 2.3, 0.0, 0.5),
     "n128_cfl": (128, 0.02964, 1.0, 0.0, 2.5, 0.0, 0.5),
+    "n32_band_integer_edges": (32, 0.02, 0.1, 1.0, 2.0, 0.005, 0.5),   # |m|^2 = 1 and 4 in the band
 }
 
 
