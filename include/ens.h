@@ -105,7 +105,9 @@ typedef struct {
 /* ---------------------------------------------------------------- context */
 
 /* Create a context on HIP device `device`.  `h` fixes the histogram axes of
- * every member (may be NULL: statistics calls then return ENS_E_STATE). */
+ * every member (may be NULL: statistics calls then return ENS_E_STATE); its
+ * ranges must be finite with hi > lo and its reference scales finite and
+ * positive, else ENS_E_INVALID before any device call. */
 ens_status ens_create(ens_ctx **out, int device, const ens_hist_desc *h);
 
 /* Free host metadata, graphs and device tables.  Caller memory is not freed. */

@@ -208,6 +208,8 @@ ens_status validate_desc(const ens_member_desc *d) {
 ens_status validate_hist(const ens_hist_desc *h) {
     if (h->qr_bins <= 0 || h->log_bins <= 0 || h->a_bins <= 0) return fail(ENS_E_INVALID, "histogram bin counts must be positive");
     if (h->qr_bins > 4096 || h->log_bins > (1 << 20) || h->a_bins > (1 << 20)) return fail(ENS_E_INVALID, "too many bins");
+    for (double v : {h->q_lo, h->q_hi, h->r_lo, h->r_hi, h->log10_lo, h->log10_hi, h->a_lo, h->a_hi, h->eps_ref, h->nu_ref})
+        if (!std::isfinite(v)) return fail(ENS_E_INVALID, "histogram ranges and reference scales must be finite");
     if (!(h->q_hi > h->q_lo) || !(h->r_hi > h->r_lo) || !(h->log10_hi > h->log10_lo) || !(h->a_hi > h->a_lo))
         return fail(ENS_E_INVALID, "histogram ranges need hi > lo");
     if (!(h->eps_ref > 0) || !(h->nu_ref > 0)) return fail(ENS_E_INVALID, "eps_ref and nu_ref must be positive");
@@ -290,18 +292,21 @@ hipError_t enqueue_step(const ens_ctx *ctx, const Plan &pl, hipStream_t s, Prof 
     hipError_t e = hipSuccess;
     auto rec = [&](int pass, auto &&fn) -> hipError_t {
         if (prof) {
+            // events belong to prof as soon as they exist: the caller destroys
+            // them whatever fails later
             hipEvent_t a, b;
             hipError_t r = hipEventCreate(&a);
             if (r != hipSuccess) return r;
+            prof->ev.push_back(a);
             r = hipEventCreate(&b);
             if (r != hipSuccess) return r;
+            prof->ev.push_back(b);
+            prof->pass.push_back(pass);
             r = hipEventRecord(a, s);
             if (r != hipSuccess) return r;
             r = fn();
             if (r != hipSuccess) return r;
-            r = hipEventRecord(b, s);
-            prof->ev.push_back(a); prof->ev.push_back(b); prof->pass.push_back(pass);
-            return r;
+            return hipEventRecord(b, s);
         }
         return fn();
     };

@@ -59,6 +59,13 @@ def test_argument_validation_without_a_gpu(L):
     ctx = ctypes.c_void_p()
     bad = _lib.HistDesc(0, -1, 1, -1, 1, 8, -1, 1, 8, -1, 1, 1.0, 1.0)
     assert L.ens_create(ctypes.byref(ctx), 0, ctypes.byref(bad)) == _lib.ENS_E_INVALID
+    # ranges and reference scales must be finite (checked before any device call)
+    inf = float("inf")
+    for i, v in ((2, inf), (1, -inf), (7, inf), (10, inf), (11, inf), (12, inf), (4, float("nan"))):
+        fields = [8, -1.0, 1.0, -1.0, 1.0, 8, -1.0, 1.0, 8, -1.0, 1.0, 1.0, 1.0]
+        fields[i] = v
+        bad = _lib.HistDesc(*fields)
+        assert L.ens_create(ctypes.byref(ctx), 0, ctypes.byref(bad)) == _lib.ENS_E_INVALID, i
 
 
 def test_no_gpu_means_a_clean_error(L):
