@@ -293,7 +293,11 @@ ens_status ens_set_stats(ens_ctx *ctx, int32_t m, const uint64_t *counts, const 
  *   [S(A_L), F(A_L), H(A_L), F(A_T), H(A_T), <eps*>, <Omega*>, 0]
  * Member pdfs are count / (n_samples * bin width (area for QR)), with
  * n_samples including under/overflow; mixed = sum_i w_i pdf_i in sorted-lambda
- * order; moments likewise from per-member means.  Runs on the GPU. */
+ * order; moments likewise from per-member means.  Runs on the GPU.  The member
+ * table of a call lives in a device buffer the context owns (grown, after a
+ * device synchronisation, when a call needs more): ens_mix and ens_mix_table
+ * calls of one context are ordered on one stream, but calls on streams whose
+ * kernels may run at once race. */
 ens_status ens_mix_len(const ens_ctx *ctx, int32_t count, size_t *n_out);
 ens_status ens_mix(ens_ctx *ctx, const int32_t *members, int32_t count, double c, double Z,
                    int32_t weight_mode, double q_sigma, double *dev_out, void *stream);

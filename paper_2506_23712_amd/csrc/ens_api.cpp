@@ -722,6 +722,8 @@ ENS_API ens_status ens_mix(ens_ctx *ctx, const int32_t *members, int32_t count, 
     for (int id : ids) HIPCK(ctx, hipStreamSynchronize(ctx->members[id]->last));
     const size_t need = mix_scratch_bytes(count);
     if (need > ctx->mix_scratch_bytes) {
+        // an earlier mixture's kernels may still read the old table
+        if (ctx->mix_scratch) HIPCK(ctx, hipDeviceSynchronize());
         if (ctx->mix_scratch) HIPCK(ctx, hipFree(ctx->mix_scratch));
         ctx->mix_scratch = nullptr;
         HIPCK(ctx, hipMalloc(&ctx->mix_scratch, need));
@@ -785,6 +787,8 @@ ENS_API ens_status ens_mix_table(ens_ctx *ctx, const int32_t *members, int32_t c
     for (int id : ids) HIPCK(ctx, hipStreamSynchronize(ctx->members[id]->last));
     const size_t need = mix_scratch_bytes(count);
     if (need > ctx->mix_scratch_bytes) {
+        // an earlier mixture's kernels may still read the old table
+        if (ctx->mix_scratch) HIPCK(ctx, hipDeviceSynchronize());
         if (ctx->mix_scratch) HIPCK(ctx, hipFree(ctx->mix_scratch));
         ctx->mix_scratch = nullptr;
         HIPCK(ctx, hipMalloc(&ctx->mix_scratch, need));
