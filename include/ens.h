@@ -209,7 +209,13 @@ ens_status ens_get_diag(ens_ctx *ctx, int32_t m, ens_diag *out);
 ens_status ens_autotune(ens_ctx *ctx, const int32_t *members, int32_t count, void *stream,
                         const char *cache_path);
 
-/* Force / query the variant of one (pass, n, precision).  Invalidates graphs. */
+/* Force / query the variant of one (pass, n, precision).  Invalidates graphs.
+ * Besides the timed passes above, pass 5 (z forward + update) has two
+ * variants, chosen by default and not timed by ens_autotune (it updates the
+ * state): 0 = the z inverse of every RK stage is a launch of its own; 1 = the
+ * z forward of the first two stages also performs the next stage's z inverse
+ * from the velocity it has just updated, so each step reads the velocity back
+ * once instead of three times (default for n <= 512). */
 ens_status ens_set_variant(ens_ctx *ctx, int32_t pass, int32_t n, int32_t precision, int32_t variant);
 ens_status ens_get_variant(const ens_ctx *ctx, int32_t pass, int32_t n, int32_t precision, int32_t *variant);
 

@@ -264,13 +264,21 @@ int variant_of(const ens_ctx *ctx, int pass, int n, int prec) {
 
 // One RK step of one group (three stages, then the end-of-step reduction) on
 // stream s; the groups of a plan are independent of each other.
+// With the fused z forward (variant 1) the z forward of stages 0 and 1 also
+// performs the next stage's z inverse, which is then not launched.
+bool zinv_fused(const ens_ctx *ctx, int pass, int stage, int n, int prec) {
+    return pass == P_ZINV && stage > 0 && variant_of(ctx, P_ZFWD, n, prec) == 1;
+}
+
 hipError_t enqueue_group(const ens_ctx *ctx, const Group &g, hipStream_t s) {
     const int cnt = (int)g.ids.size();
     hipError_t e;
     for (int stage = 0; stage < 3; stage++)
-        for (int pass = P_BAND; pass <= P_ZFWD; pass++)
+        for (int pass = P_BAND; pass <= P_ZFWD; pass++) {
+            if (zinv_fused(ctx, pass, stage, g.n, g.prec)) continue;
             if ((e = launch_pass(pass, variant_of(ctx, pass, g.n, g.prec), g.n, g.prec, g.dev, cnt, stage, g.tw, s)))
                 return e;
+        }
     return launch_pass(P_END, 0, g.n, g.prec, g.dev, cnt, 0, g.tw, s);
 }
 
@@ -314,6 +322,7 @@ hipError_t enqueue_step(const ens_ctx *ctx, const Plan &pl, hipStream_t s, Prof 
         for (const Group &g : pl.groups) {
             const int cnt = (int)g.ids.size();
             for (int pass = P_BAND; pass <= P_ZFWD; pass++) {
+                if (zinv_fused(ctx, pass, stage, g.n, g.prec)) continue;
                 const int v = variant_of(ctx, pass, g.n, g.prec);
                 if ((e = rec(pass, [&] { return launch_pass(pass, v, g.n, g.prec, g.dev, cnt, stage, g.tw, s); }))) return e;
             }

@@ -304,7 +304,7 @@ class Ensemble:
         out = {}
         for n, prec in sorted({(m.spec.n, m.spec.precision) for m in ms}):
             p = _lib.ENS_FP32 if prec == "fp32" else _lib.ENS_FP64
-            for pid in (1, 2, 3, 4):
+            for pid in (1, 2, 3, 4, 5):
                 v = ctypes.c_int32()
                 check(lib().ens_get_variant(self.ctx, pid, n, p, ctypes.byref(v)))
                 out[f"{_lib.PASS_NAMES[pid]}:{n}:{prec}"] = v.value

@@ -62,11 +62,25 @@ def pass_bytes(n: int, prec: str) -> dict:
     }
 
 
+def zfwd_stage_bytes(n: int, prec: str, stage: int, fused: bool = False) -> tuple:
+    """(read, write) algorithmic bytes of the z forward + update of one RK
+    stage for one member: the 3 z-line fields and u_hat read, u_hat written;
+    the RK register read in stages 1 and 2 and written in stages 0 and 1; the
+    fused variant (stages 0 and 1) also writes the next stage's 5 z-inverse
+    fields."""
+    K = n // 3
+    cs = 16 if prec == "fp64" else 8
+    S, zl = (2 * K + 1) ** 2 * (K + 1), n * (2 * K + 1) * (K + 1)
+    r = 3 * zl + 3 * S + (3 * S if stage > 0 else 0)
+    w = 3 * S + (3 * S if stage < 2 else 0) + (5 * zl if fused and stage < 2 else 0)
+    return r * cs, w * cs
+
+
 def kernel_name(pass_name: str, n: int, prec: str, variant) -> str:
     """Symbol (as rocprofv3 prints it, without arguments) of a pass's kernel."""
     p = "float" if prec == "fp32" else "double"
     if pass_name == "zfwd_update":                             # the kernel of the middle RK stage
-        return f"ens::k_zfwd_update<{p}, {n}, 1>"
+        return f"ens::k_zfwd_update<{p}, {n}, 1{', true' if variant == 1 else ''}>"
     ea = 16 if prec == "fp32" else 8
     if pass_name == "xpass" and variant == 6 and n >= 64:
         return f"ens::k_xpass_wave2<{p}, {n}, {ea}>"
@@ -180,11 +194,10 @@ def write_summary(n: int, counts, out: str, trace: str | None = None, workloads=
                 if f", {n}" not in short or ("float" in short) != (prec == "fp32"):
                     continue
                 ar, aw = rw[k][0] * cs * cnt, rw[k][1] * cs * cnt
-                st = re.match(r"k_zfwd_update<\w+, \d+, (\d)>", short)
+                st = re.match(r"k_zfwd_update<\w+, \d+, (\d)(, true)?>", short)
                 if st:                                     # one RK stage: its own register traffic
-                    stage = int(st.group(1))
-                    ar = (3 * zl + 3 * S + (3 * S if stage > 0 else 0)) * cs * cnt
-                    aw = (3 * S + (3 * S if stage < 2 else 0)) * cs * cnt
+                    r1, w1 = zfwd_stage_bytes(n, prec, int(st.group(1)), st.group(2) is not None)
+                    ar, aw = r1 * cnt, w1 * cnt
                 us = avg.get(name)
                 rows.append((wl, short, ar / 1e9, aw / 1e9, v["fetch_bytes"] / 1e9, v["write_bytes"] / 1e9,
                              (v["fetch_bytes"] + v["write_bytes"]) / (ar + aw), t["source_hash"], us,
@@ -202,7 +215,8 @@ def write_summary(n: int, counts, out: str, trace: str | None = None, workloads=
                   "counter per run), KiB per dispatch, scaled by what the same counter reads for a plain 1 GiB device "
                   "copy.  Algorithmic bytes: each pass's inputs read once and outputs written once, truncated storage "
                   "(a `zfwd_update` kernel of one RK stage: stage 0 does not read the RK register, stage 2 does not "
-                  "write it; the stage-averaged figure where the stage is not in the name).  The pencil buffers hold no row "
+                  "write it, and a fused kernel (`true` in its name, stages 0 and 1) also writes the next stage's "
+                  "5 z-inverse fields; the stage-averaged figure where the stage is not in the name).  The pencil buffers hold no row "
                   "padding; what the measured bytes add comes from loads that straddle 128-byte lines (the y inverse "
                   "and the z forward read rows of K + 1 values that start anywhere in a line) and from the z planes' "
                   "pad of at most one line.\n\n")

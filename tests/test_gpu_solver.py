@@ -112,6 +112,63 @@ def test_twenty_steps_fp32_within_bound(orc, n):
     E.close()
 
 
+FUSED = {
+    # name: (n, nu, eps, kf_lo, kf_hi, dt, prec, tolerance after 20 steps)
+    "n16_fp64": (16, 0.05, 0.3, 0.0, 2.5, 0.0, "fp64", 1e-11),
+    "n32_fp64_fixed_dt": (32, 0.02, 0.1, 0.0, 2.0, 0.01, "fp64", 1e-11),
+    "n64_fp64_band_paper": (64, 0.01, 1.0, 1.4, 2.3, 0.0, "fp64", 1e-11),
+    "n128_fp64": (128, 0.02964, 1.0, 0.0, 2.5, 0.0, "fp64", 1e-11),
+    "n64_fp32_band_paper": (64, 0.01, 1.0, 1.4, 2.3, 0.0, "fp32", 2e-5),
+    "n128_fp32": (128, 0.02964, 1.0, 0.0, 2.5, 0.0, "fp32", 2e-5),
+}
+
+
+@pytest.mark.parametrize("case", list(FUSED))
+def test_fused_z_forward_matches_oracle(orc, case):
+    """z forward variant 1: stages 0 and 1 also perform the next stage's z
+    inverse from the updated velocity in registers (two z-inverse launches
+    fewer per step).  Twenty steps against the oracle, in graph and direct
+    launches."""
+    n, nu, eps, lo, hi, dt, prec, tol = FUSED[case]
+    ref, rd = orc.run(oracle_member(n, nu, eps, lo, hi, dt), orc.init_field(n, 91 + n), 20)
+    for graphs in (True, False):
+        E, m = make(n, nu, eps, lo, hi, dt, prec=prec, seed=91 + n, graphs=graphs)
+        E.set_variant("zfwd_update", n, prec, 1)
+        E.step(20)
+        err = rel(m.state().cpu().numpy(), ref)
+        d = m.diag()
+        print(f"{case} graphs={graphs}: rel L2 after 20 steps = {err:.3e}")
+        assert err <= tol
+        assert abs(d["E"] - rd[-1, 2]) <= 10 * tol * rd[-1, 2]
+        assert d["step"] == 20 and not d["diverged"]
+        E.close()
+
+
+@pytest.mark.parametrize("n,prec,count", [(256, "fp32", 25), (128, "fp32", 24), (64, "fp32", 47), (256, "fp64", 1),
+                                          (512, "fp32", 1), (1024, "fp32", 1)])
+def test_fused_z_forward_agrees_with_separate_passes(n, prec, count):
+    """The fused z forward against the separate z inverse on the benchmark's
+    batch shapes, three steps: the same operations up to the order of the
+    inverse transform's stages, so agreement is to rounding."""
+    ens = ens_mod()
+    finals = []
+    for variant in (0, 1):
+        E = ens.Ensemble()
+        ms = [E.add_member(ens.MemberSpec(n=n, nu=0.03395 * (256 / n) ** (4 / 3), eps_ref=1.0, lam=0.3 * i - 1.0,
+                                          kf_hi=2.5, dt=0.0, cfl=0.5, precision=prec, seed=800 + i))
+              for i in range(count)]
+        E.set_variant("zfwd_update", n, prec, variant)
+        E.step(3)
+        pick = sorted({0, count // 2, count - 1})
+        finals.append([ms[i].state().cpu().numpy() for i in pick])
+        E.close()
+    tol = 2e-6 if prec == "fp32" else 1e-13
+    for a, b in zip(finals[0], finals[1]):
+        err = rel(b, a)
+        print(f"{n} {prec} x{count}: fused vs separate rel L2 {err:.2e}")
+        assert err <= tol
+
+
 def test_graph_and_direct_launch_agree_bitwise():
     outs = []
     for graphs in (True, False):
@@ -263,7 +320,8 @@ def test_autotune_keeps_state_and_writes_cache(tmp_path):
     cache = tmp_path / "variants.txt"
     table = E.autotune(cache_path=str(cache))
     assert np.array_equal(m.state().cpu().numpy(), before)
-    assert set(table.values()) <= {0, 1, 2, 3, 4, 5, 6} and len(table) == 4
+    assert set(table.values()) <= {0, 1, 2, 3, 4, 5, 6} and len(table) == 5
+    assert table["zfwd_update:32:fp64"] == 1          # not timed (it updates the state): the default, fused
     text = cache.read_text()
-    assert "zinv:32:fp64" in text
+    assert "zinv:32:fp64" in text and "zfwd_update" not in text
     E.close()

@@ -39,6 +39,8 @@ def test_kernel_names_exist_in_the_sources():
     assert p.kernel_name("xpass", 32, "fp32", 2) == "ens::k_xpass<float, 32, 8>"
     assert p.kernel_name("yinv", 256, "fp32", 1) == "ens::k_yinv<float, 256, 16, 1>"
     assert p.kernel_name("zinv", 256, "fp32", 2) == "ens::k_zinv<float, 256, 8, 2>"
+    assert p.kernel_name("zfwd_update", 256, "fp32", 1) == "ens::k_zfwd_update<float, 256, 1, true>"
+    assert p.kernel_name("zfwd_update", 256, "fp64", 0) == "ens::k_zfwd_update<double, 256, 1>"
     # every y/z name appears in the committed trace of the same sources
     table = open(os.path.join(ROOT, "profiles", "ens96_mixed_fp32_and_single256_fp64_kernel_stats.md")).read()
     assert "`" + p.kernel_name("yfwd", 256, "fp32", 3) + "`" in table
@@ -62,25 +64,47 @@ def test_trace_averages_read_the_committed_kernel_table():
 
 
 def test_summary_uses_each_rk_stage_own_bytes_for_the_z_forward():
-    """The z forward + update of RK stage 0 reads no RK register and that of
-    stage 2 writes none: the committed summary's algorithmic bytes of each
-    stage's kernel follow that, and average to the pass model's figure."""
+    """The z forward + update of RK stage 0 reads no RK register, that of
+    stage 2 writes none, and a fused kernel (stages 0 and 1, `true` in its
+    name) also writes the next stage's 5 z-inverse fields: the committed
+    summary's algorithmic bytes of each stage's kernel follow that, and the
+    unfused stages average to the pass model's figure."""
     from paper_2506_23712_amd import profiling as p
     path = os.path.join(ROOT, "profiles", "traffic_summary_256.md")
     n, K, cs, cnt = 256, 256 // 3, 8, 25
     S, zl = (2 * K + 1) ** 2 * (K + 1), n * (2 * K + 1) * (K + 1)
-    want = {0: ((3 * zl + 3 * S) * cs * cnt, 6 * S * cs * cnt),
-            1: ((3 * zl + 6 * S) * cs * cnt, 6 * S * cs * cnt),
-            2: ((3 * zl + 6 * S) * cs * cnt, 3 * S * cs * cnt)}
     got = {}
     for l in open(path):
         cells = [c.strip() for c in l.strip().strip("|").split("|")]
-        if len(cells) > 2 and cells[0] == "ens96_mixed_fp32" and cells[1].startswith("`k_zfwd_update<float, 256, "):
-            st = int(cells[1][-3])
-            r, w = (float(x) for x in cells[2].split("/"))
-            got[st] = (r, w)
-    assert sorted(got) == [0, 1, 2]
-    for st, (r, w) in want.items():
-        assert abs(got[st][0] - r / 1e9) < 1e-3 and abs(got[st][1] - w / 1e9) < 1e-3, (st, got[st])
-    avg = sum(r + w for r, w in want.values()) / 3
-    assert abs(avg - p.pass_bytes(n, "fp32")["zfwd_update"] * cnt) < 1e-6 * avg
+        if len(cells) > 2 and cells[0] == "ens96_mixed_fp32":
+            m = re.fullmatch(r"`k_zfwd_update<float, 256, (\d)(, true)?>`", cells[1])
+            if m:
+                r, w = (float(x) for x in cells[2].split("/"))
+                got[(int(m.group(1)), m.group(2) is not None)] = (r, w)
+    assert {st for st, _ in got} == {0, 1, 2}
+    for (st, fused), (r, w) in got.items():
+        want_r = (3 * zl + 3 * S + (3 * S if st > 0 else 0)) * cs * cnt
+        want_w = (3 * S + (3 * S if st < 2 else 0) + (5 * zl if fused else 0)) * cs * cnt
+        assert abs(r - want_r / 1e9) < 1e-3 and abs(w - want_w / 1e9) < 1e-3, (st, fused, r, w)
+        assert tuple(x * cnt for x in p.zfwd_stage_bytes(n, "fp32", st, fused)) == (want_r, want_w)
+    avg = sum(sum(p.zfwd_stage_bytes(n, "fp32", st)) for st in range(3)) / 3
+    assert abs(avg - p.pass_bytes(n, "fp32")["zfwd_update"]) < 1e-6 * avg
+
+
+def test_dominant_kernel_counts_launches_per_kernel():
+    """The benchmark's roofline kernel: the largest summed time of one kernel
+    per step.  The z forward's time is spread over three stage kernels, and
+    with the fused z forward the z inverse launches once per step."""
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    ms = {"band": 0.03, "zinv": 0.91, "yinv": 5.8, "xpass": 5.9, "yfwd": 2.9, "zfwd_update": 6.3, "end_step": 0.01}
+    res = {"prof": {(256, "fp32"): (ms, 25)}, "variants": {"zfwd_update:256:fp32": 1, "xpass:256:fp32": 6}}
+    (n, prec), k, count, avg, launches, fused = bench.dominant_kernel(res)
+    assert (n, prec, k, count, launches, fused) == (256, "fp32", "xpass", 25, 3, True)
+    assert abs(avg - 5.9 / 3) < 1e-12
+    ms2 = {"zinv": 3.0, "yinv": 2.5, "xpass": 2.9, "yfwd": 1.0, "zfwd_update": 4.0}
+    r = bench.dominant_kernel({"prof": {(128, "fp64"): (ms2, 2)}, "variants": {"zfwd_update:128:fp64": 1}})
+    assert r[1] == "zinv" and r[4] == 1 and r[3] == 3.0
+    r = bench.dominant_kernel({"prof": {(128, "fp64"): (ms2, 2)}, "variants": {"zfwd_update:128:fp64": 0}})
+    assert r[1] == "zinv" and r[4] == 3 and abs(r[3] - 1.0) < 1e-12
