@@ -80,7 +80,7 @@ def kernel_name(pass_name: str, n: int, prec: str, variant) -> str:
     """Symbol (as rocprofv3 prints it, without arguments) of a pass's kernel."""
     p = "float" if prec == "fp32" else "double"
     if pass_name == "zfwd_update":                             # the kernel of the middle RK stage
-        return f"ens::k_zfwd_update<{p}, {n}, 1{', true' if variant == 1 else ''}>"
+        return f"ens::k_zfwd_update<{p}, {n}, 1, {'true' if variant == 1 else 'false'}>"
     ea = 16 if prec == "fp32" else 8
     if pass_name == "xpass" and variant == 6 and n >= 64:
         return f"ens::k_xpass_wave2<{p}, {n}, {ea}>"
@@ -194,9 +194,9 @@ def write_summary(n: int, counts, out: str, trace: str | None = None, workloads=
                 if f", {n}" not in short or ("float" in short) != (prec == "fp32"):
                     continue
                 ar, aw = rw[k][0] * cs * cnt, rw[k][1] * cs * cnt
-                st = re.match(r"k_zfwd_update<\w+, \d+, (\d)(, true)?>", short)
+                st = re.match(r"k_zfwd_update<\w+, \d+, (\d)(?:, (true|false))?>", short)
                 if st:                                     # one RK stage: its own register traffic
-                    r1, w1 = zfwd_stage_bytes(n, prec, int(st.group(1)), st.group(2) is not None)
+                    r1, w1 = zfwd_stage_bytes(n, prec, int(st.group(1)), st.group(2) == "true")
                     ar, aw = r1 * cnt, w1 * cnt
                 us = avg.get(name)
                 rows.append((wl, short, ar / 1e9, aw / 1e9, v["fetch_bytes"] / 1e9, v["write_bytes"] / 1e9,

@@ -40,7 +40,7 @@ def test_kernel_names_exist_in_the_sources():
     assert p.kernel_name("yinv", 256, "fp32", 1) == "ens::k_yinv<float, 256, 16, 1>"
     assert p.kernel_name("zinv", 256, "fp32", 2) == "ens::k_zinv<float, 256, 8, 2>"
     assert p.kernel_name("zfwd_update", 256, "fp32", 1) == "ens::k_zfwd_update<float, 256, 1, true>"
-    assert p.kernel_name("zfwd_update", 256, "fp64", 0) == "ens::k_zfwd_update<double, 256, 1>"
+    assert p.kernel_name("zfwd_update", 256, "fp64", 0) == "ens::k_zfwd_update<double, 256, 1, false>"
     # every y/z name appears in the committed trace of the same sources
     table = open(os.path.join(ROOT, "profiles", "ens96_mixed_fp32_and_single256_fp64_kernel_stats.md")).read()
     assert "`" + p.kernel_name("yfwd", 256, "fp32", 3) + "`" in table
@@ -77,10 +77,10 @@ def test_summary_uses_each_rk_stage_own_bytes_for_the_z_forward():
     for l in open(path):
         cells = [c.strip() for c in l.strip().strip("|").split("|")]
         if len(cells) > 2 and cells[0] == "ens96_mixed_fp32":
-            m = re.fullmatch(r"`k_zfwd_update<float, 256, (\d)(, true)?>`", cells[1])
+            m = re.fullmatch(r"`k_zfwd_update<float, 256, (\d), (true|false)>`", cells[1])
             if m:
                 r, w = (float(x) for x in cells[2].split("/"))
-                got[(int(m.group(1)), m.group(2) is not None)] = (r, w)
+                got[(int(m.group(1)), m.group(2) == "true")] = (r, w)
     assert {st for st, _ in got} == {0, 1, 2}
     for (st, fused), (r, w) in got.items():
         want_r = (3 * zl + 3 * S + (3 * S if st > 0 else 0)) * cs * cnt
