@@ -177,7 +177,9 @@ ens_status ens_step(ens_ctx *ctx, const int32_t *members, int32_t count, int32_t
  * kernel on `stream`; synchronises.  ms_out[p] (p < ENS_NPASS) receives the
  * summed kernel time of pass p: 0 band energy, 1 z inverse + curl,
  * 2 y inverse, 3 x fused (c2r, u x omega, r2c), 4 y forward,
- * 5 z forward + projection + forcing + update, 6 end-of-step reduction. */
+ * 5 z forward + projection + forcing + update, 6 end-of-step reduction.
+ * With the fused z forward (pass 5 variant 1) the z inverse of stages 2 and
+ * 3 runs inside pass 5 and is counted there. */
 #define ENS_NPASS 7
 ens_status ens_profile_step(ens_ctx *ctx, const int32_t *members, int32_t count, void *stream,
                             double *ms_out);
