@@ -77,18 +77,25 @@ def run_workload(ens, torch, name, specs, steps, warmup, stats_every, hist_nu, a
     members = [E.add_member(s) for s in specs]
     torch.cuda.synchronize()
     variants = E.autotune() if autotune else E.variants()
-    for i in range(warmup):
-        E.step(1)
-        if stats_every and (i + 1) % stats_every == 0:
-            E.accumulate_stats()
+
+    def advance(k):
+        """k steps with a statistics snapshot after every stats_every-th; the
+        steps between snapshots are one library call (inside a call, each step
+        but the last hands its final z inverse to the next)."""
+        done = 0
+        while done < k:
+            chunk = min(stats_every - done % stats_every, k - done) if stats_every else k - done
+            E.step(chunk)
+            done += chunk
+            if stats_every and done % stats_every == 0:
+                E.accumulate_stats()
+
+    advance(warmup)
     for m in members:
         m.reset_stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(steps):
-        E.step(1)
-        if stats_every and (i + 1) % stats_every == 0:
-            E.accumulate_stats()
+    advance(steps)
     mix = E.mix(0.023, math.log(8), mode=0)
     torch.cuda.synchronize()
     t1 = time.perf_counter()

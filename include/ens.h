@@ -169,7 +169,11 @@ ens_status ens_member_get_state(ens_ctx *ctx, int32_t m, double *dev_uhat, void 
  * nonlinear term and, at every stage, the band's part of the m_x = 0 plane
  * is made Hermitian in place before E_f is summed.
  * Members may differ in N and precision.  Device-side dt: members with dt <= 0
- * take the CFL step from their stage-1 field.  Asynchronous on `stream`. */
+ * take the CFL step from their stage-1 field.  With the fused z forward
+ * (pass 5 variant 1, the default for n <= 512) every step of a call but the
+ * last also performs the next step's first z inverse, so splitting the same
+ * steps into calls differently changes results at the rounding level; the
+ * same sequence of calls is bitwise reproducible.  Asynchronous on `stream`. */
 ens_status ens_step(ens_ctx *ctx, const int32_t *members, int32_t count, int32_t nsteps,
                     void *stream);
 

@@ -142,11 +142,31 @@ struct Group {
     const void *tw = nullptr;
 };
 
+// What a step takes from and leaves to its neighbours in one ens_step call
+// (with the fused z forward): every step but the call's first finds its first
+// z inverse already done by the previous step's last z forward, and every
+// step but the call's last does that for the next one.
+struct StepKind {
+    bool zinv0_done;   // stage 0's z inverse was performed by the previous step
+    bool fuse_last;    // the last stage's z forward performs the next step's first z inverse
+    int index() const { return (zinv0_done ? 2 : 0) + (fuse_last ? 1 : 0); }
+};
+constexpr StepKind kLoneStep{false, false};
+
 struct Plan {
     std::vector<Group> groups;
-    hipGraphExec_t exec = nullptr;
-    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec[4] = {};     // one captured step per StepKind::index()
+    hipGraph_t graph[4] = {};
 };
+
+void free_graphs(Plan &pl) {
+    for (int i = 0; i < 4; i++) {
+        if (pl.exec[i]) (void)hipGraphExecDestroy(pl.exec[i]);
+        if (pl.graph[i]) (void)hipGraphDestroy(pl.graph[i]);
+        pl.exec[i] = nullptr;
+        pl.graph[i] = nullptr;
+    }
+}
 
 }  // namespace
 
@@ -265,18 +285,27 @@ int variant_of(const ens_ctx *ctx, int pass, int n, int prec) {
 // One RK step of one group (three stages, then the end-of-step reduction) on
 // stream s; the groups of a plan are independent of each other.
 // With the fused z forward (variant 1) the z forward of stages 0 and 1 also
-// performs the next stage's z inverse, which is then not launched.
-bool zinv_fused(const ens_ctx *ctx, int pass, int stage, int n, int prec) {
-    return pass == P_ZINV && stage > 0 && variant_of(ctx, P_ZFWD, n, prec) == 1;
+// performs the next stage's z inverse, which is then not launched; so is
+// stage 0's when the previous step of the same call performed it.
+bool zinv_fused(const ens_ctx *ctx, int pass, int stage, int n, int prec, StepKind k) {
+    return pass == P_ZINV && variant_of(ctx, P_ZFWD, n, prec) == 1 && (stage > 0 || k.zinv0_done);
 }
 
-hipError_t enqueue_group(const ens_ctx *ctx, const Group &g, hipStream_t s) {
+// The variant launched for a pass: the fused z forward's last stage runs as
+// the internal variant 2 when the next step of the call takes its z inverse.
+int launch_variant(const ens_ctx *ctx, int pass, int stage, int n, int prec, StepKind k) {
+    const int v = variant_of(ctx, pass, n, prec);
+    return (pass == P_ZFWD && v == 1 && stage == 2 && k.fuse_last) ? 2 : v;
+}
+
+hipError_t enqueue_group(const ens_ctx *ctx, const Group &g, hipStream_t s, StepKind k) {
     const int cnt = (int)g.ids.size();
     hipError_t e;
     for (int stage = 0; stage < 3; stage++)
         for (int pass = P_BAND; pass <= P_ZFWD; pass++) {
-            if (zinv_fused(ctx, pass, stage, g.n, g.prec)) continue;
-            if ((e = launch_pass(pass, variant_of(ctx, pass, g.n, g.prec), g.n, g.prec, g.dev, cnt, stage, g.tw, s)))
+            if (zinv_fused(ctx, pass, stage, g.n, g.prec, k)) continue;
+            if ((e = launch_pass(pass, launch_variant(ctx, pass, stage, g.n, g.prec, k), g.n, g.prec, g.dev, cnt,
+                                 stage, g.tw, s)))
                 return e;
         }
     return launch_pass(P_END, 0, g.n, g.prec, g.dev, cnt, 0, g.tw, s);
@@ -285,18 +314,18 @@ hipError_t enqueue_group(const ens_ctx *ctx, const Group &g, hipStream_t s) {
 // Graph mode 2: inside the capture on ctx->cap, fork one branch per group onto
 // its own stream and join them again, so that the captured graph lets the
 // groups' kernels run side by side.  Streams and events exist before capture.
-hipError_t enqueue_step_branches(const ens_ctx *ctx, const Plan &pl) {
+hipError_t enqueue_step_branches(const ens_ctx *ctx, const Plan &pl, StepKind k) {
     hipError_t e = hipEventRecord(ctx->fork[0], ctx->cap);
     for (size_t i = 0; i < pl.groups.size() && e == hipSuccess; i++) {
         if ((e = hipStreamWaitEvent(ctx->side[i], ctx->fork[0], 0))) break;
-        if ((e = enqueue_group(ctx, pl.groups[i], ctx->side[i]))) break;
+        if ((e = enqueue_group(ctx, pl.groups[i], ctx->side[i], k))) break;
         if ((e = hipEventRecord(ctx->fork[i + 1], ctx->side[i]))) break;
         e = hipStreamWaitEvent(ctx->cap, ctx->fork[i + 1], 0);
     }
     return e;
 }
 
-hipError_t enqueue_step(const ens_ctx *ctx, const Plan &pl, hipStream_t s, Prof *prof) {
+hipError_t enqueue_step(const ens_ctx *ctx, const Plan &pl, hipStream_t s, Prof *prof, StepKind k) {
     hipError_t e = hipSuccess;
     auto rec = [&](int pass, auto &&fn) -> hipError_t {
         if (prof) {
@@ -322,8 +351,8 @@ hipError_t enqueue_step(const ens_ctx *ctx, const Plan &pl, hipStream_t s, Prof 
         for (const Group &g : pl.groups) {
             const int cnt = (int)g.ids.size();
             for (int pass = P_BAND; pass <= P_ZFWD; pass++) {
-                if (zinv_fused(ctx, pass, stage, g.n, g.prec)) continue;
-                const int v = variant_of(ctx, pass, g.n, g.prec);
+                if (zinv_fused(ctx, pass, stage, g.n, g.prec, k)) continue;
+                const int v = launch_variant(ctx, pass, stage, g.n, g.prec, k);
                 if ((e = rec(pass, [&] { return launch_pass(pass, v, g.n, g.prec, g.dev, cnt, stage, g.tw, s); }))) return e;
             }
         }
@@ -403,10 +432,7 @@ ENS_API ens_status ens_destroy(ens_ctx *ctx) {
     // release (or a sticky error of the device) fails.
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
-    for (auto &kv : ctx->plans) {
-        if (kv.second->exec) (void)hipGraphExecDestroy(kv.second->exec);
-        if (kv.second->graph) (void)hipGraphDestroy(kv.second->graph);
-    }
+    for (auto &kv : ctx->plans) free_graphs(*kv.second);
     for (auto &m : ctx->members)
         if (m && m->dev) (void)hipFree(m->dev);
     for (void *p : ctx->dev_allocs) (void)hipFree(p);
@@ -424,12 +450,7 @@ ENS_API ens_status ens_set_graphs(ens_ctx *ctx, int32_t mode) {
     if (mode != ctx->graphs) {
         HIPCK(ctx, hipSetDevice(ctx->device));
         HIPCK(ctx, hipDeviceSynchronize());
-        for (auto &kv : ctx->plans) {                      // captured with the other mode
-            if (kv.second->exec) HIPCK(ctx, hipGraphExecDestroy(kv.second->exec));
-            if (kv.second->graph) HIPCK(ctx, hipGraphDestroy(kv.second->graph));
-            kv.second->exec = nullptr;
-            kv.second->graph = nullptr;
-        }
+        for (auto &kv : ctx->plans) free_graphs(*kv.second);   // captured with the other mode
     }
     ctx->graphs = mode;
     return ENS_OK;
@@ -535,8 +556,17 @@ ENS_API ens_status ens_step(ens_ctx *ctx, const int32_t *members, int32_t count,
     if (ens_status st = make_plan(ctx, ids, &pl)) return st;
     hipStream_t s = (hipStream_t)stream;
     if (nsteps == 0) return ENS_OK;
+    // step i of the call: its first z inverse done by step i - 1 (i > 0), the
+    // next step's done by its last z forward (i < nsteps - 1)
+    auto kind_of = [&](int i) { return StepKind{i > 0, i + 1 < nsteps}; };
     if (ctx->graphs) {
-        if (!pl->exec) {
+        for (int i = 0; i < nsteps; i++) {
+            const StepKind k = kind_of(i);
+            hipGraphExec_t &exec = pl->exec[k.index()];
+            if (exec) {
+                HIPCK(ctx, hipGraphLaunch(exec, s));
+                continue;
+            }
             const bool branches = ctx->graphs == 2 && pl->groups.size() > 1;
             if (branches) {
                 while (ctx->side.size() < pl->groups.size()) {
@@ -551,17 +581,17 @@ ENS_API ens_status ens_step(ens_ctx *ctx, const int32_t *members, int32_t count,
                 }
             }
             HIPCK(ctx, hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
-            hipError_t e = branches ? enqueue_step_branches(ctx, *pl) : enqueue_step(ctx, *pl, ctx->cap, nullptr);
+            hipError_t e = branches ? enqueue_step_branches(ctx, *pl, k) : enqueue_step(ctx, *pl, ctx->cap, nullptr, k);
             hipGraph_t g = nullptr;
             hipError_t e2 = hipStreamEndCapture(ctx->cap, &g);
             HIPCK(ctx, e);
             HIPCK(ctx, e2);
-            pl->graph = g;
-            HIPCK(ctx, hipGraphInstantiate(&pl->exec, g, nullptr, nullptr, 0));
+            pl->graph[k.index()] = g;
+            HIPCK(ctx, hipGraphInstantiate(&exec, g, nullptr, nullptr, 0));
+            HIPCK(ctx, hipGraphLaunch(exec, s));
         }
-        for (int i = 0; i < nsteps; i++) HIPCK(ctx, hipGraphLaunch(pl->exec, s));
     } else {
-        for (int i = 0; i < nsteps; i++) HIPCK(ctx, enqueue_step(ctx, *pl, s, nullptr));
+        for (int i = 0; i < nsteps; i++) HIPCK(ctx, enqueue_step(ctx, *pl, s, nullptr, kind_of(i)));
     }
     for (int id : ids) ctx->members[id]->last = s;
     return ENS_OK;
@@ -577,7 +607,7 @@ ENS_API ens_status ens_profile_step(ens_ctx *ctx, const int32_t *members, int32_
     if (ens_status st = make_plan(ctx, ids, &pl)) return st;
     hipStream_t s = (hipStream_t)stream;
     Prof prof;
-    hipError_t e = enqueue_step(ctx, *pl, s, &prof);
+    hipError_t e = enqueue_step(ctx, *pl, s, &prof, kLoneStep);
     hipError_t e2 = hipStreamSynchronize(s);
     for (int p = 0; p < ENS_NPASS; p++) ms_out[p] = 0.0;
     for (size_t i = 0; i < prof.pass.size(); i++) {
@@ -937,12 +967,7 @@ void read_cache(const char *path, std::map<std::string, int> &out) {
 }
 
 void drop_graphs(ens_ctx *ctx) {
-    for (auto &kv : ctx->plans) {
-        if (kv.second->exec) (void)hipGraphExecDestroy(kv.second->exec);
-        if (kv.second->graph) (void)hipGraphDestroy(kv.second->graph);
-        kv.second->exec = nullptr;
-        kv.second->graph = nullptr;
-    }
+    for (auto &kv : ctx->plans) free_graphs(*kv.second);
 }
 
 }  // namespace

@@ -129,7 +129,9 @@ enum Pass { P_BAND = 0, P_ZINV = 1, P_YINV = 2, P_XPASS = 3, P_YFWD = 4, P_ZFWD 
 // `variant` selects a compiled kernel variant (0: 8 values per thread,
 // 1: 16 values per thread; y/z passes 2, 3: the same with twice the lines
 // per workgroup; x pass 2 to 6: the streamed and wave-private passes, see
-// ens_autotune in ens.h) for passes with pass_variants(pass) > 1.
+// ens_autotune in ens.h; z forward 1: fused with the next stage's z inverse,
+// 2 (not selectable by callers): the last stage too, for a step followed by
+// another in the same call) for passes with pass_variants(pass) > 1.
 hipError_t launch_pass(int pass, int variant, int n, int prec, const MemberDev *mem, int count, int stage,
                        const void *tw, hipStream_t s);
 int pass_variants(int pass);

@@ -1138,16 +1138,16 @@ __global__ void __launch_bounds__((Cfg<P, N, EV, TM>::NT)) k_yfwd(const MemberDe
 // Forward along z, keep |m_z| <= K, normalise by N^-3, project, add band
 // forcing, RK stage update.
 // The RK stage is a template parameter: no run-time branches on it.
-// FUSE (stages 0 and 1): the kernel also performs the next stage's z inverse
-// (k_zinv's five outputs in bufA) from the updated velocity it holds in
-// registers, so that the next stage does not read the velocity back.  That
-// velocity is the one before the next stage's band step makes the band's part
-// of the m_x = 0 plane Hermitian; the part it removes is invisible to the x
-// pass, which takes only the real part at m_x = 0.
+// FUSE: the kernel also performs the next stage's z inverse (k_zinv's five
+// outputs in bufA) from the updated velocity it holds in registers, so that
+// the next stage does not read the velocity back; in the last stage, the z
+// inverse of the next step's first stage.  That velocity is the one before
+// the next stage's band step makes the band's part of the m_x = 0 plane
+// Hermitian; the part it removes is invisible to the x pass, which takes
+// only the real part at m_x = 0.
 template <typename P, int N, int stage, bool FUSE = false>
 __global__ void __launch_bounds__((Cfg<P, N, 8>::NTZ), (Cfg<P, N, 8>::ZMINB)) k_zfwd_update(const MemberDev *__restrict__ mems, const Cx<P> *__restrict__ twg) {
     using C = Cfg<P, N, 8>;
-    static_assert(!FUSE || stage < 2, "the last stage's velocity goes to the next step's own z inverse");
     constexpr int E = C::EZ, M = C::MZ, T = C::TZ, K = C::K, KX = C::KX, NYL = C::NYL, S = C::S;
     constexpr int ZB = C::ZB, BL = C::BL;
     constexpr int NT = C::NTZ;
@@ -1479,12 +1479,15 @@ static hipError_t run_pass(int pass, int variant, const MemberDev *mem, int coun
         return variant == 1 ? run_pencil<P, N, 16>(pass, mem, count, stage, twp, s)
                             : run_pencil<P, N, 8>(pass, mem, count, stage, twp, s);
     case P_ZFWD: {
-        // variant 1: stages 0 and 1 also perform the next stage's z inverse
+        // variant 1: stages 0 and 1 also perform the next stage's z inverse;
+        // variant 2 (internal, a step followed by another in the same call):
+        // the last stage too, for the next step's first stage
         const dim3 grid((C::NZLS + C::TZ - 1) / C::TZ, count);
-        if (stage == 0 && variant == 1) k_zfwd_update<P, N, 0, true><<<grid, C::NTZ, 0, s>>>(mem, twp);
+        if (stage == 0 && variant >= 1) k_zfwd_update<P, N, 0, true><<<grid, C::NTZ, 0, s>>>(mem, twp);
         else if (stage == 0) k_zfwd_update<P, N, 0><<<grid, C::NTZ, 0, s>>>(mem, twp);
-        else if (stage == 1 && variant == 1) k_zfwd_update<P, N, 1, true><<<grid, C::NTZ, 0, s>>>(mem, twp);
+        else if (stage == 1 && variant >= 1) k_zfwd_update<P, N, 1, true><<<grid, C::NTZ, 0, s>>>(mem, twp);
         else if (stage == 1) k_zfwd_update<P, N, 1><<<grid, C::NTZ, 0, s>>>(mem, twp);
+        else if (variant == 2) k_zfwd_update<P, N, 2, true><<<grid, C::NTZ, 0, s>>>(mem, twp);
         else k_zfwd_update<P, N, 2><<<grid, C::NTZ, 0, s>>>(mem, twp);
         break;
     }
@@ -1526,6 +1529,7 @@ hipError_t launch_pass(int pass, int variant, int n, int prec, const MemberDev *
 int pass_variants(int pass) {
     if (pass == P_XPASS) return 7;
     if (pass == P_ZFWD) return 2;                               // 1: fused with the next stage's z inverse
+                                                                // (2, internal: the last stage too)
     return (pass == P_ZINV || pass == P_YINV || pass == P_YFWD) ? 4 : 1;
 }
 

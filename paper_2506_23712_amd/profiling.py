@@ -65,14 +65,14 @@ def pass_bytes(n: int, prec: str) -> dict:
 def zfwd_stage_bytes(n: int, prec: str, stage: int, fused: bool = False) -> tuple:
     """(read, write) algorithmic bytes of the z forward + update of one RK
     stage for one member: the 3 z-line fields and u_hat read, u_hat written;
-    the RK register read in stages 1 and 2 and written in stages 0 and 1; the
-    fused variant (stages 0 and 1) also writes the next stage's 5 z-inverse
-    fields."""
+    the RK register read in stages 1 and 2 and written in stages 0 and 1; a
+    fused kernel (stages 0 and 1, and stage 2 of a step followed by another
+    in the same call) also writes the next stage's 5 z-inverse fields."""
     K = n // 3
     cs = 16 if prec == "fp64" else 8
     S, zl = (2 * K + 1) ** 2 * (K + 1), n * (2 * K + 1) * (K + 1)
     r = 3 * zl + 3 * S + (3 * S if stage > 0 else 0)
-    w = 3 * S + (3 * S if stage < 2 else 0) + (5 * zl if fused and stage < 2 else 0)
+    w = 3 * S + (3 * S if stage < 2 else 0) + (5 * zl if fused else 0)
     return r * cs, w * cs
 
 
@@ -215,7 +215,7 @@ def write_summary(n: int, counts, out: str, trace: str | None = None, workloads=
                   "counter per run), KiB per dispatch, scaled by what the same counter reads for a plain 1 GiB device "
                   "copy.  Algorithmic bytes: each pass's inputs read once and outputs written once, truncated storage "
                   "(a `zfwd_update` kernel of one RK stage: stage 0 does not read the RK register, stage 2 does not "
-                  "write it, and a fused kernel (`true` in its name, stages 0 and 1) also writes the next stage's "
+                  "write it, and a fused kernel (`true` in its name) also writes the next stage's "
                   "5 z-inverse fields; the stage-averaged figure where the stage is not in the name).  The pencil buffers hold no row "
                   "padding; what the measured bytes add comes from loads that straddle 128-byte lines (the y inverse "
                   "and the z forward read rows of K + 1 values that start anywhere in a line) and from the z planes' "
