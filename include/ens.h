@@ -221,7 +221,8 @@ ens_status ens_autotune(ens_ctx *ctx, const int32_t *members, int32_t count, voi
  * state): 0 = the z inverse of every RK stage is a launch of its own; 1 = the
  * z forward of the first two stages also performs the next stage's z inverse
  * from the velocity it has just updated, so each step reads the velocity back
- * once instead of three times (default for n <= 512). */
+ * once instead of three times, and inside one ens_step call of several steps
+ * the last stage does the same for the next step (default for n <= 512). */
 ens_status ens_set_variant(ens_ctx *ctx, int32_t pass, int32_t n, int32_t precision, int32_t variant);
 ens_status ens_get_variant(const ens_ctx *ctx, int32_t pass, int32_t n, int32_t precision, int32_t *variant);
 
